@@ -1,0 +1,223 @@
+/*
+ * krr.h -- C ABI of the MI355X (gfx950) solver for regularised Gaussian kernel
+ * systems (K_hat + gamma I) w = y, after Srinivasan, Hu, Gumerov, Murtugudde,
+ * Duraiswami, "Preconditioned Krylov solvers for kernel regression".
+ *
+ * Problem statement (section 1, section 2): points X = {x_1..x_N} in R^d, the
+ * Gaussian kernel k(x_i, x_j) = exp(-||x_i - x_j||^2 / (2 sigma^2))
+ * (eq. Gaussian), the kernel matrix K_hat_ij = k(x_i, x_j) including the
+ * diagonal (eq. kernelMatrix), and the regularised matrix K = K_hat + gamma I
+ * (eq. RegKernel).  The solver is flexible GMRES (Algorithm 1, section 4.2),
+ * right-preconditioned by M = K_hat + delta I (section 5) whose systems are
+ * solved approximately by a truncated inner CG (sections 4.3, 5.2) with a
+ * low-precision kernel product; the outer product is double precision
+ * (section 5.1).  K_hat is never stored: every product is an on-the-fly
+ * weighted kernel sum (section 1; section 3.1).
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers unless the comment says (host).  The caller
+ *    owns every buffer, including the workspace `ws` of `ws_bytes` bytes; the
+ *    library never allocates or frees device memory.  Required workspace sizes
+ *    come from krr_workspace_size().
+ *  - Points are n x d row-major FP64 (x[i*d + t]), read only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the default stream).
+ *    The product and gradient calls are asynchronous.  The solvers read small
+ *    status words back from the device (one per outer step, or per group of CG
+ *    iterations) and therefore synchronise `stream`.
+ *  - Return values: KRR_OK (0); positive values mean the call completed with
+ *    a result but not the requested one (KRR_NOT_CONVERGED: the best iterate is
+ *    in the output; KRR_BREAKDOWN: a non-positive curvature or non-finite value
+ *    stopped a CG); negative values are errors.  Argument errors are detected on
+ *    the host before anything is enqueued, and outputs are then untouched.
+ *  - Non-finite inputs (NaN/Inf in points, right-hand sides or vectors) are
+ *    reported as KRR_ENONFINITE by the solvers (detected on the device during
+ *    set-up, before the iteration starts).
+ *  - Calls that share a workspace must not overlap; different workspaces may
+ *    be used concurrently on different streams.
+ */
+#ifndef KRR_H
+#define KRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;
+typedef struct ihipStream_t *krr_stream_t; /* same type as hipStream_t */
+
+/* Arithmetic of a kernel product.  KRR_BF16 stores point offsets and the input
+ * vector in bfloat16 (round to nearest even) and accumulates in FP32; its
+ * vectors are FP32 in memory. */
+typedef enum { KRR_FP64 = 0, KRR_FP32 = 1, KRR_BF16 = 2 } krr_prec;
+
+typedef enum {
+    KRR_OK = 0,
+    KRR_NOT_CONVERGED = 1,
+    KRR_BREAKDOWN = 2,
+    KRR_EINVAL = -1,      /* bad argument (sizes, sigma <= 0, gamma < 0, NULL, ...) */
+    KRR_ENONFINITE = -2,  /* NaN or Inf in an input */
+    KRR_EWORKSPACE = -3,  /* ws NULL or ws_bytes below krr_workspace_size() */
+    KRR_EHIP = -4,        /* a HIP runtime call failed */
+    KRR_EUNSUPPORTED = -5 /* valid but not implemented (e.g. d above KRR_MAX_DIM) */
+} krr_status;
+
+#define KRR_MAX_DIM 64
+
+/* One point set: n points of dimension d, n x d row-major FP64, device. */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    const double *x;
+} krr_points;
+
+/* Inner preconditioner of the flexible solver. */
+typedef enum {
+    KRR_INNER_CG = 0,   /* truncated CG on M = K_hat + delta I (section 5) */
+    KRR_INNER_NONE = 1  /* z_j = v_j: M = I, i.e. plain restarted GMRES */
+} krr_inner;
+
+/* Orthogonalisation of the Arnoldi vectors: modified Gram-Schmidt as printed
+ * in Algorithm 1, or classical Gram-Schmidt applied twice. */
+typedef enum { KRR_GS_MGS = 0, KRR_GS_CGS2 = 1 } krr_gs;
+
+/* Options of the flexible solver.  krr_default_opts() fills the paper's rules
+ * (section 6): outer tolerance 1e-6, inner tolerance ten times the outer
+ * tolerance, delta ten times gamma (1e-3 when gamma = 0).  Fields with a
+ * negative value take those defaults at call time. */
+typedef struct {
+    int32_t restart_m;   /* Krylov vectors per cycle ("iter" of Algorithm 1); default 30 */
+    int32_t max_outer;   /* cap on outer steps over all cycles; default 1000 */
+    double tol;          /* stop when ||y - K w|| / ||y|| <= tol (true FP64 residual) */
+    int32_t inner;       /* krr_inner */
+    int32_t inner_prec;  /* krr_prec of the inner products; default KRR_FP32 */
+    double delta;        /* M = K_hat + delta I; < 0: 10 gamma, or 1e-3 if gamma == 0 */
+    int32_t inner_maxit; /* inner CG iterations cap (>= 1); default 10 */
+    double inner_tol;    /* inner stop at ||r|| / ||v|| <= inner_tol; < 0: 10 tol; 0: run to the cap */
+    int32_t gs;          /* krr_gs; default KRR_GS_MGS */
+    int32_t cg_check;    /* plain CG: iterations between host checks of the stop flag; default 16 */
+} krr_fgmres_opts;
+
+/* Per-solve report (host struct, caller-owned). */
+typedef struct {
+    int32_t status;        /* krr_status of this solve */
+    int32_t outer_iters;   /* outer steps over all cycles (CG: iterations) */
+    int32_t inner_iters;   /* inner CG iterations in total */
+    int32_t cycles;        /* restart cycles (CG: true-residual restarts + 1) */
+    int64_t mvp64, mvp32, mvp16; /* kernel products by precision */
+    double relres_true;    /* ||y - K w|| / ||y|| from an FP64 product at exit */
+    double relres_est;     /* the solver's own last estimate */
+    double t_total_ms;     /* host wall time of the call */
+} krr_info;
+
+/* Solver modes of krr_solve. */
+typedef enum {
+    KRR_MODE_FGMRES = 0, /* mixed precision flexible GMRES (the paper's method) */
+    KRR_MODE_CG64 = 1,   /* plain FP64 conjugate gradient (the paper's baseline) */
+    KRR_MODE_GMRES = 2   /* FGMRES with inner = KRR_INNER_NONE */
+} krr_mode;
+
+/* Which call a workspace is sized for (krr_workspace_size). */
+typedef enum {
+    KRR_WS_KMVP = 0,
+    KRR_WS_KMVP_MULTI = 1,
+    KRR_WS_KMVP_GRAD = 2,
+    KRR_WS_CG_INNER = 3,
+    KRR_WS_FGMRES = 4,
+    KRR_WS_SOLVE = 5,
+    KRR_WS_KMVP_CROSS = 6
+} krr_ws_call;
+
+void krr_default_opts(krr_fgmres_opts *opts /* host */);
+const char *krr_status_string(int status);
+
+/* Bytes of workspace needed by call `which` for the given problem(s).
+ * probs: host array of nprob point sets (only n and d are read); for
+ * KRR_WS_KMVP_CROSS probs[0] are the targets and probs[1] the sources.  nrhs is
+ * the number of right-hand sides (multi products, krr_solve).  opts may be NULL
+ * (defaults).  Returns 0 for invalid arguments. */
+size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob, int32_t nrhs,
+                          const krr_fgmres_opts *opts);
+
+/* y = K_hat q + shift q  (section 3.1: the weighted kernel summation, here with
+ * the regularisation shift of eq. RegKernel; shift = gamma gives K, shift =
+ * delta gives M).  prec KRR_FP64: q, y are double[n]; KRR_FP32 / KRR_BF16:
+ * float[n].  The product is computed on the fly; K_hat is never formed.  y may
+ * not alias q.  Errors: KRR_EINVAL (n < 1, d outside 1..KRR_MAX_DIM, sigma <= 0
+ * or not finite, shift not finite, NULL pointers), KRR_EWORKSPACE. */
+int kmvp_gauss(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
+               const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Y[:, r] = K_hat Q[:, r] + shift Q[:, r] for r < nrhs (several right-hand
+ * sides, the multi-RHS need of the posterior variance, section 2.1).  Q and Y are
+ * column-major with leading dimensions ldq, ldy >= n; element types as in
+ * kmvp_gauss.  The kernel tile is formed once per pair and applied to all
+ * columns on the matrix cores. */
+int kmvp_gauss_multi(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
+                     int32_t nrhs, const void *Q, int64_t ldq, void *Y, int64_t ldy,
+                     void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Rectangular product y = K_hat(targets, sources) q: y_i = sum_j k(t_i, s_j) q_j
+ * for i < targets->n (the prediction k(x*)^T w of eq. GPR_mean and eq. Kriging).
+ * Both point sets have the same d.  Element types as in kmvp_gauss. */
+int kmvp_gauss_cross(const krr_points *targets /* host */, const krr_points *sources /* host */,
+                     double sigma, int32_t prec, const void *q, void *y,
+                     void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Adjoint pass for the gradient of a loss l(w), w = K^{-1} y (hyperparameters
+ * by maximum likelihood, section 2.1).  Given lam = K^{-1} dl/dw and w, writes
+ * dl/dtheta = -lam^T (dK/dtheta) w:
+ *   gx[i*d + t]   = (1/sigma^2) sum_j (lam_i w_j + lam_j w_i) K_hat_ij (x_it - x_jt)
+ *   *g_logsigma   = -(1/sigma^2) sum_ij lam_i w_j K_hat_ij ||x_i - x_j||^2
+ *   *g_loggamma   = -gamma lam^T w
+ * gx is n x d row-major double (device); g_logsigma and g_loggamma are single
+ * doubles in device memory.  lam may equal w (the case l = y^T K^{-1} y).
+ * Products run in FP32 on the matrix cores; the reduction and epilogue in FP64. */
+int kmvp_grad(const krr_points *pts /* host */, double sigma, double gamma, const double *lam,
+              const double *w, double *gx, double *g_logsigma, double *g_loggamma,
+              void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Truncated CG for the preconditioner system (K_hat + shift I) z = v from z = 0
+ * (sections 4.3, 5.2): at most maxit iterations (>= 1), stopping early when the
+ * recursive residual satisfies ||r|| / ||v|| <= tol (tol = 0: always maxit).
+ * Vectors are double[n] for KRR_FP64, float[n] otherwise.  info (host, may be
+ * NULL) receives the iteration count; passing it synchronises the stream. */
+int cg_inner_solve(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
+                   const void *v, void *z, int32_t maxit, double tol, krr_info *info /* host */,
+                   void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Flexible GMRES (Algorithm 1) for (K_hat + gamma I) x = b, right-preconditioned
+ * by inner CG solves of M = K_hat + delta I in opts->inner_prec, outer product,
+ * Gram-Schmidt and Givens least squares in FP64.  b, x: double[n]; x holds the
+ * initial guess on entry (warm start; zero it for x0 = 0) and the solution on
+ * exit.  Convergence is declared on the true FP64 residual.  Returns KRR_OK,
+ * KRR_NOT_CONVERGED (max_outer reached; best iterate in x) or an error. */
+int fgmres_solve(const krr_points *pts /* host */, double sigma, double gamma, const double *b,
+                 double *x, const krr_fgmres_opts *opts /* host, may be NULL */,
+                 krr_info *info /* host, may be NULL */, void *ws, size_t ws_bytes,
+                 krr_stream_t stream);
+
+/* Solve nprob independent systems, each with nrhs right-hand sides:
+ * (K_hat_k + gamma_k I) W_k = Y_k.  probs, sigma, gamma, Y, W, ldy are host
+ * arrays of length nprob; Y[k] and W[k] are device pointers to column-major
+ * n_k x nrhs blocks with leading dimension ldy[k] >= n_k (ldy may be NULL:
+ * ld = n_k).  W[k] is overwritten (x0 = 0).  mode is a krr_mode.  infos (host,
+ * may be NULL) has nprob*nrhs entries, entry k*nrhs + r for column r of system k.
+ * With nprob == 1 and nrhs == 1 this is fgmres_solve / the plain CG.  Several
+ * systems or columns run together: their kernel products are batched into
+ * multi-column launches and every (system, column) pair stops on its own.
+ * Returns the worst status over all pairs. */
+int krr_solve(const krr_points *probs /* host */, int32_t nprob, const double *sigma /* host */,
+              const double *gamma /* host */, int32_t nrhs, const double *const *Y /* host array */,
+              const int64_t *ldy /* host, may be NULL */, double *const *W /* host array */,
+              int32_t mode, const krr_fgmres_opts *opts /* host, may be NULL */,
+              krr_info *infos /* host, may be NULL */, void *ws, size_t ws_bytes,
+              krr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRR_H */

@@ -1,0 +1,165 @@
+// Internal declarations of the gfx950 kernel-system solver library.
+//
+// Layout of a prepared point set (all device memory, carved from the caller's
+// workspace):
+//  * coordinates are pre-scaled by c = sqrt(log2 e) / (sigma sqrt 2), so the
+//    Gaussian of eq. (Gaussian) becomes k_ij = 2^(-||xs_i - xs_j||^2);
+//  * points are sorted along a Morton (Z-order) curve and grouped in tiles of
+//    TILE consecutive points; each tile J has an FP64 anchor a_J (centre of its
+//    bounding box) and every point stores its offset o_j = xs_j - a_J in the
+//    working precision (FP64, FP32 or bfloat16), structure-of-arrays;
+//  * per tile: R2_J = max_j ||o_j||^2 and a normaliser N_J = floor(R2_J / 2);
+//    per point and precision: w_j = 2^(N_J - ||o_j||^2) (o_j as rounded in that
+//    precision), 0 for padding points.
+// With t = x_i - a_J the exponent splits as
+//   -||t - o_j||^2 = (2 t . o_j - ||t||^2 - N_J) + (N_J - ||o_j||^2),
+// so the inner loop of a product evaluates 2^(c_i + sum_k T_ik o_jk) * (w_j q_j)
+// with per-row constants T = 2t, c = -||t||^2 - N_J: d fused multiply-adds, one
+// exp2 and one accumulate per pair.  Tiles whose radius exceeds the precision's
+// limit use the direct form 2^(-||t - o_j||^2) instead.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/krr.h"
+
+namespace krr {
+
+constexpr int TILE = 256;       // points per anchor tile; also rows per product block
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int VEC_BLOCKS = 512; // blocks of the vector (reduction) kernels
+
+// Above these squared tile radii (scaled units) a tile uses the direct form.
+constexpr double WIDE_R2_FP32 = 64.0;
+constexpr double WIDE_R2_FP64 = 512.0;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Device counters and scratch for the last-block reductions of one solver.
+struct RedScratch {
+    unsigned *counters;  // NCOUNTERS
+    double *partials;    // VEC_BLOCKS * NPARTIAL_SLOTS doubles (also used as float)
+    static constexpr int NCOUNTERS = 16;
+    static constexpr int NPARTIAL_SLOTS = 4;
+};
+
+struct Prepared {
+    int64_t n = 0, n_pad = 0;
+    int d = 0, dpad = 0;      // dpad: dimension of the kernel instance (>= d, extra coords 0)
+    int ntiles = 0;
+    double scale = 0.0;
+    int32_t *perm = nullptr;  // n_pad: sorted position -> original index, -1 for padding
+    double *anchor = nullptr; // ntiles * dpad
+    double *tile_r2 = nullptr;
+    double *tile_nj = nullptr;
+    double *off64 = nullptr;  // dpad * n_pad
+    float *off32 = nullptr;
+    uint16_t *off16 = nullptr;
+    double *w64 = nullptr;    // n_pad
+    float *w32 = nullptr;
+    float *w16 = nullptr;
+    double *sq64 = nullptr;   // n_pad: ||o_j||^2 (FP64 offsets)
+    int *flags = nullptr;     // [0]: non-finite input seen
+};
+
+// Sizes of a prepared set.
+int dim_instance(int d);  // smallest compiled kernel dimension >= d, 0 if none
+size_t prepared_bytes(int64_t n, int d);
+size_t prep_temp_bytes(int64_t n);
+// Carve a Prepared from the workspace (pointers only).
+Prepared carve_prepared(Carver &cv, int64_t n, int d);
+
+// Build the prepared layout from FP64 row-major points; temp is scratch of
+// prep_temp_bytes(n).  Returns a HIP error code.
+hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp, size_t temp_bytes,
+                          hipStream_t s);
+
+// Gather an original-order vector into sorted order (padding 0), and back.
+template <typename Tin, typename Tout>
+hipError_t gather_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t scatter_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStream_t s);
+
+// Kernel products on sorted, zero-padded vectors of length n_pad.
+// prec: KRR_FP64 (q, y double), KRR_FP32 (float), KRR_BF16 (q16: bf16 bits, y float).
+struct KmvpPlan {
+    int splits = 1;          // column splits
+    int tiles_per_split = 0;
+};
+KmvpPlan kmvp_plan(const Prepared &P, int prec);
+size_t kmvp_parts_bytes(const Prepared &P, int prec);  // bytes of partial sums for the plan
+// y = K_hat q + shift q on sorted vectors. parts: scratch of kmvp_parts_bytes.
+// active: optional device flag; when it reads 0 the kernels return at once.
+hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, void *parts,
+                       const int *active, hipStream_t s);
+
+// Device-resident scalars of one CG solve (T = float for the inner
+// preconditioner solve, double for the plain solver).
+template <typename T>
+struct CgScalars {
+    T rr;       // r . r
+    T rr0;      // ||rhs||^2 at start
+    T thresh;   // stop when rr <= thresh (tol^2 rr0)
+    T alpha, beta, pAp;
+    int active;     // 1 while iterating
+    int iters;      // iterations done
+    int maxit;
+    int status;     // 0 ok, KRR_BREAKDOWN
+    int candidate;  // plain solver: recursive residual reached the tolerance
+    int pad_[3];
+};
+
+// Device-resident state of one FGMRES solve (FP64), m = restart length.
+struct FgmresScalars {
+    double bnorm;   // ||b||
+    double beta;    // ||r0|| of the current cycle
+    double est;     // |g_{j+1}| / ||b||
+    double wnorm0;  // ||K z_j|| before orthogonalisation
+    int breakdown;  // h_{j+1,j} negligible: happy breakdown
+    int nonfinite;
+    int pad_[2];
+};
+
+// bf16 conversion of a float vector (round to nearest even).
+hipError_t to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s);
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    uint32_t u = static_cast<uint32_t>(h) << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+#define KRR_HIP(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return e_;                \
+    } while (0)
+
+}  // namespace krr

@@ -1,0 +1,285 @@
+// Point preparation for the kernel products: scaling, Morton ordering, tile
+// anchors and per-precision offsets and weights (layout described in
+// krr_internal.h).  Runs once per solve; O(N log N) and negligible next to the
+// O(N^2) products.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <cmath>
+
+#include "krr_internal.h"
+
+namespace krr {
+
+static const int kDims[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+
+int dim_instance(int d) {
+    for (int v : kDims)
+        if (v >= d) return v;
+    return 0;
+}
+
+Prepared carve_prepared(Carver &cv, int64_t n, int d) {
+    Prepared P;
+    P.n = n;
+    P.d = d;
+    P.dpad = dim_instance(d);
+    P.n_pad = (n + TILE - 1) / TILE * TILE;
+    P.ntiles = static_cast<int>(P.n_pad / TILE);
+    P.perm = cv.take<int32_t>(P.n_pad);
+    P.anchor = cv.take<double>(static_cast<size_t>(P.ntiles) * P.dpad);
+    P.tile_r2 = cv.take<double>(P.ntiles);
+    P.tile_nj = cv.take<double>(P.ntiles);
+    P.off64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
+    P.off32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
+    P.off16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
+    P.w64 = cv.take<double>(P.n_pad);
+    P.w32 = cv.take<float>(P.n_pad);
+    P.w16 = cv.take<float>(P.n_pad);
+    P.sq64 = cv.take<double>(P.n_pad);
+    P.flags = cv.take<int>(4);
+    return P;
+}
+
+size_t prepared_bytes(int64_t n, int d) {
+    Carver cv(nullptr);
+    carve_prepared(cv, n, d);
+    return cv.off + 256;
+}
+
+// keys (2 buffers) + values (2 buffers) + bbox + sort scratch bound
+static size_t sort_scratch_bound(int64_t n) { return (size_t(16) << 20) + static_cast<size_t>(n) * 16; }
+
+size_t prep_temp_bytes(int64_t n) {
+    Carver cv(nullptr);
+    cv.take<uint64_t>(n);
+    cv.take<uint64_t>(n);
+    cv.take<int32_t>(n);
+    cv.take<int32_t>(n);
+    cv.take<double>(2 * KRR_MAX_DIM * 1024);
+    cv.take<double>(2 * KRR_MAX_DIM);
+    cv.take<char>(sort_scratch_bound(n));
+    return cv.off + 256;
+}
+
+// ---------------------------------------------------------------- reductions
+
+template <typename T, class Op>
+__device__ T block_reduce(T v, Op op, T *lds /* >= BLOCK/WAVE */) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off /= 2) v = op(v, __shfl_xor(v, off, WAVE));
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x % WAVE) == 0) lds[w] = v;
+    __syncthreads();
+    T r = lds[0];
+    for (int k = 1; k < static_cast<int>(blockDim.x) / WAVE; ++k) r = op(r, lds[k]);
+    __syncthreads();
+    return r;
+}
+
+struct MinOp { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct MaxOp { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+
+// ---------------------------------------------------------------- kernels
+
+// Per-block min / max of the scaled coordinate t over a slice of points
+// (grid: nblk x d); part[(t * 2 + 0|1) * nblk + blk].  Flags non-finite input.
+__global__ __launch_bounds__(BLOCK) void k_bbox_partial(const double *__restrict__ x, int64_t n, int d,
+                                                        double scale, double *part, int *flags) {
+    __shared__ double lds[BLOCK / WAVE];
+    const int t = blockIdx.y;
+    const int nblk = gridDim.x;
+    double lo = INFINITY, hi = -INFINITY;
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) {
+        double v = x[i * d + t];
+        if (!isfinite(v)) bad = 1;
+        v *= scale;
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    if (bad) atomicOr(flags, 1);
+    lo = block_reduce(lo, MinOp(), lds);
+    hi = block_reduce(hi, MaxOp(), lds);
+    if (threadIdx.x == 0) {
+        part[(t * 2 + 0) * nblk + blockIdx.x] = lo;
+        part[(t * 2 + 1) * nblk + blockIdx.x] = hi;
+    }
+}
+
+__global__ void k_bbox_final(const double *part, int nblk, int d, double *bbox) {
+    const int t = threadIdx.x;
+    if (t >= d) return;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int b = 0; b < nblk; ++b) {
+        lo = fmin(lo, part[(t * 2 + 0) * nblk + b]);
+        hi = fmax(hi, part[(t * 2 + 1) * nblk + b]);
+    }
+    bbox[2 * t] = lo;
+    bbox[2 * t + 1] = hi;
+}
+
+// Morton code: the first dm = min(d, 63) scaled coordinates quantised to
+// bits = min(63 / dm, 31) bits each over the bounding box, bits interleaved.
+__global__ __launch_bounds__(BLOCK) void k_morton(const double *__restrict__ x, int64_t n, int d, double scale,
+                                                  const double *__restrict__ bbox, int dm, int bits,
+                                                  uint64_t *keys, int32_t *vals) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double qmax = static_cast<double>((uint64_t(1) << bits) - 1);
+    uint64_t code = 0;
+    for (int t = 0; t < dm; ++t) {
+        const double lo = bbox[2 * t], hi = bbox[2 * t + 1];
+        const double ext = hi - lo;
+        double f = ext > 0 ? (x[i * d + t] * scale - lo) / ext : 0.0;
+        f = fmin(fmax(f, 0.0), 1.0);
+        const uint64_t qt = static_cast<uint64_t>(f * qmax);
+        for (int b = 0; b < bits; ++b) code |= ((qt >> b) & 1u) << (b * dm + t);
+    }
+    keys[i] = code;
+    vals[i] = static_cast<int32_t>(i);
+}
+
+// One block per tile: anchor, offsets, radius, normaliser and weights.
+__global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, int64_t n, int d, int dpad,
+                                                double scale, const int32_t *__restrict__ sorted_idx,
+                                                Prepared P) {
+    __shared__ double lds[TILE / WAVE];
+    const int J = blockIdx.x;
+    const int64_t j = static_cast<int64_t>(J) * TILE + threadIdx.x;
+    const bool real = j < n;
+    const int32_t idx = real ? sorted_idx[j] : -1;
+    P.perm[j] = idx;
+    double sq64 = 0.0, sq32 = 0.0, sq16 = 0.0;
+    for (int t = 0; t < dpad; ++t) {
+        const double v = (real && t < d) ? x[static_cast<int64_t>(idx) * d + t] * scale : 0.0;
+        const double lo = block_reduce(real ? v : INFINITY, MinOp(), lds);
+        const double hi = block_reduce(real ? v : -INFINITY, MaxOp(), lds);
+        const double a = (t < d) ? 0.5 * (lo + hi) : 0.0;
+        const double o = real ? v - a : 0.0;
+        const float o32 = static_cast<float>(o);
+        const uint16_t o16 = f32_to_bf16_rne(o32);
+        const double o16d = static_cast<double>(bf16_to_f32(o16));
+        if (threadIdx.x == 0) P.anchor[static_cast<size_t>(J) * dpad + t] = a;
+        P.off64[t * P.n_pad + j] = o;
+        P.off32[t * P.n_pad + j] = o32;
+        P.off16[t * P.n_pad + j] = o16;
+        sq64 += o * o;
+        sq32 += static_cast<double>(o32) * static_cast<double>(o32);
+        sq16 += o16d * o16d;
+    }
+    const double r2 = block_reduce(fmax(sq64, fmax(sq32, sq16)), MaxOp(), lds);
+    const double nj = floor(0.5 * r2);
+    if (threadIdx.x == 0) {
+        P.tile_r2[J] = r2;
+        P.tile_nj[J] = nj;
+    }
+    P.sq64[j] = sq64;
+    P.w64[j] = (real && r2 <= WIDE_R2_FP64) ? exp2(nj - sq64) : 0.0;
+    P.w32[j] = (real && r2 <= WIDE_R2_FP32) ? static_cast<float>(exp2(nj - sq32)) : 0.0f;
+    P.w16[j] = (real && r2 <= WIDE_R2_FP32) ? static_cast<float>(exp2(nj - sq16)) : 0.0f;
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp, size_t temp_bytes,
+                          hipStream_t s) {
+    const int64_t n = P.n;
+    const int d = P.d;
+    P.scale = std::sqrt(std::log2(std::exp(1.0))) / (sigma * std::sqrt(2.0));
+    Carver cv(temp);
+    uint64_t *k0 = cv.take<uint64_t>(n);
+    uint64_t *k1 = cv.take<uint64_t>(n);
+    int32_t *v0 = cv.take<int32_t>(n);
+    int32_t *v1 = cv.take<int32_t>(n);
+    double *part = cv.take<double>(2 * KRR_MAX_DIM * 1024);
+    double *bbox = cv.take<double>(2 * KRR_MAX_DIM);
+    const size_t sort_cap = sort_scratch_bound(n);
+    char *sort_tmp = cv.take<char>(sort_cap);
+    if (cv.off > temp_bytes) return hipErrorInvalidValue;
+
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, P.flags, 4, 0);
+    const int nblk = static_cast<int>(std::min<int64_t>(1024, (n + BLOCK - 1) / BLOCK));
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nblk, d), dim3(BLOCK), 0, s, x, n, d, P.scale, part, P.flags);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(KRR_MAX_DIM), 0, s, part, nblk, d, bbox);
+    const int dm = d < 63 ? d : 63;
+    const int bits = (63 / dm) < 31 ? 63 / dm : 31;
+    hipLaunchKernelGGL(k_morton, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, x, n, d, P.scale, bbox, dm,
+                       bits, k0, v0);
+    KRR_HIP(hipGetLastError());
+    rocprim::double_buffer<uint64_t> keys(k0, k1);
+    rocprim::double_buffer<int32_t> vals(v0, v1);
+    size_t need = 0;
+    KRR_HIP(rocprim::radix_sort_pairs(nullptr, need, keys, vals, static_cast<size_t>(n), 0u,
+                                      static_cast<unsigned>(dm * bits), s));
+    if (need > sort_cap) return hipErrorInvalidValue;
+    KRR_HIP(rocprim::radix_sort_pairs(sort_tmp, need, keys, vals, static_cast<size_t>(n), 0u,
+                                      static_cast<unsigned>(dm * bits), s));
+    hipLaunchKernelGGL(k_tiles, dim3(P.ntiles), dim3(TILE), 0, s, x, n, d, P.dpad, P.scale,
+                       static_cast<const int32_t *>(vals.current()), P);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- gather / scatter
+
+template <typename T>
+__device__ inline T cvt(double v);
+template <>
+__device__ inline double cvt<double>(double v) { return v; }
+template <>
+__device__ inline float cvt<float>(double v) { return static_cast<float>(v); }
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(BLOCK) void k_gather(const int32_t *__restrict__ perm, int64_t n_pad,
+                                                  const Tin *__restrict__ src, Tout *__restrict__ dst) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n_pad) return;
+    const int32_t p = perm[i];
+    dst[i] = p >= 0 ? static_cast<Tout>(src[p]) : Tout(0);
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ perm, int64_t n_pad,
+                                                   const Tin *__restrict__ src, Tout *__restrict__ dst) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i >= n_pad) return;
+    const int32_t p = perm[i];
+    if (p >= 0) dst[p] = static_cast<Tout>(src[i]);
+}
+
+template <typename Tin, typename Tout>
+hipError_t gather_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_gather<Tin, Tout>), dim3((P.n_pad + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.perm,
+                       P.n_pad, src, dst);
+    return hipGetLastError();
+}
+template <typename Tin, typename Tout>
+hipError_t scatter_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_scatter<Tin, Tout>), dim3((P.n_pad + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.perm,
+                       P.n_pad, src, dst);
+    return hipGetLastError();
+}
+
+template hipError_t gather_sorted<double, double>(const Prepared &, const double *, double *, hipStream_t);
+template hipError_t gather_sorted<float, float>(const Prepared &, const float *, float *, hipStream_t);
+template hipError_t gather_sorted<double, float>(const Prepared &, const double *, float *, hipStream_t);
+template hipError_t scatter_sorted<double, double>(const Prepared &, const double *, double *, hipStream_t);
+template hipError_t scatter_sorted<float, float>(const Prepared &, const float *, float *, hipStream_t);
+template hipError_t scatter_sorted<float, double>(const Prepared &, const float *, double *, hipStream_t);
+template hipError_t gather_sorted<float, double>(const Prepared &, const float *, double *, hipStream_t);
+template hipError_t scatter_sorted<double, float>(const Prepared &, const double *, float *, hipStream_t);
+
+__global__ __launch_bounds__(BLOCK) void k_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ dst,
+                                                   int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    if (i < n) dst[i] = f32_to_bf16_rne(src[i]);
+}
+
+hipError_t to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace krr

@@ -1,0 +1,59 @@
+// Solver drivers on prepared (sorted, zero-padded) point sets.
+#pragma once
+
+#include "krylov.h"
+
+namespace krr {
+
+// Status words read back by the host (one copy per outer step).
+struct StatusBlock {
+    FgmresScalars F;
+    CgScalars<float> c32;
+    CgScalars<double> c64;
+};
+
+// Resolved options (defaults applied).
+struct SolverOpts {
+    int restart_m = 30;
+    int max_outer = 1000;
+    double tol = 1e-6;
+    int inner = KRR_INNER_CG;
+    int inner_prec = KRR_FP32;
+    double delta = 0.0;
+    int inner_maxit = 10;
+    double inner_tol = 1e-5;
+    int gs = KRR_GS_MGS;
+    int cg_check = 16;
+};
+
+// Buffers of one solve, carved from the workspace.  b and x are the right-hand
+// side and the solution in sorted order.
+struct SolverWork {
+    double *b = nullptr, *x = nullptr, *w = nullptr;
+    double *Ap64 = nullptr, *r64 = nullptr, *p64 = nullptr, *z64 = nullptr;
+    double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+    double *hcol = nullptr, *hscr = nullptr;
+    float *z32 = nullptr, *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr;
+    uint16_t *p16 = nullptr;
+    char *parts = nullptr;
+    StatusBlock *status = nullptr;
+    Red R;
+};
+
+SolverWork carve_solver(Carver &cv, const Prepared &P, const SolverOpts &o, bool fgmres);
+
+// Map a HIP error to KRR_EHIP inside functions returning a krr_status.
+#define KRR_HIP_STATUS(expr)                            \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return KRR_EHIP;          \
+    } while (0)
+
+int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpts &o, const SolverWork &W,
+                  krr_info *info, hipStream_t s);
+int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,
+                hipStream_t s);
+int cg_inner_sorted(const Prepared &P, int prec, double shift, const double *v_s, double *z_s, int maxit,
+                    double tol, const SolverWork &W, krr_info *info, hipStream_t s);
+
+}  // namespace krr

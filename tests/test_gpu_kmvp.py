@@ -1,0 +1,118 @@
+"""Parity of the HIP kernel products with the FP64 oracle (GPU).
+
+Tolerances (norm-wise ||y_gpu - y_oracle|| / ||y_oracle||, q ~ N(0, 1)):
+FP64 1e-12, FP32 1e-5, BF16-input 1e-2.  The oracle evaluates the kernel on the
+original FP64 points, so input rounding counts against the low precisions.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_1237_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}
+DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
+
+
+def _api():
+    from paper_1408_1237_amd import api
+    return api
+
+
+def _gpu_mvp(x, sigma, q, shift, prec):
+    api = _api()
+    xt = torch.from_numpy(x).cuda()
+    qt = torch.from_numpy(q).to(DT[prec]).cuda()
+    y = api.kmvp_gauss(xt, sigma, qt, shift=shift, prec=prec)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 255, 256, 257, 1000, 2000])
+def test_kmvp_sizes(prec, n):
+    x = workloads.random_points(100 + n, n, 3, 2.0)
+    q = workloads.random_vector(200 + n, n)
+    y = _gpu_mvp(x, 0.6, q, 0.01, prec)
+    want = oracle.mvp(x, 0.6, q, shift=0.01)
+    assert _relerr(y, want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 4, 5, 8, 12, 16, 17, 33, 64])
+def test_kmvp_dims(prec, d):
+    n = 700
+    x = workloads.random_points(300 + d, n, d, 1.0, kind="normal")
+    sigma = 0.5 * np.sqrt(d)
+    q = workloads.random_vector(400 + d, n)
+    y = _gpu_mvp(x, sigma, q, 0.1, prec)
+    want = oracle.mvp(x, sigma, q, shift=0.1)
+    assert _relerr(y, want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_kmvp_coincident_points(prec):
+    # K_hat = 1 1^T: y_i = sum(q) + s q_i
+    n = 300
+    x = np.tile(np.array([[3.0, -2.0, 7.5]]), (n, 1))
+    q = workloads.random_vector(5, n)
+    y = _gpu_mvp(x, 0.3, q, 0.5, prec)
+    qr = q.astype(np.float32).astype(np.float64) if prec != "fp64" else q
+    want = qr.sum() + 0.5 * qr
+    assert _relerr(y, want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_kmvp_far_points(prec):
+    # points 1000 sigma apart: K_hat = I, y = (1 + s) q (every tile is wide)
+    n = 600
+    x = np.zeros((n, 2))
+    x[:, 0] = np.arange(n) * 1000.0
+    q = workloads.random_vector(6, n)
+    y = _gpu_mvp(x, 1.0, q, 0.25, prec)
+    assert _relerr(y, 1.25 * q) <= TOL[prec]
+
+
+def test_kmvp_deterministic():
+    x = workloads.random_points(7, 5000, 3, 10.0)
+    q = workloads.random_vector(8, 5000)
+    a = _gpu_mvp(x, 0.5, q, 0.0, "fp32")
+    b = _gpu_mvp(x, 0.5, q, 0.0, "fp32")
+    assert np.array_equal(a, b)
+
+
+def test_kmvp_permutation_equivariant():
+    x = workloads.random_points(9, 3000, 2, 1.0)
+    q = workloads.random_vector(10, 3000)
+    perm = np.random.default_rng(11).permutation(3000)
+    a = _gpu_mvp(x, 0.1, q, 0.0, "fp64")
+    b = _gpu_mvp(np.ascontiguousarray(x[perm]), 0.1, np.ascontiguousarray(q[perm]), 0.0, "fp64")
+    assert np.allclose(a[perm], b, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kmvp_kriging_shape_sampled_rows(prec):
+    # the full kriging shape (N = 1e5, d = 3), checked on 64 sampled rows
+    p = workloads.kriging()
+    q = workloads.random_vector(7, p.n)
+    y = _gpu_mvp(p.x, p.sigma, q, p.gamma, prec)
+    rows = np.random.default_rng(12).choice(p.n, 64, replace=False)
+    want = oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+    assert _relerr(y[rows], want) <= TOL[prec]
+
+
+def test_kmvp_clustered_large_bf16_sampled_rows():
+    # N = 1e6, d = 2 clustered points, BF16 inputs, 16 sampled rows
+    p = workloads.clustered_large()
+    q = workloads.random_vector(7, p.n)
+    y = _gpu_mvp(p.x, p.sigma, q, p.delta, "bf16")
+    rows = np.random.default_rng(13).choice(p.n, 16, replace=False)
+    want = oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.delta)
+    assert _relerr(y[rows], want) <= TOL["bf16"]

@@ -1,0 +1,165 @@
+"""Solver parity on the GPU against the FP64 oracle.
+
+Several iterates are correct (any w with true residual <= tol), so the checks
+are: the true FP64 relative residual ||y - K w|| / ||y||, recomputed by the
+oracle, is <= 1e-6 in every mode; the distance to the Cholesky solution w* is
+within kappa(K) x tol; and exact special cases (happy breakdown, FP64 inner CG
+iterates) match the oracle closely.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_1237_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_1408_1237_amd import api
+    return api
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = workloads.plain_small()
+    wd = oracle.direct_solve(p.x, p.sigma, p.gamma, p.y)
+    K = oracle.kernel_matrix(p.x, p.sigma)
+    K[np.diag_indices_from(K)] += p.gamma
+    ev = np.linalg.eigvalsh(K)
+    return p, wd, ev.max() / ev.min()
+
+
+def test_cg64_plain_small_against_cholesky(small):
+    p, wd, kappa = small
+    api = _api()
+    (w,), (info,) = api.krr_solve([_t(p.x)], [p.sigma], [p.gamma], [_t(p.y)], mode="cg64", max_outer=20000)
+    w = w.cpu().numpy()
+    assert info["status"] == 0
+    rel = oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w)
+    assert rel <= 1e-6
+    assert info["relres_true"] == pytest.approx(rel, rel=1e-3, abs=1e-12)
+    assert np.linalg.norm(w - wd) / np.linalg.norm(wd) <= kappa * 1e-6
+    # same algorithm and stopping rule as the oracle; with kappa ~ 1e4 the count
+    # depends on rounding (summation order), so it agrees only approximately
+    _, _, it_or, _, _ = oracle.cg(p.x, p.sigma, p.gamma, p.y, 20000, 1e-6)
+    assert abs(info["outer_iters"] - it_or) <= max(3, 0.1 * it_or)
+
+
+@pytest.mark.parametrize("inner_prec", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("gs", ["mgs", "cgs2"])
+def test_fgmres_plain_small(small, inner_prec, gs):
+    p, wd, kappa = small
+    api = _api()
+    w, info = api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y), inner_prec=inner_prec, gs=gs,
+                               inner_maxit=10)
+    w = w.cpu().numpy()
+    assert info["status"] == 0, info
+    rel = oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w)
+    assert rel <= 1e-6
+    assert info["relres_true"] == pytest.approx(rel, rel=1e-3, abs=1e-12)
+    assert np.linalg.norm(w - wd) / np.linalg.norm(wd) <= kappa * 1e-6
+    assert info["outer_iters"] >= 1 and info["inner_iters"] <= 10 * info["outer_iters"]
+
+
+def test_gmres_mode_matches_oracle_gmres(small):
+    p, wd, kappa = small
+    api = _api()
+    (w,), (info,) = api.krr_solve([_t(p.x)], [p.sigma], [p.gamma], [_t(p.y)], mode="gmres", restart_m=50,
+                                  max_outer=5000)
+    r = oracle.fgmres(p.x, p.sigma, p.gamma, p.y, m=50, max_outer=5000, tol=1e-6, inner="none")
+    assert info["status"] == 0 and r["status"] == 0
+    # FP64 on both sides with the same restart length: the step counts agree
+    assert abs(info["outer_iters"] - r["outer"]) <= 2
+    assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w.cpu().numpy()) <= 1e-6
+
+
+def test_fgmres_happy_breakdown_coincident_points():
+    n, gamma = 500, 0.1
+    x = np.zeros((n, 3))
+    api = _api()
+    w, info = api.fgmres_solve(_t(x), 1.0, gamma, _t(np.ones(n)), tol=1e-12, inner="none")
+    assert info["status"] == 0 and info["outer_iters"] == 1
+    assert np.allclose(w.cpu().numpy(), np.ones(n) / (n + gamma), rtol=1e-13)
+
+
+def test_fgmres_not_converged_returns_best_iterate(small):
+    p, wd, kappa = small
+    api = _api()
+    from paper_1408_1237_amd import native as N
+    import ctypes
+    pts = N.Points(p.n, p.d, 0)
+    xt, yt = _t(p.x), _t(p.y)
+    w = torch.zeros_like(yt)
+    o = api.make_opts(max_outer=1, tol=1e-12)
+    info = N.Info()
+    ws = api.workspace(N.workspace_size(N.KRR_WS_FGMRES, [(p.n, p.d)], opts=o), xt.device)
+    pts = N.Points(p.n, p.d, xt.data_ptr())
+    rc = N.load().fgmres_solve(ctypes.byref(pts), p.sigma, p.gamma, yt.data_ptr(), w.data_ptr(), ctypes.byref(o),
+                               ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == N.KRR_NOT_CONVERGED and info.outer_iters == 1
+    rel = oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w.cpu().numpy())
+    assert rel < 1.0 and info.relres_true == pytest.approx(rel, rel=1e-6)
+
+
+def test_fgmres_warm_start(small):
+    p, wd, kappa = small
+    api = _api()
+    x0 = wd * (1 + 1e-3)
+    w, info = api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y), x0=_t(x0))
+    assert info["status"] == 0
+    assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w.cpu().numpy()) <= 1e-6
+
+
+def test_nonfinite_input_rejected():
+    api = _api()
+    from paper_1408_1237_amd import native as N
+    x = workloads.random_points(1, 100, 2, 1.0)
+    x[17, 1] = np.nan
+    with pytest.raises(N.KrrError) as e:
+        api.fgmres_solve(_t(x), 0.3, 0.01, _t(np.ones(100)))
+    assert e.value.code == N.KRR_ENONFINITE
+    y = np.ones(100)
+    y[3] = np.inf
+    with pytest.raises(N.KrrError) as e:
+        api.fgmres_solve(_t(workloads.random_points(1, 100, 2, 1.0)), 0.3, 0.01, _t(y))
+    assert e.value.code == N.KRR_ENONFINITE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cg_inner_solve_matches_oracle_iterates(prec):
+    # truncated CG (5 iterations, no early stop) on M = K_hat + delta I
+    p = workloads.plain_small(n=1500)
+    api = _api()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    z, info = api.cg_inner_solve(_t(p.x), p.sigma, p.delta, _t(p.y).to(dt), maxit=5, tol=0.0, prec=prec)
+    zo, st, it, _, _ = oracle.cg(p.x, p.sigma, p.delta, p.y, 5, 0.0, confirm=False)
+    assert info["inner_iters"] == 5 and it == 5
+    err = np.linalg.norm(z.double().cpu().numpy() - zo) / np.linalg.norm(zo)
+    assert err <= (1e-11 if prec == "fp64" else 2e-4)
+
+
+def test_cg_inner_solve_early_stop():
+    p = workloads.plain_small(n=800)
+    api = _api()
+    z, info = api.cg_inner_solve(_t(p.x), p.sigma, 1.0, _t(p.y).float(), maxit=200, tol=1e-4, prec="fp32")
+    zo, st, it, rel, _ = oracle.cg(p.x, p.sigma, 1.0, p.y, 200, 1e-4, confirm=False)
+    assert info["inner_iters"] < 200 and abs(info["inner_iters"] - it) <= 1
+
+
+def test_krr_solve_several_systems_and_columns():
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=300, nmax=900, nrhs=2)
+    Ws, infos = api.krr_solve([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+                              [torch.from_numpy(np.asfortranarray(p.y)).cuda() for p in probs], mode="fgmres")
+    assert len(infos) == 6 and all(i["status"] == 0 for i in infos)
+    for p, W in zip(probs, Ws):
+        Wn = W.cpu().numpy()
+        for r in range(2):
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], Wn[:, r]) <= 1e-6
