@@ -73,17 +73,18 @@ void or_kernel_matrix(int64_t nt, int64_t ns, int d, const double *xt,
 /* Weighted kernel summation computed on the fly (section 1 and section 3.1,
  * "Fast matrix-vector products"): y_i = sum_j k(xt_i, xs_j) q_j.  When the
  * target and source sets are the same point set (nt == ns and xt == xs) the
- * shift term shift * q_i is added, giving y = (K_hat + shift I) q; for a
- * rectangular product shift must be 0. */
+ * shift term shift * q_i is added, giving y = (K_hat + shift I) q; a
+ * rectangular product has no shift term (shift is ignored there). */
 void or_mvp(int64_t nt, int64_t ns, int d, const double *xt, const double *xs,
             double sigma, double shift, const double *q, double *y)
 {
+    const int square = (nt == ns && xt == xs);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nt; ++i) {
         double acc = 0.0;
         for (int64_t j = 0; j < ns; ++j)
             acc += or_gauss(xt + i * d, xs + j * d, d, sigma) * q[j];
-        y[i] = acc + shift * q[i];
+        y[i] = square ? acc + shift * q[i] : acc;
     }
 }
 

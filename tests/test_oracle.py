@@ -46,6 +46,9 @@ def test_rectangular_hand_values():
     want = np.exp(-0.5) * 1 + np.exp(-2.0) * 10 + np.exp(-0.5) * 100
     assert y.shape == (1,)
     assert y[0] == pytest.approx(want, rel=1e-15)
+    # many targets, one source: only q_0 is read (no shift term in a rectangular product)
+    y1 = oracle.mvp(np.arange(300, dtype=float).reshape(-1, 1) * 0.01, 1.0, np.array([3.0]), xs=np.array([[0.0]]))
+    assert np.all(np.isfinite(y1)) and y1[0] == pytest.approx(3.0, rel=1e-15)
     # the transposed product (3 targets, 1 source) is a different vector
     y3 = oracle.mvp(np.array([[1.0], [2.0], [-1.0]]), 1.0, np.array([2.0]), xs=np.array([[0.0]]))
     assert y3 == pytest.approx(2 * np.array([np.exp(-0.5), np.exp(-2.0), np.exp(-0.5)]), rel=1e-15)
