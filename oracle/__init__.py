@@ -67,6 +67,7 @@ def _load():
                                       _int, _dbl, _int, _dbl, _ip, _dp, _dp, _dp,
                                       _dp, _dp, _dp, _ip]
             lib.or_grad.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _dp, _dp, _dp, _dp]
+            lib.or_grad_rows.argtypes = [_i64, _int, _dp, _dbl, _dp, _dp, _i64, _lp, _dp]
             _lib = lib
     return _lib
 
@@ -238,6 +239,17 @@ def grad(x, sigma: float, gamma: float, lam, w):
     _load().or_grad(n, d, _p(x), float(sigma), float(gamma), _p(lam), _p(w), _p(gx),
                     ctypes.byref(gs), ctypes.byref(gg))
     return gx, gs.value, gg.value
+
+
+def grad_rows(x, sigma: float, lam, w, rows) -> np.ndarray:
+    """The rows `rows` of the point gradient of grad() (shape (len(rows), d))."""
+    x, n, d = _pts(x)
+    lam = _f64(lam)
+    w = _f64(w)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.size, d))
+    _load().or_grad_rows(n, d, _p(x), float(sigma), _p(lam), _p(w), rows.size, rows.ctypes.data_as(_lp), _p(out))
+    return out
 
 
 def true_relres(x, sigma: float, gamma: float, y, w) -> float:

@@ -430,3 +430,27 @@ void or_grad(int64_t n, int d, const double *x, double sigma, double gamma,
     *g_logsigma = -gs / s2;
     *g_loggamma = -gamma * dot(n, lam, w);
 }
+
+/* The point gradient of or_grad for a subset of rows only:
+ * gx_rows[k*d + t] = (1/sigma^2) sum_j (lam_i w_j + lam_j w_i) K_hat_ij (x_it - x_jt),
+ * i = rows[k].  Used to check large gradients on sampled rows. */
+void or_grad_rows(int64_t n, int d, const double *x, double sigma, const double *lam,
+                  const double *w, int64_t nrows, const int64_t *rows, double *gx_rows)
+{
+    double s2 = sigma * sigma;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k];
+        for (int t = 0; t < d; ++t) gx_rows[k * d + t] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double r2 = 0.0;
+            for (int t = 0; t < d; ++t) {
+                double diff = x[i * d + t] - x[j * d + t];
+                r2 += diff * diff;
+            }
+            double kv = exp(-r2 / (2.0 * s2));
+            double c = (lam[i] * w[j] + lam[j] * w[i]) * kv / s2;
+            for (int t = 0; t < d; ++t) gx_rows[k * d + t] += c * (x[i * d + t] - x[j * d + t]);
+        }
+    }
+}

@@ -331,6 +331,15 @@ def test_gradient_against_central_differences():
         assert gx[i, t] == pytest.approx(fd, rel=1e-5, abs=1e-7)
 
 
+def test_gradient_rows_equal_full_gradient():
+    x = workloads.random_points(36, 50, 3, 1.0, kind="normal")
+    lam = workloads.random_vector(37, 50)
+    w = workloads.random_vector(38, 50)
+    gx, _, _ = oracle.grad(x, 0.7, 0.1, lam, w)
+    rows = np.array([0, 13, 49])
+    assert np.array_equal(oracle.grad_rows(x, 0.7, lam, w, rows), gx[rows])
+
+
 def test_gradient_invariants_and_closed_forms():
     x = workloads.random_points(33, 40, 4, 1.0, kind="normal")
     lam = workloads.random_vector(34, 40)
