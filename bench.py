@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed-precision flexible-preconditioned kernel solver.
+
+One step = one solve of (K_hat + gamma I) w = y on the kriging-shaped workload
+(N = 100,000 points, d = 3, x ~ U[0,10]^3, sigma = 0.5, gamma = 1e-3) with
+flexible GMRES: FP64 outer products, Gram-Schmidt (CGS2) and Givens; exactly 10
+FP32 inner CG iterations on K_hat + delta I, delta = 10 gamma; restart 100; stop
+at true relative residual 1e-6.  Inputs are resident in device memory before
+the timed region; the step includes point preparation.
+
+Beside the timed steps, one solve with the paper's inner-accuracy rule (inner
+tolerance ten times the outer one, section 6, capped at 100 inner iterations;
+no restart) and one plain FP64 CG solve are timed on the same GPU.
+
+Printed (one JSON line): whole-step kernel pair-evaluations per second (value),
+the time to a 1e-6 residual for the mixed solver and for plain FP64 CG on the
+same GPU, the roofline of the dominant kernel (the FP32 product, timed with HIP
+events inside the timed region) and the FP64 CPU oracle's pair rate on a
+bounded row sample of the same product.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "kernel-MVP pairs/s + time to 1e-6 residual, mixed-prec FGMRES vs FP64 CG"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes issue one FP32 VALU op per lane per clock
+# (packed FP32 excluded) at 2.4 GHz; FP32 matrix cores 157.3 TFLOP/s dense.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+MFMA_F32_MACS = 157.3e12 / 2
+
+
+def product_peak(d: int) -> tuple[float, str, str]:
+    """Peak pairs/s of the FP32 product kernel that runs for dimension d.
+
+    d <= 16 (matrix-core exponent): per pair one exp2 and one FMA on the VALU and
+    4 ceil((d+1)/4) FP32 MACs on the matrix cores; the smaller of the two rates.
+    Otherwise (VALU kernel): d + 2 VALU issue slots per pair.
+    """
+    if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
+        dk = (d + 4) // 4
+        valu = VALU_LANE_OPS / 2
+        mfma = MFMA_F32_MACS / (4 * dk)
+        rule = ("min(256 CU x 64 lanes x 2.4 GHz / 2 VALU ops per pair, "
+                f"157.3 TFLOP/s / (2 x {4 * dk} MACs per pair))")
+        return min(valu, mfma), rule, f"k_kmvp_mg<{d}, FP32>"
+    return VALU_LANE_OPS / (d + 2), "256 CU x 64 lanes x 2.4 GHz / (d + 2) VALU slots per pair", f"k_kmvp<{d}, FP32>"
+
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kmvp.hip", "krr_internal.h"):
+        with open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name: str):
+    """Per-launch HBM bytes of the product kernel from the committed counter summary."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(p, target_s: float = 12.0) -> dict:
+    """FP64 oracle kernel sum on a bounded sample of rows (OpenMP over rows)."""
+    import numpy as np
+
+    import oracle
+    from paper_1408_1237_amd import workloads
+
+    q = workloads.random_vector(7, p.n)
+    rng = np.random.default_rng(0)
+    rows = rng.choice(p.n, 64, replace=False)
+    t0 = time.perf_counter()
+    oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+    dt = time.perf_counter() - t0
+    nrows = int(min(p.n, max(64, 64 * target_s / max(dt, 1e-3))))
+    rows = rng.choice(p.n, nrows, replace=False)
+    t0 = time.perf_counter()
+    oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+    dt = time.perf_counter() - t0
+    pairs = float(nrows) * p.n
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nrows} rows x {p.n} sources of (K_hat + gamma I) q, FP64 on-the-fly loop, {dt:.1f} s"}
+
+
+def kernel_only(api, native, workloads, torch, p, x, reps: int) -> int:
+    """Repeated FP32 products (through the C ABI, which also prepares the points
+    each call) and one plain copy of known size for counter calibration."""
+    q = torch.from_numpy(workloads.random_vector(7, p.n)).float().cuda()
+    ws = api.workspace(native.workspace_size(native.KRR_WS_KMVP, [(p.n, p.d)]), x.device)
+    api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec="fp32", ws=ws)  # tunes the plan
+    torch.cuda.synchronize()
+    with native.profile() as prof:
+        for _ in range(reps):
+            api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec="fp32", ws=ws)
+        torch.cuda.synchronize()
+    a = torch.ones(64 << 20, dtype=torch.float32, device=x.device)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    st = prof.stats["fp32"]
+    ach = st["pairs"] / (st["total_ms"] * 1e-3) / 1e9
+    print(json.dumps({"mode": "kernel-only", "n": p.n, "d": p.d, "launches": st["launches"],
+                      "avg_launch_ms": st["total_ms"] / max(st["launches"], 1), "gpair_s": ach,
+                      "copy_bytes": 2 * a.numel() * 4}), flush=True)
+    return 0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cg", action="store_true", help="skip the FP64 CG comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
+                    help="only K FP32 products on the workload's points plus one 256 MiB copy "
+                         "(the short run used for rocprofv3 counter passes)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded path is not built.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1408_1237_amd import api, native, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    native.load()
+    p = workloads.kriging(n=args.n)
+    x = torch.from_numpy(p.x).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    if args.kernel_only:
+        return kernel_only(api, native, workloads, torch, p, x, args.kernel_only)
+    opts = dict(inner_prec="fp32", inner_maxit=p.inner_maxit, inner_tol=0.0, delta=p.delta, restart_m=100,
+                tol=p.tol, max_outer=5000, gs="cgs2")
+    paper_opts = dict(inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol, delta=p.delta, restart_m=1000,
+                      tol=p.tol, max_outer=1000, gs="cgs2")
+    need = max(native.workspace_size(native.KRR_WS_FGMRES, [(p.n, p.d)], opts=api.make_opts(**o))
+               for o in (opts, paper_opts))
+    ws = api.workspace(need, x.device)
+    log(f"workload kriging n={p.n} d={p.d} sigma={p.sigma} gamma={p.gamma}; workspace {need / 2**20:.0f} MiB")
+
+    for k in range(args.warmup):
+        w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, ws=ws, **opts)
+        log(f"warmup {k}: status={info['status']} outer={info['outer_iters']} relres={info['relres_true']:.3e}")
+    torch.cuda.synchronize()
+
+    infos = []
+    with native.profile(max_launches=200_000) as prof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, ws=ws, **opts)
+            infos.append(info)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    for k, info in enumerate(infos):
+        log(f"step {k}: status={info['status']} outer={info['outer_iters']} inner={info['inner_iters']} "
+            f"mvp64={info['mvp64']} mvp32={info['mvp32']} relres={info['relres_true']:.3e} "
+            f"t={info['t_total_ms']:.1f} ms")
+    if any(i["status"] != 0 or i["relres_true"] > p.tol for i in infos):
+        log("FGMRES did not reach the tolerance")
+    pairs_step = sum((i["mvp64"] + i["mvp32"] + i["mvp16"]) for i in infos) * float(p.n) ** 2
+    value = pairs_step / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    st = prof.stats
+    f32 = st["fp32"]
+    f64 = st["fp64"]
+    achieved = f32["pairs"] / (f32["total_ms"] * 1e-3) / 1e9
+    peak_pairs, peak_rule, kname = product_peak(p.d)
+    peak = peak_pairs / 1e9
+    traffic = read_traffic("kmvp_fp32_d3_kriging_counters.txt")
+    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gpair/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": kname, "launches": f32["launches"],
+                "avg_launch_ms": round(f32["total_ms"] / max(f32["launches"], 1), 4),
+                "peak_rule": peak_rule,
+                "fp64_kernel_gpair_s": round(f64["pairs"] / max(f64["total_ms"], 1e-9) / 1e6, 1),
+                "fp64_avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4)}
+    log(f"kernel fp32: {f32['launches']} launches, {roofline['avg_launch_ms']} ms avg, {achieved:.0f} Gpair/s "
+        f"({100 * achieved / peak:.1f}% of {peak:.0f}); fp64: {roofline['fp64_kernel_gpair_s']} Gpair/s")
+
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"kriging-shaped N={p.n} d=3 x~U[0,10]^3 sigma=0.5 gamma=1e-3; "
+                                  "FGMRES(100) FP64 outer, 10 FP32 inner CG on K_hat+1e-2 I, tol 1e-6",
+                      "n": p.n, "d": p.d, "parallelism": "single GPU"},
+           "fgmres": {"time_to_solution_s": ms_per_step / 1e3, "outer_iters": infos[-1]["outer_iters"],
+                      "inner_iters": infos[-1]["inner_iters"], "mvp64": infos[-1]["mvp64"],
+                      "mvp32": infos[-1]["mvp32"], "relres_true": infos[-1]["relres_true"]},
+           "roofline": roofline}
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wp, ip = api.fgmres_solve(x, p.sigma, p.gamma, y, ws=ws, **paper_opts)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log(f"fgmres (paper inner rule): status={ip['status']} outer={ip['outer_iters']} inner={ip['inner_iters']} "
+        f"relres={ip['relres_true']:.3e} t={tp:.2f} s")
+    out["fgmres_paper_rule"] = {"time_to_solution_s": tp, "outer_iters": ip["outer_iters"],
+                                "inner_iters": ip["inner_iters"], "mvp64": ip["mvp64"], "mvp32": ip["mvp32"],
+                                "relres_true": ip["relres_true"], "status": ip["status"],
+                                "settings": "inner tol 1e-5 (10x outer), <= 100 inner its, restart 1000"}
+
+    if not args.no_cg:
+        o64 = dict(tol=p.tol, max_outer=20000, cg_check=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", ws=ws, **o64)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        log(f"cg64: status={ic['status']} iters={ic['outer_iters']} relres={ic['relres_true']:.3e} t={tc:.2f} s")
+        out["cg64"] = {"time_to_solution_s": tc, "iters": ic["outer_iters"], "mvp64": ic["mvp64"],
+                       "relres_true": ic["relres_true"], "status": ic["status"]}
+        out["speedup_fgmres_vs_cg64"] = tc / (ms_per_step / 1e3)
+        out["speedup_fgmres_paper_rule_vs_cg64"] = tc / tp
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p)
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} pairs/s on {out['cpu_baseline']['cores']} threads")
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

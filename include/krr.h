@@ -216,6 +216,29 @@ int krr_solve(const krr_points *probs /* host */, int32_t nprob, const double *s
               krr_info *infos /* host, may be NULL */, void *ws, size_t ws_bytes,
               krr_stream_t stream);
 
+/* Launch timing of the kernel products (measurement support).  Between
+ * krr_profile_begin() and krr_profile_end() every kernel-product launch made by
+ * any call on this process records a pair of HIP events on its own stream
+ * around the product kernel (the main O(N^2) kernel, not the O(N) partial-sum
+ * kernel).  krr_profile_end() waits for the recorded events and returns, per
+ * product precision, the launch count, the summed kernel time and the summed
+ * algorithmic pair count (n_targets x n_sources, padding excluded).  At most
+ * max_launches launches are recorded (later ones are counted in `dropped`).
+ * Host-side state only; no device memory is allocated.  Not thread-safe. */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double pairs;
+} krr_profile_entry;
+
+typedef struct {
+    krr_profile_entry prec[3]; /* indexed by krr_prec */
+    int64_t dropped;
+} krr_profile_stats;
+
+int krr_profile_begin(int32_t max_launches);
+int krr_profile_end(krr_profile_stats *out /* host */);
+
 #ifdef __cplusplus
 }
 #endif

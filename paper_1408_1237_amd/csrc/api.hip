@@ -75,8 +75,7 @@ Layout carve(void *ws, int64_t n, int d, const SolverOpts &o, Kind kind) {
         L.q = cv.take<double>(L.P.n_pad);
         L.y = cv.take<double>(L.P.n_pad);
         L.q16 = cv.take<uint16_t>(L.P.n_pad);
-        const size_t parts = kmvp_parts_bytes(L.P, KRR_FP64);
-        L.W.parts = cv.take<char>(parts > 0 ? parts : 256);
+        L.W.ksc = carve_kmvp_scratch(cv, L.P);
     } else {
         L.W = carve_solver(cv, L.P, o, kind == K_FGMRES || kind == K_INNER);
     }
@@ -85,6 +84,72 @@ Layout carve(void *ws, int64_t n, int d, const SolverOpts &o, Kind kind) {
 }
 
 size_t layout_bytes(int64_t n, int d, const SolverOpts &o, Kind kind) { return carve(nullptr, n, d, o, kind).total; }
+
+// Several right-hand sides: one prepared set and the product scratch.
+struct MultiLayout {
+    Prepared P;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    void *scratch = nullptr;
+    size_t total = 0;
+};
+
+MultiLayout carve_multi(void *ws, int64_t n, int d, int nrhs) {
+    Carver cv(ws);
+    MultiLayout L;
+    L.P = carve_prepared(cv, n, d);
+    L.temp_bytes = prep_temp_bytes(n);
+    L.temp = cv.take<char>(L.temp_bytes);
+    L.scratch = cv.take<char>(kmvp_multi_scratch_bytes(L.P, nrhs));
+    L.total = cv.off + 256;
+    return L;
+}
+
+// Gradient pass: one prepared set and the pass's scratch.
+struct GradLayout {
+    Prepared P;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    void *scratch = nullptr;
+    size_t total = 0;
+};
+
+GradLayout carve_grad(void *ws, int64_t n, int d) {
+    Carver cv(ws);
+    GradLayout L;
+    L.P = carve_prepared(cv, n, d);
+    L.temp_bytes = prep_temp_bytes(n);
+    L.temp = cv.take<char>(L.temp_bytes);
+    L.scratch = cv.take<char>(grad_scratch_bytes(L.P));
+    L.total = cv.off + 256;
+    return L;
+}
+
+// Rectangular product: two prepared sets, one preparation scratch (reused).
+struct CrossLayout {
+    Prepared T, S;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    void *q = nullptr, *y = nullptr;
+    uint16_t *q16 = nullptr;
+    KmvpScratch ksc;
+    size_t total = 0;
+};
+
+CrossLayout carve_cross(void *ws, int64_t nt, int64_t ns, int d) {
+    Carver cv(ws);
+    CrossLayout L;
+    L.T = carve_prepared(cv, nt, d);
+    L.S = carve_prepared(cv, ns, d);
+    L.temp_bytes = prep_temp_bytes(nt > ns ? nt : ns);
+    L.temp = cv.take<char>(L.temp_bytes);
+    L.q = cv.take<double>(L.S.n_pad);
+    L.y = cv.take<double>(L.T.n_pad);
+    L.q16 = cv.take<uint16_t>(L.S.n_pad);
+    L.ksc = carve_kmvp_cross_scratch(cv, L.T, L.S);
+    L.total = cv.off + 256;
+    return L;
+}
 
 // Align the caller's workspace to 256 bytes.
 void *align_ws(void *ws, size_t &bytes) {
@@ -142,16 +207,26 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
     if (resolve_opts(opts, 0.0, o) != KRR_OK) return 0;
     switch (which) {
         case KRR_WS_KMVP:
-        case KRR_WS_KMVP_MULTI:
-        case KRR_WS_KMVP_GRAD:
             if (probs[0].n < 1 || probs[0].d < 1 || probs[0].d > KRR_MAX_DIM) return 0;
             return layout_bytes(probs[0].n, probs[0].d, o, K_MVP) + 256;
+        case KRR_WS_KMVP_GRAD:
+            if (probs[0].n < 1 || probs[0].d < 1 || probs[0].d > KRR_MAX_DIM) return 0;
+            return carve_grad(nullptr, probs[0].n, probs[0].d).total + 256;
+        case KRR_WS_KMVP_MULTI:
+            if (probs[0].n < 1 || probs[0].d < 1 || probs[0].d > KRR_MAX_DIM || nrhs < 1 || nrhs > 4096) return 0;
+            return carve_multi(nullptr, probs[0].n, probs[0].d, nrhs).total + 256;
         case KRR_WS_CG_INNER:
             if (probs[0].n < 1 || probs[0].d < 1 || probs[0].d > KRR_MAX_DIM) return 0;
             return layout_bytes(probs[0].n, probs[0].d, o, K_INNER) + 256;
         case KRR_WS_FGMRES:
             if (probs[0].n < 1 || probs[0].d < 1 || probs[0].d > KRR_MAX_DIM) return 0;
             return layout_bytes(probs[0].n, probs[0].d, o, K_FGMRES) + 256;
+        case KRR_WS_KMVP_CROSS:
+            if (nprob < 2) return 0;
+            for (int k = 0; k < 2; ++k)
+                if (probs[k].n < 1 || probs[k].d < 1 || probs[k].d > KRR_MAX_DIM) return 0;
+            if (probs[0].d != probs[1].d) return 0;
+            return carve_cross(nullptr, probs[0].n, probs[1].n, probs[0].d).total + 256;
         case KRR_WS_SOLVE: {
             if (nrhs < 1) return 0;
             size_t mx = 0;
@@ -159,6 +234,10 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
                 if (probs[k].n < 1 || probs[k].d < 1 || probs[k].d > KRR_MAX_DIM) return 0;
                 const size_t b = layout_bytes(probs[k].n, probs[k].d, o, K_FGMRES);
                 if (b > mx) mx = b;
+            }
+            if (nprob > 1 || nrhs > 1) {
+                const size_t bb = batch_workspace_bytes(probs, nprob, nrhs, o.restart_m);
+                if (bb > mx) mx = bb;
             }
             return mx + 256;
         }
@@ -181,7 +260,8 @@ int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, 
     KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
     if (prec == KRR_FP64) {
         KRR_HIP_STATUS((gather_sorted<double, double>(L.P, static_cast<const double *>(q), static_cast<double *>(L.q), s)));
-        KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, L.q, L.y, L.W.parts, nullptr, s));
+        KRR_HIP_STATUS(kmvp_tune(L.P, prec, L.q, L.y, L.W.ksc, s));
+        KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, L.q, L.y, L.W.ksc, nullptr, s));
         KRR_HIP_STATUS((scatter_sorted<double, double>(L.P, static_cast<double *>(L.y), static_cast<double *>(y), s)));
     } else {
         float *qs = static_cast<float *>(L.q);
@@ -191,7 +271,8 @@ int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, 
             KRR_HIP_STATUS(to_bf16(qs, L.q16, L.P.n_pad, s));
             qin = L.q16;
         }
-        KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, qin, L.y, L.W.parts, nullptr, s));
+        KRR_HIP_STATUS(kmvp_tune(L.P, prec, qin, L.y, L.W.ksc, s));
+        KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, qin, L.y, L.W.ksc, nullptr, s));
         KRR_HIP_STATUS((scatter_sorted<float, float>(L.P, static_cast<float *>(L.y), static_cast<float *>(y), s)));
     }
     return KRR_OK;
@@ -201,27 +282,69 @@ int kmvp_gauss_multi(const krr_points *pts, double sigma, double shift, int32_t 
                      int64_t ldq, void *Y, int64_t ldy, void *ws, size_t ws_bytes, krr_stream_t stream) {
     int rc;
     if ((rc = check_points(pts)) || (rc = check_sigma(sigma)) || (rc = check_prec(prec))) return rc;
-    if (!is_fin(shift) || Q == nullptr || Y == nullptr || nrhs < 1 || ldq < pts->n || ldy < pts->n) return KRR_EINVAL;
-    const size_t el = prec == KRR_FP64 ? 8 : 4;
-    for (int r = 0; r < nrhs; ++r) {
-        const void *qr = static_cast<const char *>(Q) + static_cast<size_t>(r) * ldq * el;
-        void *yr = static_cast<char *>(Y) + static_cast<size_t>(r) * ldy * el;
-        if ((rc = kmvp_gauss(pts, sigma, shift, prec, qr, yr, ws, ws_bytes, stream)) != KRR_OK) return rc;
-    }
+    if (!is_fin(shift) || Q == nullptr || Y == nullptr || Q == Y || nrhs < 1 || nrhs > 4096 || ldq < pts->n ||
+        ldy < pts->n)
+        return KRR_EINVAL;
+    if (ws == nullptr) return KRR_EWORKSPACE;
+    ws = align_ws(ws, ws_bytes);
+    MultiLayout L = carve_multi(nullptr, pts->n, pts->d, nrhs);
+    if (L.total > ws_bytes) return KRR_EWORKSPACE;
+    L = carve_multi(ws, pts->n, pts->d, nrhs);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(kmvp_multi(L.P, prec, nrhs, shift, L.P.perm, Q, ldq, Y, ldy, L.scratch, s));
     return KRR_OK;
 }
 
 int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, double sigma, int32_t prec,
                      const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
-    (void)targets; (void)sources; (void)sigma; (void)prec; (void)q; (void)y; (void)ws; (void)ws_bytes; (void)stream;
-    return KRR_EUNSUPPORTED;
+    int rc;
+    if ((rc = check_points(targets)) || (rc = check_points(sources)) || (rc = check_sigma(sigma)) ||
+        (rc = check_prec(prec)))
+        return rc;
+    if (targets->d != sources->d || q == nullptr || y == nullptr || q == y) return KRR_EINVAL;
+    if (ws == nullptr) return KRR_EWORKSPACE;
+    ws = align_ws(ws, ws_bytes);
+    CrossLayout L = carve_cross(nullptr, targets->n, sources->n, targets->d);
+    if (L.total > ws_bytes) return KRR_EWORKSPACE;
+    L = carve_cross(ws, targets->n, sources->n, targets->d);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KRR_HIP_STATUS(prepare_points(L.T, targets->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(prepare_points(L.S, sources->x, sigma, L.temp, L.temp_bytes, s));
+    if (prec == KRR_FP64) {
+        KRR_HIP_STATUS((gather_sorted<double, double>(L.S, static_cast<const double *>(q), static_cast<double *>(L.q), s)));
+        KRR_HIP_STATUS(kmvp_cross_sorted(L.T, L.S, prec, L.q, L.y, L.ksc, s));
+        KRR_HIP_STATUS((scatter_sorted<double, double>(L.T, static_cast<double *>(L.y), static_cast<double *>(y), s)));
+    } else {
+        float *qs = static_cast<float *>(L.q);
+        KRR_HIP_STATUS((gather_sorted<float, float>(L.S, static_cast<const float *>(q), qs, s)));
+        const void *qin = qs;
+        if (prec == KRR_BF16) {
+            KRR_HIP_STATUS(to_bf16(qs, L.q16, L.S.n_pad, s));
+            qin = L.q16;
+        }
+        KRR_HIP_STATUS(kmvp_cross_sorted(L.T, L.S, prec, qin, L.y, L.ksc, s));
+        KRR_HIP_STATUS((scatter_sorted<float, float>(L.T, static_cast<float *>(L.y), static_cast<float *>(y), s)));
+    }
+    return KRR_OK;
 }
 
 int kmvp_grad(const krr_points *pts, double sigma, double gamma, const double *lam, const double *w, double *gx,
               double *g_logsigma, double *g_loggamma, void *ws, size_t ws_bytes, krr_stream_t stream) {
-    (void)pts; (void)sigma; (void)gamma; (void)lam; (void)w; (void)gx; (void)g_logsigma; (void)g_loggamma;
-    (void)ws; (void)ws_bytes; (void)stream;
-    return KRR_EUNSUPPORTED;
+    int rc;
+    if ((rc = check_points(pts)) || (rc = check_sigma(sigma))) return rc;
+    if (!is_fin(gamma) || gamma < 0.0 || lam == nullptr || w == nullptr || gx == nullptr || g_logsigma == nullptr ||
+        g_loggamma == nullptr)
+        return KRR_EINVAL;
+    if (ws == nullptr) return KRR_EWORKSPACE;
+    ws = align_ws(ws, ws_bytes);
+    GradLayout L = carve_grad(nullptr, pts->n, pts->d);
+    if (L.total > ws_bytes) return KRR_EWORKSPACE;
+    L = carve_grad(ws, pts->n, pts->d);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(kmvp_grad_run(L.P, sigma, gamma, lam, w, gx, g_logsigma, g_loggamma, L.scratch, s));
+    return KRR_OK;
 }
 
 int cg_inner_solve(const krr_points *pts, double sigma, double shift, int32_t prec, const void *v, void *z,
@@ -322,6 +445,15 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     if (ws == nullptr) return KRR_EWORKSPACE;
     ws = align_ws(ws, ws_bytes);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (mode != KRR_MODE_CG64 && (nprob > 1 || nrhs > 1)) {
+        // all systems and columns advance together (one product launch per system
+        // per step for all columns, per-column solver state on the device)
+        SolverOpts o;
+        resolve_opts(opts, gamma[0], o);
+        o.delta = (opts && opts->delta >= 0) ? opts->delta : -1.0;  // per system: 10 gamma_k
+        if (mode == KRR_MODE_GMRES) o.inner = KRR_INNER_NONE;
+        return batched_fgmres(probs, nprob, sigma, gamma, nrhs, Y, ldy, W, o, infos, ws, ws_bytes, s);
+    }
     int worst = KRR_OK;
     for (int k = 0; k < nprob; ++k) {
         SolverOpts o;
@@ -337,5 +469,9 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     }
     return worst;
 }
+
+int krr_profile_begin(int32_t max_launches) { return profile_begin(max_launches); }
+
+int krr_profile_end(krr_profile_stats *out) { return profile_end(out); }
 
 }  // extern "C"

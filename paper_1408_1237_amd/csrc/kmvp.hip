@@ -10,6 +10,13 @@
 // addresses, so it arrives through scalar loads into SGPRs and feeds the VALU
 // directly: no LDS staging and no barriers.  Per pair the folded form costs d
 // fused multiply-adds, one exp2 and one accumulate (layout in krr_internal.h).
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "krr_internal.h"
 
 namespace krr {
@@ -91,17 +98,24 @@ constexpr int unroll_cols() {
     return u >= 16 ? 16 : u >= 8 ? 8 : u >= 4 ? 4 : u >= 2 ? 2 : 1;
 }
 
+// Rows are the target points (one lane each), columns the source points.  For
+// the square product both are the same prepared set and the shift term is added.
 struct KArgs {
-    int64_t n, n_pad;
-    int ntiles, nrowblocks, splits, tps;
+    int64_t n_rows, n_pad_rows;  // targets
+    int nrowblocks;
+    const double *row_anchor;
+    const void *row_off;
+    int64_t n_pad;               // sources
+    int ntiles, splits, tps;
     const double *anchor;
     const double *tile_r2;
     const double *tile_nj;
     const void *off;
-    const void *w;
     const void *q;
+    const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
     void *out;
-    double shift;
+    double shift;    // square products only
+    int square;
     const int *active;
 };
 
@@ -114,21 +128,22 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
     using Q = typename P::Q;
     constexpr int U = unroll_cols<D, PREC>();
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
-    const T *__restrict__ w = static_cast<const T *>(a.w);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const T *__restrict__ qw = static_cast<const T *>(a.qw);
     const double *__restrict__ anchor = a.anchor;
     const int64_t n_pad = a.n_pad;
 
     const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
 
     double aI[D];
     T oi[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        aI[k] = anchor[static_cast<int64_t>(bx) * D + k];
-        oi[k] = P::off(off[k * n_pad + i]);
+        aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
+        oi[k] = P::off(row_off[k * a.n_pad_rows + i]);
     }
     T acc = T(0);
     const int J0 = by * a.tps;
@@ -151,15 +166,36 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
 #pragma unroll
             for (int k = 0; k < D; ++k) Tk[k] = t[k] + t[k];
             const T c = static_cast<T>(-tt - nj);
+            // Source values of one chunk of U columns live in SGPRs; the next
+            // chunk is requested before the current one is consumed.
+            T co[D][U], cq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cq[u] = qw[j0 + u];
+#pragma unroll
+                for (int k = 0; k < D; ++k) co[k][u] = P::off(off[k * n_pad + j0 + u]);
+            }
             for (int jb = 0; jb < TILE; jb += U) {
+                const int64_t jn = j0 + ((jb + U) & (TILE - 1));  // wraps on the last chunk (in bounds)
+                T no[D][U], nq[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int64_t j = j0 + jb + u;
-                    const T qq = P::q(q[j]) * w[j];
-                    T arg = c;
+                    nq[u] = qw[jn + u];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) arg = fma_t(Tk[k], P::off(off[k * n_pad + j]), arg);
-                    acc = fma_t(P::ex2(arg), qq, acc);
+                    for (int k = 0; k < D; ++k) no[k][u] = P::off(off[k * n_pad + jn + u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    T arg = fma_t(Tk[0], co[0][u], c);
+#pragma unroll
+                    for (int k = 1; k < D; ++k) arg = fma_t(Tk[k], co[k][u], arg);
+                    acc = fma_t(P::ex2(arg), cq[u], acc);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    cq[u] = nq[u];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) co[k][u] = no[k][u];
                 }
             }
         } else {
@@ -179,16 +215,173 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
         }
     }
     T *out = static_cast<T *>(a.out);
-    if (a.splits == 1)
-        out[i] = (i < a.n) ? acc + static_cast<T>(a.shift) * P::q(q[i]) : T(0);
-    else
-        out[static_cast<int64_t>(by) * n_pad + i] = acc;
+    if (a.splits == 1) {
+        if (i < a.n_rows && a.square) acc += static_cast<T>(a.shift) * P::q(q[i]);
+        out[i] = (i < a.n_rows) ? acc : T(0);
+    } else {
+        out[static_cast<int64_t>(by) * a.n_pad_rows + i] = acc;
+    }
 }
 
-// y_i = sum_s parts[s][i] + shift q_i for i < n, 0 on the padding.
+// ---------------------------------------------------------------- matrix-core exponent
+//
+// FP32 / BF16 products with the exponent on the matrix cores.  The folded
+// exponent of a pair is an inner product of length d + 1,
+//   arg_ij = [2 t_i, c_i] . [o_j, 1],   t_i = x_i - a_J, c_i = -||t_i||^2 - N_J,
+// so v_mfma_f32_16x16x4f32 forms it for 16 x 16 pairs at once (DK = ceil((d+1)/4)
+// instructions): A = the 16 sources x 4 coordinates (lane l: source l % 16,
+// coordinate l / 16 of the chunk), B = the 4 coordinates x 16 targets (lane l:
+// target l % 16), and the accumulator gives lane l the exponents of target
+// l % 16 against sources 4 (l / 16) + v, v < 4.  The VALU then does exp2 and one
+// fused multiply-add per pair, accumulating each target's sum in the four lanes
+// that hold it (added by two cross-lane steps at the end).  A wave owns 4 groups
+// of 16 targets (64 rows), a block one 256-row tile.  Wide tiles use the direct
+// form on the VALU.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using Off = typename P::Off;
+    using Q = typename P::Q;
+    constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
+    constexpr int RG = 4;
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const float *__restrict__ qw = static_cast<const float *>(a.qw);
+    const int64_t n_pad = a.n_pad;
+
+    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int lane = threadIdx.x % WAVE;
+    const int r16 = lane % 16, g = lane / 16;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (threadIdx.x / WAVE) * 64;
+
+    double aI[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
+    float oi[RG][D];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+        for (int k = 0; k < D; ++k) oi[rg][k] = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
+    float acc[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.f;
+
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    for (int J = J0; J < J1; ++J) {
+        const double r2 = a.tile_r2[J];
+        const double nj = a.tile_nj[J];
+        float t[RG][D];
+        float bval[RG][DK];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            double tt = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                t[rg][k] = static_cast<float>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
+                                              static_cast<double>(oi[rg][k]));
+                const double tk = static_cast<double>(t[rg][k]);
+                tt = __builtin_fma(tk, tk, tt);
+            }
+            const float c = static_cast<float>(-tt - nj);
+            // coordinate 4 kc + g of [2t, c, 0...] for this lane's chunk slots
+#pragma unroll
+            for (int kc = 0; kc < DK; ++kc) {
+                const int dim = 4 * kc + g;
+                float v = (dim == D) ? c : 0.f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) v = (dim == k) ? 2.f * t[rg][k] : v;
+                bval[rg][kc] = v;
+            }
+        }
+        const int64_t j0 = static_cast<int64_t>(J) * TILE;
+        if (r2 <= P::wide) {
+#pragma unroll 2
+            for (int cb = 0; cb < TILE; cb += 16) {
+                const int64_t col = j0 + cb;
+                float aval[DK];
+#pragma unroll
+                for (int kc = 0; kc < DK; ++kc) {
+                    const int dim = 4 * kc + g;
+                    const int dsafe = dim < D ? dim : D - 1;
+                    const float o = P::off(off[dsafe * n_pad + col + r16]);
+                    aval[kc] = dim < D ? o : (dim == D ? 1.f : 0.f);
+                }
+                const floatx4_t qv = *reinterpret_cast<const floatx4_t *>(qw + col + 4 * g);
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) {
+                    floatx4_t G = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kc = 0; kc < DK; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(aval[kc], bval[rg][kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[v]), qv[v], acc[rg]);
+                }
+            }
+        } else {
+            for (int cb = 0; cb < TILE; cb += 16) {
+                const int64_t col = j0 + cb + 4 * g;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float oc[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + col + v]);
+                    const float qj = P::q(q[col + v]);
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg) {
+                        float ss = 0.f;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float dd = t[rg][k] - oc[k];
+                            ss = __builtin_fmaf(dd, dd, ss);
+                        }
+                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), qj, acc[rg]);
+                    }
+                }
+            }
+        }
+    }
+    float *out = static_cast<float *>(a.out);
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+        float sum = acc[rg];
+        sum += __shfl_xor(sum, 16, WAVE);
+        sum += __shfl_xor(sum, 32, WAVE);
+        const int64_t i = row0 + rg * 16 + r16;
+        if (g == 0) {
+            if (a.splits == 1) {
+                if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
+                out[i] = (i < a.n_rows) ? sum : 0.f;
+            } else {
+                out[static_cast<int64_t>(by) * a.n_pad_rows + i] = sum;
+            }
+        }
+    }
+}
+
+// qw_j = q_j * w_j (the per-source factor of the folded form), once per product.
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void k_prescale(int64_t n_pad, const void *q_, const void *w_, void *qw_,
+                                                    const int *active) {
+    if (active != nullptr && *active == 0) return;
+    using P = Prec<PREC>;
+    using T = typename P::T;
+    const typename P::Q *q = static_cast<const typename P::Q *>(q_);
+    const T *w = static_cast<const T *>(w_);
+    T *qw = static_cast<T *>(qw_);
+    const int64_t i = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    if (i < n_pad) qw[i] = P::q(q[i]) * w[i];
+}
+
+// y_i = sum_s parts[s][i] (+ shift q_i when square) for i < n, 0 on the padding.
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad, int splits, const void *parts_,
-                                                       const void *q_, double shift, void *y_, const int *active) {
+                                                       const void *q_, double shift, int square, void *y_,
+                                                       const int *active) {
     if (active != nullptr && *active == 0) return;
     using P = Prec<PREC>;
     using T = typename P::T;
@@ -203,31 +396,104 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad,
     }
     T s = parts[i];
     for (int k = 1; k < splits; ++k) s += parts[static_cast<int64_t>(k) * n_pad + i];
-    y[i] = s + static_cast<T>(shift) * P::q(q[i]);
+    y[i] = square ? s + static_cast<T>(shift) * P::q(q[i]) : s;
 }
 
-KmvpPlan kmvp_plan(const Prepared &P, int prec) {
-    (void)prec;
+// ---------------------------------------------------------------- plans and tuning
+
+// Column splits: enough blocks to fill the chip several times over for small
+// N; few splits once the row tiles alone give thousands of blocks.
+int kmvp_max_splits(const Prepared &P) {
+    int m = P.ntiles / 2 > 1 ? P.ntiles / 2 : 1;
+    const int cap = P.ntiles >= 2048 ? 4 : 32;
+    return m < cap ? m : cap;
+}
+
+static KmvpPlan plan_for(const Prepared &P, int splits) {
     KmvpPlan pl;
-    const int rowblocks = P.ntiles;
-    const int target_blocks = 4096;
-    int splits = (target_blocks + rowblocks - 1) / rowblocks;
-    int max_splits = P.ntiles / 2 > 1 ? P.ntiles / 2 : 1;
-    if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
+    if (splits > kmvp_max_splits(P)) splits = kmvp_max_splits(P);
     pl.tiles_per_split = (P.ntiles + splits - 1) / splits;
     pl.splits = (P.ntiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
     return pl;
 }
 
-size_t kmvp_parts_bytes(const Prepared &P, int prec) {
-    const KmvpPlan pl = kmvp_plan(P, prec);
-    const size_t el = prec == KRR_FP64 ? 8 : 4;
-    return pl.splits > 1 ? static_cast<size_t>(pl.splits) * P.n_pad * el : 0;
+static KmvpPlan heuristic_plan(const Prepared &P) {
+    const int target_blocks = 4096;
+    return plan_for(P, (target_blocks + P.ntiles - 1) / P.ntiles);
+}
+
+namespace {
+struct TuneKey {
+    int prec, dpad, ntiles;
+    bool operator<(const TuneKey &o) const {
+        return prec != o.prec ? prec < o.prec : dpad != o.dpad ? dpad < o.dpad : ntiles < o.ntiles;
+    }
+};
+std::map<TuneKey, int> g_tuned;
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+
+// Optional persistent cache: KRR_TUNE_CACHE names a text file of lines
+// "prec dpad ntiles splits".
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("KRR_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int a, b, c, d;
+    while (std::fscanf(f, "%d %d %d %d", &a, &b, &c, &d) == 4) g_tuned[TuneKey{a, b, c}] = d;
+    std::fclose(f);
+}
+
+void tune_cache_append(const TuneKey &k, int splits) {
+    const char *path = std::getenv("KRR_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d\n", k.prec, k.dpad, k.ntiles, splits);
+    std::fclose(f);
+}
+}  // namespace
+
+KmvpPlan kmvp_plan(const Prepared &P, int prec) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tuned.find(TuneKey{prec, P.dpad, P.ntiles});
+    if (it != g_tuned.end()) return plan_for(P, it->second);
+    return heuristic_plan(P);
+}
+
+size_t kmvp_scratch_bytes(const Prepared &P) {
+    const size_t parts = static_cast<size_t>(kmvp_max_splits(P)) * P.n_pad * 8;
+    return align_up(parts, 256) + align_up(static_cast<size_t>(P.n_pad) * 8, 256);
+}
+
+KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
+    KmvpScratch k;
+    k.parts = cv.take<double>(static_cast<size_t>(kmvp_max_splits(P)) * P.n_pad);
+    k.qw = cv.take<double>(P.n_pad);
+    return k;
+}
+
+// FP32 / BF16 products up to d = 16 take the matrix-core exponent kernel; FP64
+// and larger d the VALU kernel.  KRR_KMVP_VALU=1 forces the VALU kernel (used to
+// cross-check the two).
+static bool use_valu_kernel() {
+    const char *v = std::getenv("KRR_KMVP_VALU");
+    return v && v[0] == '1';
 }
 
 template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, hipStream_t s) {
+    if constexpr (PREC != KRR_FP64 && D <= 16) {
+        if (!use_valu_kernel()) {
+            hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -251,62 +517,234 @@ static hipError_t launch_kmvp_d(int dpad, const KArgs &a, hipStream_t s) {
     }
 }
 
-hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, void *parts,
-                       const int *active, hipStream_t s) {
-    const KmvpPlan pl = kmvp_plan(P, prec);
+// The three kernels of one product: prescale, product, partial-sum finish.
+// R: targets (rows), C: sources (columns); R == C for the square product.
+static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const KmvpPlan &pl, double shift,
+                           const void *q, void *y, const KmvpScratch &sc, const int *active, bool timed_slot,
+                           hipStream_t s) {
+    const bool square = (&R == &C);
     KArgs a;
-    a.n = P.n;
-    a.n_pad = P.n_pad;
-    a.ntiles = P.ntiles;
-    a.nrowblocks = P.ntiles;
+    a.n_rows = R.n;
+    a.n_pad_rows = R.n_pad;
+    a.nrowblocks = R.ntiles;
+    a.row_anchor = R.anchor;
+    a.n_pad = C.n_pad;
+    a.ntiles = C.ntiles;
     a.splits = pl.splits;
     a.tps = pl.tiles_per_split;
-    a.anchor = P.anchor;
-    a.tile_r2 = P.tile_r2;
-    a.tile_nj = P.tile_nj;
+    a.anchor = C.anchor;
+    a.tile_r2 = C.tile_r2;
+    a.tile_nj = C.tile_nj;
     a.q = q;
-    a.shift = shift;
+    a.qw = sc.qw;
+    a.shift = square ? shift : 0.0;
+    a.square = square ? 1 : 0;
     a.active = active;
-    a.out = pl.splits > 1 ? parts : y;
+    a.out = pl.splits > 1 ? sc.parts : y;
+    const void *w = prec == KRR_FP64 ? static_cast<const void *>(C.w64)
+                    : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
+                                       : static_cast<const void *>(C.w16);
+    const dim3 gc((C.n_pad + BLOCK - 1) / BLOCK), gr((R.n_pad + BLOCK - 1) / BLOCK);
+    switch (prec) {
+        case KRR_FP64: hipLaunchKernelGGL(k_prescale<KRR_FP64>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+        case KRR_FP32: hipLaunchKernelGGL(k_prescale<KRR_FP32>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+        default: hipLaunchKernelGGL(k_prescale<KRR_BF16>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+    }
+    KRR_HIP(hipGetLastError());
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool timed =
+        timed_slot && profile_slot(prec, static_cast<double>(R.n) * static_cast<double>(C.n), &ev0, &ev1);
+    if (timed) KRR_HIP(hipEventRecord(ev0, s));
     hipError_t e;
     switch (prec) {
         case KRR_FP64:
-            a.off = P.off64;
-            a.w = P.w64;
-            e = launch_kmvp_d<KRR_FP64>(P.dpad, a, s);
+            a.off = C.off64;
+            a.row_off = R.off64;
+            e = launch_kmvp_d<KRR_FP64>(C.dpad, a, s);
             break;
         case KRR_FP32:
-            a.off = P.off32;
-            a.w = P.w32;
-            e = launch_kmvp_d<KRR_FP32>(P.dpad, a, s);
+            a.off = C.off32;
+            a.row_off = R.off32;
+            e = launch_kmvp_d<KRR_FP32>(C.dpad, a, s);
             break;
         case KRR_BF16:
-            a.off = P.off16;
-            a.w = P.w16;
-            e = launch_kmvp_d<KRR_BF16>(P.dpad, a, s);
+            a.off = C.off16;
+            a.row_off = R.off16;
+            e = launch_kmvp_d<KRR_BF16>(C.dpad, a, s);
             break;
         default: return hipErrorInvalidValue;
     }
     KRR_HIP(e);
+    if (timed) KRR_HIP(hipEventRecord(ev1, s));
     if (pl.splits > 1) {
-        const dim3 g((P.n_pad + BLOCK - 1) / BLOCK);
+        const int sq = square ? 1 : 0;
         switch (prec) {
             case KRR_FP64:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, g, dim3(BLOCK), 0, s, P.n, P.n_pad, pl.splits, parts, q,
-                                   shift, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                                   q, shift, sq, y, active);
                 break;
             case KRR_FP32:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, g, dim3(BLOCK), 0, s, P.n, P.n_pad, pl.splits, parts, q,
-                                   shift, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                                   q, shift, sq, y, active);
                 break;
             default:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, g, dim3(BLOCK), 0, s, P.n, P.n_pad, pl.splits, parts, q,
-                                   shift, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                                   q, shift, sq, y, active);
                 break;
         }
         KRR_HIP(hipGetLastError());
     }
     return hipSuccess;
+}
+
+hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, const KmvpScratch &sc,
+                       const int *active, hipStream_t s) {
+    return kmvp_run(P, P, prec, kmvp_plan(P, prec), shift, q, y, sc, active, true, s);
+}
+
+// Rectangular product y = K_hat(targets, sources) q on sorted vectors (targets
+// order of T, sources order of S).  Both sets prepared with the same sigma.
+hipError_t kmvp_cross_sorted(const Prepared &T, const Prepared &S, int prec, const void *q, void *y,
+                             const KmvpScratch &sc, hipStream_t s) {
+    const int target_blocks = 4096;
+    int splits = (target_blocks + T.ntiles - 1) / T.ntiles;
+    const int mx = kmvp_max_splits(S);
+    if (splits > mx) splits = mx;
+    if (splits < 1) splits = 1;
+    KmvpPlan pl;
+    pl.tiles_per_split = (S.ntiles + splits - 1) / splits;
+    pl.splits = (S.ntiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
+    return kmvp_run(T, S, prec, pl, 0.0, q, y, sc, nullptr, true, s);
+}
+
+size_t kmvp_cross_scratch_bytes(const Prepared &T, const Prepared &S) {
+    return align_up(static_cast<size_t>(kmvp_max_splits(S)) * T.n_pad * 8, 256) +
+           align_up(static_cast<size_t>(S.n_pad) * 8, 256);
+}
+
+KmvpScratch carve_kmvp_cross_scratch(Carver &cv, const Prepared &T, const Prepared &S) {
+    KmvpScratch k;
+    k.parts = cv.take<double>(static_cast<size_t>(kmvp_max_splits(S)) * T.n_pad);
+    k.qw = cv.take<double>(S.n_pad);
+    return k;
+}
+
+// Time every candidate split count on this point set and keep the fastest.
+// q must be a valid input vector of the precision; y is overwritten.
+hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s) {
+    const TuneKey key{prec, P.dpad, P.ntiles};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        if (g_tuned.count(key)) return hipSuccess;
+    }
+    static const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    const double pairs = static_cast<double>(P.n_pad) * static_cast<double>(P.n_pad);
+    const int reps = pairs > 1e11 ? 1 : 3;
+    hipEvent_t e0, e1;
+    KRR_HIP(hipEventCreate(&e0));
+    KRR_HIP(hipEventCreate(&e1));
+    int best = heuristic_plan(P).splits;
+    float best_ms = 1e30f;
+    int last = -1;
+    for (int c : cands) {
+        const KmvpPlan pl = plan_for(P, c);
+        if (pl.splits == last) continue;
+        last = pl.splits;
+        hipError_t err = kmvp_run(P, P, prec, pl, 0.0, q, y, sc, nullptr, false, s);
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r)
+            err = kmvp_run(P, P, prec, pl, 0.0, q, y, sc, nullptr, false, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return err;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = pl.splits;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    tune_cache_append(key, best);
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- launch timing
+
+namespace {
+struct ProfileState {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // 2 per record
+    std::vector<int> prec;
+    std::vector<double> pairs;
+    size_t used = 0;
+    int64_t dropped = 0;
+};
+ProfileState g_prof;
+}  // namespace
+
+namespace {
+thread_local bool g_prof_suspended = false;
+}
+
+void profile_suspend(bool on) { g_prof_suspended = on; }
+
+bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop) {
+    if (!g_prof.on || g_prof_suspended) return false;
+    if (g_prof.used >= g_prof.prec.size()) {
+        ++g_prof.dropped;
+        return false;
+    }
+    const size_t k = g_prof.used++;
+    g_prof.prec[k] = prec;
+    g_prof.pairs[k] = pairs;
+    *start = g_prof.ev[2 * k];
+    *stop = g_prof.ev[2 * k + 1];
+    return true;
+}
+
+int profile_begin(int max_launches) {
+    if (max_launches < 1) return KRR_EINVAL;
+    if (g_prof.on) return KRR_EINVAL;
+    const size_t want = static_cast<size_t>(max_launches);
+    while (g_prof.ev.size() < 2 * want) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return KRR_EHIP;
+        g_prof.ev.push_back(e);
+    }
+    g_prof.prec.assign(want, 0);
+    g_prof.pairs.assign(want, 0.0);
+    g_prof.used = 0;
+    g_prof.dropped = 0;
+    g_prof.on = true;
+    return KRR_OK;
+}
+
+int profile_end(krr_profile_stats *out) {
+    if (!g_prof.on) return KRR_EINVAL;
+    g_prof.on = false;
+    krr_profile_stats st;
+    std::memset(&st, 0, sizeof(st));
+    for (size_t k = 0; k < g_prof.used; ++k) {
+        if (hipEventSynchronize(g_prof.ev[2 * k + 1]) != hipSuccess) return KRR_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[2 * k], g_prof.ev[2 * k + 1]) != hipSuccess) return KRR_EHIP;
+        krr_profile_entry &e = st.prec[g_prof.prec[k]];
+        e.launches += 1;
+        e.total_ms += ms;
+        e.pairs += g_prof.pairs[k];
+    }
+    st.dropped = g_prof.dropped;
+    if (out) *out = st;
+    return KRR_OK;
 }
 
 }  // namespace krr

@@ -1,0 +1,54 @@
+// Arguments of the matrix-core multi-RHS product (kmvp_multi.hip), shared with
+// the batched solver.
+#pragma once
+
+#include "krr_internal.h"
+
+namespace krr {
+
+struct MArgs {
+    int64_t n, n_pad;
+    int ntiles, nrowblocks, splits, tps, nrb;  // nrb: blocks of 16 right-hand sides
+    const double *anchor;
+    const double *tile_r2;
+    const double *tile_nj;
+    const void *off;
+    const void *qwt;  // Q' as [nrb][n_pad][16]
+    void *parts;      // [splits][nrb][n_pad][16]
+};
+
+// One work item of a batched product: (system, row tile, column chunk, RHS block).
+struct MItem {
+    int sys, bx, by, rbk;
+};
+
+// One system of a batched product: its product arguments, the offset of its
+// block in the concatenated vectors, its weights and its two shifts (delta for
+// the inner products, gamma for the outer ones).
+struct MSysB {
+    MArgs a;
+    int64_t base;
+    const void *w;
+    double shift_in, shift_out;
+};
+
+constexpr int BATCH_TPS = 32;  // column tiles per work item of a batched product
+
+// A batched product over the systems of one compiled dimension and one
+// precision: device arrays of systems and work items, sizes for the grids.
+struct BatchedProduct {
+    int dpad = 0, prec = 0, nsys = 0, nrhs = 0, nitems = 0;
+    MSysB *d_sys = nullptr;
+    MItem *d_items = nullptr;
+    int64_t max_elems = 0;  // max over systems of n_pad * 16 * nrb
+    int64_t max_rows = 0;   // max over systems of n_pad * nrhs
+    double pairs = 0.0;     // sum over systems of n^2
+};
+
+size_t batched_product_scratch_bytes(const Prepared &P, int nrhs);
+void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, int64_t base, double shift_in,
+               double shift_out);
+// Y = K_hat Q + shift Q for every system of bp (inner != 0: shift_in).
+hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s);
+
+}  // namespace krr

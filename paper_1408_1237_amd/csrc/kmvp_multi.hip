@@ -1,0 +1,506 @@
+// Several right-hand sides at once: Y = K_hat Q + shift Q on the matrix cores.
+//
+// Per pair the kernel value is formed once on the VALU (the folded, tile-
+// anchored exponent of krr_internal.h: d fused multiply-adds and one exp2) and
+// applied to 16 right-hand sides by one MFMA: with v_mfma_{f32,f64}_16x16x4
+// the A operand is a 16 (rows) x 4 (columns) block of K_hat, one value per lane
+// (lane l: row l % 16, column l / 16), the B operand the 4 x 16 block of the
+// prescaled sources Q'[j][r] = Q[j][r] w_j (lane l: column l / 16, right-hand
+// side l % 16), and the 16 x 16 accumulator holds the block of Y (right-hand
+// side l % 16; rows 4 (l / 16) + v for FP32, l / 16 + 4 v for FP64, v < 4).
+// A wave owns 64 rows (four 16-row blocks, four accumulators) and sweeps the
+// columns of its split 4 at a time; a block of 4 waves owns one 256-row tile.
+// Partial sums per split are added in fixed order by the finish kernel.
+#include "krr_internal.h"
+
+namespace krr {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double exp2_f64m(double a) {
+    a = fmax(a, -1100.0);
+    const double n = __builtin_rint(a);
+    const double f = a - n;
+    double p = 2.5678435993488206e-11;
+    p = __builtin_fma(p, f, 4.4455382718708116e-10);
+    p = __builtin_fma(p, f, 7.054911620801123e-09);
+    p = __builtin_fma(p, f, 1.01780860092397e-07);
+    p = __builtin_fma(p, f, 1.321548679014431e-06);
+    p = __builtin_fma(p, f, 1.5252733804059841e-05);
+    p = __builtin_fma(p, f, 0.0001540353039338161);
+    p = __builtin_fma(p, f, 0.0013333558146428443);
+    p = __builtin_fma(p, f, 0.009618129107628477);
+    p = __builtin_fma(p, f, 0.05550410866482158);
+    p = __builtin_fma(p, f, 0.24022650695910072);
+    p = __builtin_fma(p, f, 0.6931471805599453);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+}
+
+__device__ __forceinline__ int xcd_remap_m(int b, int nb) {
+    const int tall = nb / 8, extra = nb % 8;
+    const int xcd = b % 8, local = b / 8;
+    return xcd < extra ? xcd * (tall + 1) + local : extra * (tall + 1) + (xcd - extra) * tall + local;
+}
+
+template <int PREC>
+struct MP;
+template <>
+struct MP<KRR_FP64> {
+    using T = double;
+    using Off = double;
+    using Acc = doublex4;
+    static constexpr double wide = WIDE_R2_FP64;
+    static __device__ __forceinline__ T off(Off v) { return v; }
+    static __device__ __forceinline__ T ex2(T a) { return exp2_f64m(a); }
+    static __device__ __forceinline__ T fma(T a, T b, T c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ Acc mfma(T a, T b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MP<KRR_FP32> {
+    using T = float;
+    using Off = float;
+    using Acc = floatx4;
+    static constexpr double wide = WIDE_R2_FP32;
+    static __device__ __forceinline__ T off(Off v) { return v; }
+    static __device__ __forceinline__ T ex2(T a) { return __builtin_amdgcn_exp2f(a); }
+    static __device__ __forceinline__ T fma(T a, T b, T c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ Acc mfma(T a, T b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MP<KRR_BF16> : MP<KRR_FP32> {
+    using Off = uint16_t;
+    static __device__ __forceinline__ float off(Off v) { return bf16_to_f32(v); }
+};
+
+}  // namespace krr
+#include "kmvp_multi.h"
+namespace krr {
+
+// 16-row blocks processed together by one wave (register budget); a wave
+// covers its 64 rows in 4 / RB passes over the columns.
+template <int D, int PREC>
+constexpr int multi_rb() {
+    return (PREC == KRR_FP64 ? 2 : 1) * D <= 16 ? 4 : (PREC == KRR_FP64 ? 2 : 1) * D <= 32 ? 2 : 1;
+}
+
+template <int D, int PREC>
+__device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int rbk) {
+    using P = MP<PREC>;
+    using T = typename P::T;
+    using Off = typename P::Off;
+    using Acc = typename P::Acc;
+    constexpr int RB = multi_rb<D, PREC>();
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const T *__restrict__ qwt = static_cast<const T *>(a.qwt);
+    const int64_t n_pad = a.n_pad;
+    const int wave = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int r16 = lane % 16, g = lane / 16;
+    const T *qb = qwt + static_cast<int64_t>(rbk) * n_pad * 16;
+    T *parts = static_cast<T *>(a.parts) + (static_cast<int64_t>(by) * a.nrb + rbk) * n_pad * 16;
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+
+    double aI[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) aI[k] = a.anchor[static_cast<int64_t>(bx) * D + k];
+
+    for (int pass = 0; pass < 4 / RB; ++pass) {
+        const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + wave * 64 + pass * RB * 16;
+        T oi[RB][D];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int k = 0; k < D; ++k) oi[rb][k] = P::off(off[k * n_pad + row0 + rb * 16 + r16]);
+        Acc acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
+
+        for (int J = J0; J < J1; ++J) {
+            const double r2 = a.tile_r2[J];
+            const double nj = a.tile_nj[J];
+            T t[RB][D];
+            T c[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                double tt = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double td =
+                        (aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rb][k]);
+                    t[rb][k] = static_cast<T>(td);
+                    const double tk = static_cast<double>(t[rb][k]);
+                    tt = __builtin_fma(tk, tk, tt);
+                }
+                c[rb] = static_cast<T>(-tt - nj);
+            }
+            const int64_t j0 = static_cast<int64_t>(J) * TILE + g;
+            if (r2 <= P::wide) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t[rb][k] = t[rb][k] + t[rb][k];
+#pragma unroll 4
+                for (int s = 0; s < TILE; s += 4) {
+                    const int64_t j = j0 + s;
+                    T oc[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + j]);
+                    const T b = qb[j * 16 + r16];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        T arg = P::fma(t[rb][0], oc[0], c[rb]);
+#pragma unroll
+                        for (int k = 1; k < D; ++k) arg = P::fma(t[rb][k], oc[k], arg);
+                        acc[rb] = P::mfma(P::ex2(arg), b, acc[rb]);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int s = 0; s < TILE; s += 4) {
+                    const int64_t j = j0 + s;
+                    T oc[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + j]);
+                    const T b = qb[j * 16 + r16];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        T ss = T(0);
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const T dd = t[rb][k] - oc[k];
+                            ss = P::fma(dd, dd, ss);
+                        }
+                        acc[rb] = P::mfma(P::ex2(-ss), b, acc[rb]);
+                    }
+                }
+            }
+        }
+        // accumulator layout: FP32 lane l holds rows 4 (l / 16) + v; FP64 lane l
+        // holds rows l / 16 + 4 v (right-hand side l % 16 in both)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = (PREC == KRR_FP64) ? g + 4 * v : 4 * g + v;
+                parts[(row0 + rb * 16 + rr) * 16 + r16] = acc[rb][v];
+            }
+    }
+}
+
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_multi(MArgs a) {
+    const int lb = xcd_remap_m(blockIdx.x, a.nrowblocks * a.splits * a.nrb);
+    const int bx = lb % a.nrowblocks;
+    const int rest = lb / a.nrowblocks;
+    multi_body<D, PREC>(a, bx, rest % a.splits, rest / a.splits);
+}
+
+
+// Batched over many systems of one dimension: block b runs work item b
+// (system, row tile, column chunk, RHS block) with that system's arguments.
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_multi_batched(const MSysB *__restrict__ sys,
+                                                              const MItem *__restrict__ items) {
+    const MItem it = items[blockIdx.x];
+    multi_body<D, PREC>(sys[it.sys].a, it.bx, it.by, it.rbk);
+}
+
+// Q'[rbk][j][r % 16] = Q[p_j + r ldq] * weff_j for r < nrhs (0 beyond), where
+// p_j is the original index of sorted position j (perm == nullptr: p_j = j),
+// weff_j = w_j on folded tiles and 1 on wide tiles.  BF16: Q rounded first.
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void k_multi_prescale(int64_t n_pad, int nrhs, int nrb, const int32_t *perm,
+                                                          const void *Q_, int64_t ldq, const void *w_,
+                                                          const double *tile_r2, void *qwt_) {
+    using T = typename MP<PREC>::T;
+    const T *Q = static_cast<const T *>(Q_);
+    const T *w = static_cast<const T *>(w_);
+    T *qwt = static_cast<T *>(qwt_);
+    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    const int64_t total = n_pad * 16 * nrb;
+    if (idx >= total) return;
+    const int r16 = static_cast<int>(idx % 16);
+    const int64_t j = (idx / 16) % n_pad;
+    const int rbk = static_cast<int>(idx / (16 * n_pad));
+    const int r = rbk * 16 + r16;
+    const int64_t p = perm ? static_cast<int64_t>(perm[j]) : j;
+    T v = T(0);
+    if (r < nrhs && p >= 0) {
+        v = Q[p + static_cast<int64_t>(r) * ldq];
+        if (PREC == KRR_BF16) v = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(v)));
+        const bool wide = tile_r2[j / TILE] > MP<PREC>::wide;
+        v = wide ? v : v * w[j];
+    }
+    qwt[idx] = v;
+}
+
+// Y[p_i + r ldy] = sum_s parts[s][r / 16][i][r % 16] + shift Q[p_i + r ldq], i < n.
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void k_multi_finish(int64_t n, int64_t n_pad, int nrhs, int nrb, int splits,
+                                                        const int32_t *perm, const void *parts_, const void *Q_,
+                                                        int64_t ldq, double shift, void *Y_, int64_t ldy) {
+    using T = typename MP<PREC>::T;
+    const T *parts = static_cast<const T *>(parts_);
+    const T *Q = static_cast<const T *>(Q_);
+    T *Y = static_cast<T *>(Y_);
+    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    if (idx >= n_pad * nrhs) return;
+    const int64_t i = idx % n_pad;
+    const int r = static_cast<int>(idx / n_pad);
+    const int64_t p = perm ? static_cast<int64_t>(perm[i]) : (i < n ? i : -1);
+    if (p < 0) {
+        if (!perm) Y[i + static_cast<int64_t>(r) * ldy] = T(0);  // keep sorted vectors zero-padded
+        return;
+    }
+    const int rbk = r / 16, r16 = r % 16;
+    T s = T(0);
+    for (int k = 0; k < splits; ++k) s += parts[((static_cast<int64_t>(k) * nrb + rbk) * n_pad + i) * 16 + r16];
+    T qv = Q[p + static_cast<int64_t>(r) * ldq];
+    if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
+    Y[p + static_cast<int64_t>(r) * ldy] = s + static_cast<T>(shift) * qv;
+}
+
+// ---------------------------------------------------------------- batched over systems
+
+// Prescale / finish for every system of a batched product (grid.y = system).
+// Vectors are the concatenated sorted blocks: system k's column r is at
+// base_k + r n_pad_k.
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void k_multi_prescale_b(const MSysB *__restrict__ S, const void *Qall_,
+                                                            int nrhs) {
+    using T = typename MP<PREC>::T;
+    const MSysB &m = S[blockIdx.y];
+    const int64_t n_pad = m.a.n_pad;
+    const int nrb = m.a.nrb;
+    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    if (idx >= n_pad * 16 * nrb) return;
+    const T *Q = static_cast<const T *>(Qall_) + m.base;
+    const T *w = static_cast<const T *>(m.w);
+    T *qwt = static_cast<T *>(const_cast<void *>(m.a.qwt));
+    const int r16 = static_cast<int>(idx % 16);
+    const int64_t j = (idx / 16) % n_pad;
+    const int r = static_cast<int>(idx / (16 * n_pad)) * 16 + r16;
+    T v = T(0);
+    if (r < nrhs) {
+        v = Q[j + static_cast<int64_t>(r) * n_pad];
+        if (PREC == KRR_BF16) v = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(v)));
+        const bool wide = m.a.tile_r2[j / TILE] > MP<PREC>::wide;
+        v = wide ? v : v * w[j];
+    }
+    qwt[idx] = v;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void k_multi_finish_b(const MSysB *__restrict__ S, const void *Qall_, void *Yall_,
+                                                          int nrhs, int inner) {
+    using T = typename MP<PREC>::T;
+    const MSysB &m = S[blockIdx.y];
+    const int64_t n_pad = m.a.n_pad;
+    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    if (idx >= n_pad * nrhs) return;
+    const int64_t i = idx % n_pad;
+    const int r = static_cast<int>(idx / n_pad);
+    T *Y = static_cast<T *>(Yall_) + m.base;
+    if (i >= m.a.n) {
+        Y[idx] = T(0);
+        return;
+    }
+    const T *Q = static_cast<const T *>(Qall_) + m.base;
+    const T *parts = static_cast<const T *>(m.a.parts);
+    const int rbk = r / 16, r16 = r % 16;
+    T s = T(0);
+    for (int k = 0; k < m.a.splits; ++k)
+        s += parts[((static_cast<int64_t>(k) * m.a.nrb + rbk) * n_pad + i) * 16 + r16];
+    T qv = Q[idx];
+    if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
+    Y[idx] = s + static_cast<T>(inner ? m.shift_in : m.shift_out) * qv;
+}
+
+size_t batched_product_scratch_bytes(const Prepared &P, int nrhs) {
+    const int nrb = (nrhs + 15) / 16;
+    const int splits = (P.ntiles + BATCH_TPS - 1) / BATCH_TPS;
+    return align_up(static_cast<size_t>(splits) * nrb * P.n_pad * 16 * 8, 256) +
+           align_up(static_cast<size_t>(nrb) * P.n_pad * 16 * 8, 256);
+}
+
+void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, int64_t base, double shift_in,
+               double shift_out) {
+    Carver cv(scratch);
+    const int nrb = (nrhs + 15) / 16;
+    MArgs &a = m.a;
+    a.n = P.n;
+    a.n_pad = P.n_pad;
+    a.ntiles = P.ntiles;
+    a.nrowblocks = P.ntiles;
+    a.tps = P.ntiles < BATCH_TPS ? P.ntiles : BATCH_TPS;
+    a.splits = (P.ntiles + a.tps - 1) / a.tps;
+    a.nrb = nrb;
+    a.anchor = P.anchor;
+    a.tile_r2 = P.tile_r2;
+    a.tile_nj = P.tile_nj;
+    a.parts = cv.take<double>(static_cast<size_t>(a.splits) * nrb * P.n_pad * 16);
+    a.qwt = cv.take<double>(static_cast<size_t>(nrb) * P.n_pad * 16);
+    a.off = prec == KRR_FP64 ? static_cast<const void *>(P.off64)
+            : prec == KRR_FP32 ? static_cast<const void *>(P.off32)
+                               : static_cast<const void *>(P.off16);
+    m.w = prec == KRR_FP64 ? static_cast<const void *>(P.w64)
+          : prec == KRR_FP32 ? static_cast<const void *>(P.w32)
+                             : static_cast<const void *>(P.w16);
+    m.base = base;
+    m.shift_in = shift_in;
+    m.shift_out = shift_out;
+}
+
+template <int D, int PREC>
+static hipError_t launch_multi_b(const MSysB *S, const MItem *items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC>), dim3(nitems), dim3(BLOCK), 0, s, S, items);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_multi_b_d(int dpad, const MSysB *S, const MItem *items, int nitems, hipStream_t s) {
+    switch (dpad) {
+        case 1: return launch_multi_b<1, PREC>(S, items, nitems, s);
+        case 2: return launch_multi_b<2, PREC>(S, items, nitems, s);
+        case 3: return launch_multi_b<3, PREC>(S, items, nitems, s);
+        case 4: return launch_multi_b<4, PREC>(S, items, nitems, s);
+        case 6: return launch_multi_b<6, PREC>(S, items, nitems, s);
+        case 8: return launch_multi_b<8, PREC>(S, items, nitems, s);
+        case 12: return launch_multi_b<12, PREC>(S, items, nitems, s);
+        case 16: return launch_multi_b<16, PREC>(S, items, nitems, s);
+        case 24: return launch_multi_b<24, PREC>(S, items, nitems, s);
+        case 32: return launch_multi_b<32, PREC>(S, items, nitems, s);
+        case 48: return launch_multi_b<48, PREC>(S, items, nitems, s);
+        case 64: return launch_multi_b<64, PREC>(S, items, nitems, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC>
+static hipError_t batched_run(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s) {
+    const dim3 g((bp.max_elems + BLOCK - 1) / BLOCK, bp.nsys);
+    hipLaunchKernelGGL(k_multi_prescale_b<PREC>, g, dim3(BLOCK), 0, s, bp.d_sys, Qall, bp.nrhs);
+    KRR_HIP(hipGetLastError());
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool timed = profile_slot(PREC, bp.pairs * bp.nrhs, &ev0, &ev1);
+    if (timed) KRR_HIP(hipEventRecord(ev0, s));
+    KRR_HIP(launch_multi_b_d<PREC>(bp.dpad, bp.d_sys, bp.d_items, bp.nitems, s));
+    if (timed) KRR_HIP(hipEventRecord(ev1, s));
+    const dim3 gf((bp.max_rows + BLOCK - 1) / BLOCK, bp.nsys);
+    hipLaunchKernelGGL(k_multi_finish_b<PREC>, gf, dim3(BLOCK), 0, s, bp.d_sys, Qall, Yall, bp.nrhs, inner);
+    return hipGetLastError();
+}
+
+hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s) {
+    switch (bp.prec) {
+        case KRR_FP64: return batched_run<KRR_FP64>(bp, Qall, Yall, inner, s);
+        case KRR_FP32: return batched_run<KRR_FP32>(bp, Qall, Yall, inner, s);
+        case KRR_BF16: return batched_run<KRR_BF16>(bp, Qall, Yall, inner, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- host
+
+static int multi_splits(const Prepared &P, int nrb) {
+    const int target_blocks = 2048;
+    int blocks = P.ntiles * nrb;
+    int s = (target_blocks + blocks - 1) / blocks;
+    int mx = P.ntiles / 2 > 1 ? P.ntiles / 2 : 1;
+    if (mx > 16) mx = 16;
+    if (s > mx) s = mx;
+    return s < 1 ? 1 : s;
+}
+
+size_t kmvp_multi_scratch_bytes(const Prepared &P, int nrhs) {
+    const int nrb = (nrhs + 15) / 16;
+    const int mx = P.ntiles / 2 > 1 ? (P.ntiles / 2 < 16 ? P.ntiles / 2 : 16) : 1;
+    return align_up(static_cast<size_t>(mx) * nrb * P.n_pad * 16 * 8, 256) +
+           align_up(static_cast<size_t>(nrb) * P.n_pad * 16 * 8, 256);
+}
+
+template <int D, int PREC>
+static hipError_t launch_multi(const MArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_kmvp_multi<D, PREC>), dim3(a.nrowblocks * a.splits * a.nrb), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_multi_d(int dpad, const MArgs &a, hipStream_t s) {
+    switch (dpad) {
+        case 1: return launch_multi<1, PREC>(a, s);
+        case 2: return launch_multi<2, PREC>(a, s);
+        case 3: return launch_multi<3, PREC>(a, s);
+        case 4: return launch_multi<4, PREC>(a, s);
+        case 6: return launch_multi<6, PREC>(a, s);
+        case 8: return launch_multi<8, PREC>(a, s);
+        case 12: return launch_multi<12, PREC>(a, s);
+        case 16: return launch_multi<16, PREC>(a, s);
+        case 24: return launch_multi<24, PREC>(a, s);
+        case 32: return launch_multi<32, PREC>(a, s);
+        case 48: return launch_multi<48, PREC>(a, s);
+        case 64: return launch_multi<64, PREC>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC>
+static hipError_t multi_run(const Prepared &P, int nrhs, double shift, const int32_t *perm, const void *Q,
+                            int64_t ldq, void *Y, int64_t ldy, void *scratch, hipStream_t s) {
+    const int nrb = (nrhs + 15) / 16;
+    const int splits_req = multi_splits(P, nrb);
+    MArgs a;
+    a.n = P.n;
+    a.n_pad = P.n_pad;
+    a.ntiles = P.ntiles;
+    a.nrowblocks = P.ntiles;
+    a.tps = (P.ntiles + splits_req - 1) / splits_req;
+    a.splits = (P.ntiles + a.tps - 1) / a.tps;
+    a.nrb = nrb;
+    a.anchor = P.anchor;
+    a.tile_r2 = P.tile_r2;
+    a.tile_nj = P.tile_nj;
+    Carver cv(scratch);
+    const int mx = P.ntiles / 2 > 1 ? (P.ntiles / 2 < 16 ? P.ntiles / 2 : 16) : 1;
+    a.parts = cv.take<double>(static_cast<size_t>(mx) * nrb * P.n_pad * 16);
+    void *qwt = cv.take<double>(static_cast<size_t>(nrb) * P.n_pad * 16);
+    a.qwt = qwt;
+    const void *w = PREC == KRR_FP64 ? static_cast<const void *>(P.w64)
+                    : PREC == KRR_FP32 ? static_cast<const void *>(P.w32)
+                                       : static_cast<const void *>(P.w16);
+    a.off = PREC == KRR_FP64 ? static_cast<const void *>(P.off64)
+            : PREC == KRR_FP32 ? static_cast<const void *>(P.off32)
+                               : static_cast<const void *>(P.off16);
+    const int64_t tot_pre = P.n_pad * 16 * nrb;
+    hipLaunchKernelGGL(k_multi_prescale<PREC>, dim3((tot_pre + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.n_pad, nrhs,
+                       nrb, perm, Q, ldq, w, P.tile_r2, qwt);
+    KRR_HIP(hipGetLastError());
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool timed = profile_slot(PREC, static_cast<double>(P.n) * static_cast<double>(P.n) * nrhs, &ev0, &ev1);
+    if (timed) KRR_HIP(hipEventRecord(ev0, s));
+    KRR_HIP(launch_multi_d<PREC>(P.dpad, a, s));
+    if (timed) KRR_HIP(hipEventRecord(ev1, s));
+    const int64_t tot = P.n_pad * nrhs;
+    hipLaunchKernelGGL(k_multi_finish<PREC>, dim3((tot + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.n, P.n_pad, nrhs,
+                       nrb, a.splits, perm, a.parts, Q, ldq, shift, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t kmvp_multi(const Prepared &P, int prec, int nrhs, double shift, const int32_t *perm, const void *Q,
+                      int64_t ldq, void *Y, int64_t ldy, void *scratch, hipStream_t s) {
+    switch (prec) {
+        case KRR_FP64: return multi_run<KRR_FP64>(P, nrhs, shift, perm, Q, ldq, Y, ldy, scratch, s);
+        case KRR_FP32: return multi_run<KRR_FP32>(P, nrhs, shift, perm, Q, ldq, Y, ldy, scratch, s);
+        case KRR_BF16: return multi_run<KRR_BF16>(P, nrhs, shift, perm, Q, ldq, Y, ldy, scratch, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace krr

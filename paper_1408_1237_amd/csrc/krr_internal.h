@@ -100,17 +100,45 @@ template <typename Tin, typename Tout>
 hipError_t scatter_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStream_t s);
 
 // Kernel products on sorted, zero-padded vectors of length n_pad.
-// prec: KRR_FP64 (q, y double), KRR_FP32 (float), KRR_BF16 (q16: bf16 bits, y float).
+// prec: KRR_FP64 (q, y double), KRR_FP32 (float), KRR_BF16 (q: bf16 bits, y float).
 struct KmvpPlan {
     int splits = 1;          // column splits
     int tiles_per_split = 0;
 };
-KmvpPlan kmvp_plan(const Prepared &P, int prec);
-size_t kmvp_parts_bytes(const Prepared &P, int prec);  // bytes of partial sums for the plan
-// y = K_hat q + shift q on sorted vectors. parts: scratch of kmvp_parts_bytes.
-// active: optional device flag; when it reads 0 the kernels return at once.
-hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, void *parts,
+// Scratch of one product: partial sums (kmvp_max_splits x n_pad, 8 bytes each)
+// and the prescaled sources q_j w_j (n_pad, 8 bytes each).
+struct KmvpScratch {
+    void *parts = nullptr;
+    void *qw = nullptr;
+};
+int kmvp_max_splits(const Prepared &P);
+KmvpPlan kmvp_plan(const Prepared &P, int prec);  // tuned, else a heuristic
+size_t kmvp_scratch_bytes(const Prepared &P);
+KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P);
+// y = K_hat q + shift q on sorted vectors.  active: optional device flag; when it
+// reads 0 the kernels return at once.
+hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, const KmvpScratch &sc,
                        const int *active, hipStream_t s);
+// Rectangular product y = K_hat(targets T, sources S) q (sorted orders of T and S).
+hipError_t kmvp_cross_sorted(const Prepared &T, const Prepared &S, int prec, const void *q, void *y,
+                             const KmvpScratch &sc, hipStream_t s);
+size_t kmvp_cross_scratch_bytes(const Prepared &T, const Prepared &S);
+KmvpScratch carve_kmvp_cross_scratch(Carver &cv, const Prepared &T, const Prepared &S);
+// Several right-hand sides on the matrix cores: Y[p_i + r ldy] = (K_hat Q)_i,r +
+// shift Q[p_i + r ldq] with p_i = perm[i] (original order; perm == nullptr: the
+// vectors are in sorted order, zero-padded, and Y's padding is zeroed).
+// scratch: kmvp_multi_scratch_bytes(P, nrhs).
+size_t kmvp_multi_scratch_bytes(const Prepared &P, int nrhs);
+hipError_t kmvp_multi(const Prepared &P, int prec, int nrhs, double shift, const int32_t *perm, const void *Q,
+                      int64_t ldq, void *Y, int64_t ldy, void *scratch, hipStream_t s);
+// Gradient pass (grad.hip): gx (n x d, original order), g_logsigma, g_loggamma
+// (device scalars) of -lam^T (dK/dtheta) w.  scratch: grad_scratch_bytes(P).
+size_t grad_scratch_bytes(const Prepared &P);
+hipError_t kmvp_grad_run(const Prepared &P, double sigma, double gamma, const double *lam, const double *w,
+                         double *gx, double *g_ls, double *g_lg, void *scratch, hipStream_t s);
+// Autotuner: time the candidate column splits for (prec, d, N) on this point
+// set once per process (and KRR_TUNE_CACHE file) and keep the fastest.
+hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s);
 
 // Device-resident scalars of one CG solve (T = float for the inner
 // preconditioner solve, double for the plain solver).
@@ -138,6 +166,14 @@ struct FgmresScalars {
     int nonfinite;
     int pad_[2];
 };
+
+// Launch timing (krr_profile_begin / krr_profile_end): when enabled, returns
+// the event pair to record around one product kernel of `pairs` pair
+// evaluations in precision prec, or false when disabled / the pool is full.
+bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop);
+int profile_begin(int max_launches);
+void profile_suspend(bool on);  // while on, profile_slot hands out no events
+int profile_end(krr_profile_stats *out);
 
 // bf16 conversion of a float vector (round to nearest even).
 hipError_t to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s);

@@ -30,8 +30,8 @@ hipError_t red_init(const Red &R, hipStream_t s);
 template <typename T, typename TV>
 hipError_t cg_init(const CgVecs<T> &c, const TV *rhs, double tol, int maxit, const Red &R, hipStream_t s);
 template <typename T>
-hipError_t cg_step(const Prepared &P, int prec, double shift, const CgVecs<T> &c, void *parts, const Red &R,
-                   hipStream_t s);
+hipError_t cg_step(const Prepared &P, int prec, double shift, const CgVecs<T> &c, const KmvpScratch &sc,
+                   const Red &R, hipStream_t s);
 template <typename T>
 hipError_t cg_restart(const CgVecs<T> &c, const T *b, const T *Kx, const Red &R, hipStream_t s);
 
@@ -41,6 +41,7 @@ hipError_t fg_first_basis(int64_t n_pad, const double *r, double *v, const Fgmre
 hipError_t cast_f2d(int64_t n_pad, const float *z, double *Zj, hipStream_t s);
 hipError_t copy_d(int64_t n_pad, const double *a, double *b, hipStream_t s);
 hipError_t fill_d(double *p, int64_t n, double v, hipStream_t s);
+hipError_t zero_bytes(void *p, int64_t n, hipStream_t s);  // fill kernel (no memset nodes)
 hipError_t fg_orthogonalize(int gs, int64_t n_pad, int j, double *w, const double *V, double *hcol, double *hscratch,
                             FgmresScalars *F, const Red &R, hipStream_t s);
 hipError_t fg_givens(int j, int m, const double *hcol, double *H, double *cs, double *sn, double *g,

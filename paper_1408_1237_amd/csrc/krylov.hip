@@ -372,6 +372,10 @@ __global__ void k_fill_d(double *p, int64_t n, double v) {
     GRID_STRIDE(i, n) p[i] = v;
 }
 
+__global__ void k_fill_bytes(unsigned char *p, int64_t n) {
+    GRID_STRIDE(i, n) p[i] = 0;
+}
+
 // ------------------------------------------------------------------ host launchers
 
 int vec_blocks(int64_t n_pad) {
@@ -394,10 +398,10 @@ hipError_t cg_init(const CgVecs<T> &c, const TV *rhs, double tol, int maxit, con
 }
 
 template <typename T>
-hipError_t cg_step(const Prepared &P, int prec, double shift, const CgVecs<T> &c, void *parts, const Red &R,
-                   hipStream_t s) {
+hipError_t cg_step(const Prepared &P, int prec, double shift, const CgVecs<T> &c, const KmvpScratch &sc,
+                   const Red &R, hipStream_t s) {
     const void *qin = (prec == KRR_BF16) ? static_cast<const void *>(c.p16) : static_cast<const void *>(c.p);
-    KRR_HIP(kmvp_sorted(P, prec, shift, qin, c.Ap, parts, &c.S->active, s));
+    KRR_HIP(kmvp_sorted(P, prec, shift, qin, c.Ap, sc, &c.S->active, s));
     const int nb = vec_blocks(c.n_pad);
     T *part = reinterpret_cast<T *>(R.partials);
     LAUNCH(k_cg_alpha<T>, nb, c.n_pad, c.p, c.Ap, c.S, part, R.counters + 1);
@@ -419,10 +423,10 @@ template hipError_t cg_init<float, float>(const CgVecs<float> &, const float *, 
                                           hipStream_t);
 template hipError_t cg_init<double, double>(const CgVecs<double> &, const double *, double, int, const Red &,
                                             hipStream_t);
-template hipError_t cg_step<float>(const Prepared &, int, double, const CgVecs<float> &, void *, const Red &,
-                                   hipStream_t);
-template hipError_t cg_step<double>(const Prepared &, int, double, const CgVecs<double> &, void *, const Red &,
-                                    hipStream_t);
+template hipError_t cg_step<float>(const Prepared &, int, double, const CgVecs<float> &, const KmvpScratch &,
+                                   const Red &, hipStream_t);
+template hipError_t cg_step<double>(const Prepared &, int, double, const CgVecs<double> &, const KmvpScratch &,
+                                    const Red &, hipStream_t);
 template hipError_t cg_restart<double>(const CgVecs<double> &, const double *, const double *, const Red &,
                                        hipStream_t);
 
@@ -449,6 +453,11 @@ hipError_t copy_d(int64_t n_pad, const double *a, double *b, hipStream_t s) {
 
 hipError_t fill_d(double *p, int64_t n, double v, hipStream_t s) {
     LAUNCH(k_fill_d, vec_blocks(n), p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t zero_bytes(void *p, int64_t n, hipStream_t s) {
+    LAUNCH(k_fill_bytes, vec_blocks(n), static_cast<unsigned char *>(p), n);
     return hipGetLastError();
 }
 

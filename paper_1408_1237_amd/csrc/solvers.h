@@ -35,7 +35,7 @@ struct SolverWork {
     double *hcol = nullptr, *hscr = nullptr;
     float *z32 = nullptr, *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr;
     uint16_t *p16 = nullptr;
-    char *parts = nullptr;
+    KmvpScratch ksc;
     StatusBlock *status = nullptr;
     Red R;
 };
@@ -53,6 +53,15 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
                   krr_info *info, hipStream_t s);
 int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,
                 hipStream_t s);
+// Tune the product plans a solve will use (no-op when already tuned).
+hipError_t tune_products(const Prepared &P, const SolverWork &W, bool inner, int inner_prec, hipStream_t s);
+
+// Batched flexible GMRES over many systems and right-hand sides (batched.hip).
+size_t batch_workspace_bytes(const krr_points *probs, int nprob, int nrhs, int m);
+int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, const double *gamma, int nrhs,
+                   const double *const *Y, const int64_t *ldy, double *const *W, const SolverOpts &o,
+                   krr_info *infos, void *ws, size_t ws_bytes, hipStream_t s);
+
 int cg_inner_sorted(const Prepared &P, int prec, double shift, const double *v_s, double *z_s, int maxit,
                     double tol, const SolverWork &W, krr_info *info, hipStream_t s);
 

@@ -46,13 +46,26 @@ SolverWork carve_solver(Carver &cv, const Prepared &P, const SolverOpts &o, bool
         W.p16 = cv.take<uint16_t>(np);
         W.z64 = cv.take<double>(np);
     }
-    size_t parts = kmvp_parts_bytes(P, KRR_FP64);
-    W.parts = cv.take<char>(parts > 0 ? parts : 256);
+    W.ksc = carve_kmvp_scratch(cv, P);
     W.status = cv.take<StatusBlock>(1);
     const int nv = (m + 1) > 2 ? (m + 1) : 2;
     W.R.partials = cv.take<double>(Red::partial_count(nv));
     W.R.counters = cv.take<unsigned>(Red::NCOUNTERS);
     return W;
+}
+
+hipError_t tune_products(const Prepared &P, const SolverWork &W, bool inner, int inner_prec, hipStream_t s) {
+    KRR_HIP(kmvp_tune(P, KRR_FP64, W.b, W.w, W.ksc, s));
+    if (inner && inner_prec == KRR_FP64) return hipSuccess;
+    if (inner && inner_prec == KRR_FP32) {
+        KRR_HIP(zero_bytes(W.p32, P.n_pad * 4, s));
+        return kmvp_tune(P, KRR_FP32, W.p32, W.Ap32, W.ksc, s);
+    }
+    if (inner && inner_prec == KRR_BF16) {
+        KRR_HIP(zero_bytes(W.p16, P.n_pad * 2, s));
+        return kmvp_tune(P, KRR_BF16, W.p16, W.Ap32, W.ksc, s);
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- inner CG
@@ -90,18 +103,19 @@ static hipError_t inner_solve(const Prepared &P, int prec, double shift, const d
     if (prec == KRR_FP64) {
         CgVecs<double> c = inner_vecs<double>(W, P.n_pad, prec);
         KRR_HIP((cg_init<double, double>(c, v, tol, maxit, W.R, s)));
-        for (int it = 0; it < maxit; ++it) KRR_HIP(cg_step<double>(P, prec, shift, c, W.parts, W.R, s));
+        for (int it = 0; it < maxit; ++it) KRR_HIP(cg_step<double>(P, prec, shift, c, W.ksc, W.R, s));
         return copy_d(P.n_pad, c.x, out, s);
     }
     CgVecs<float> c = inner_vecs<float>(W, P.n_pad, prec);
     KRR_HIP((cg_init<float, double>(c, v, tol, maxit, W.R, s)));
-    for (int it = 0; it < maxit; ++it) KRR_HIP(cg_step<float>(P, prec, shift, c, W.parts, W.R, s));
+    for (int it = 0; it < maxit; ++it) KRR_HIP(cg_step<float>(P, prec, shift, c, W.ksc, W.R, s));
     return cast_f2d(P.n_pad, c.x, out, s);
 }
 
 int cg_inner_sorted(const Prepared &P, int prec, double shift, const double *v_s, double *z_s, int maxit,
                     double tol, const SolverWork &W, krr_info *info, hipStream_t s) {
     KRR_HIP_STATUS(red_init(W.R, s));
+    KRR_HIP_STATUS(tune_products(P, W, true, prec, s));
     KRR_HIP_STATUS(inner_solve(P, prec, shift, v_s, z_s, maxit, tol, W, s));
     if (info) {
         StatusBlock st;
@@ -132,9 +146,10 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
     int result = KRR_NOT_CONVERGED;
 
     KRR_HIP_STATUS(red_init(W.R, s));
+    KRR_HIP_STATUS(tune_products(P, W, o.inner != KRR_INNER_NONE, o.inner_prec, s));
     // r0 = b - K x0 (section 4.2, first line of the algorithm); r0 lives in W.w
     if (!x0_zero) {
-        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.w, W.parts, nullptr, s));
+        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.w, W.ksc, nullptr, s));
         ++mvp64;
     }
     KRR_HIP_STATUS(fg_residual(np, W.b, x0_zero ? nullptr : W.w, W.w, F, W.g, W.R, s));
@@ -166,7 +181,7 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
                 KRR_HIP_STATUS(inner_solve(P, o.inner_prec, o.delta, Vj, Zj, o.inner_maxit, o.inner_tol, W, s));
             }
             // w = K z_j
-            KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, Zj, W.w, W.parts, nullptr, s));
+            KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, Zj, W.w, W.ksc, nullptr, s));
             ++mvp64;
             KRR_HIP_STATUS(fg_orthogonalize(o.gs, np, j, W.w, W.V, W.hcol, W.hscr, F, W.R, s));
             KRR_HIP_STATUS(fg_givens(j, m, W.hcol, W.H, W.cs, W.sn, W.g, F, s));
@@ -191,7 +206,7 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
         if (k > 0) KRR_HIP_STATUS(fg_update_x(np, k, m, W.H, W.g, W.y, W.Z, W.x, s));
         ++cycles;
         // true residual; also the next cycle's r0
-        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.w, W.parts, nullptr, s));
+        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.w, W.ksc, nullptr, s));
         ++mvp64;
         KRR_HIP_STATUS(fg_residual(np, W.b, W.w, W.w, F, W.g, W.R, s));
         KRR_HIP_STATUS(read_status(W.status, st, s));
@@ -234,6 +249,7 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
     const int check = o.cg_check > 0 ? o.cg_check : 16;
 
     KRR_HIP_STATUS(red_init(W.R, s));
+    KRR_HIP_STATUS(tune_products(P, W, false, KRR_FP64, s));
     KRR_HIP_STATUS((cg_init<double, double>(c, W.b, o.tol, o.max_outer, W.R, s)));
     KRR_HIP_STATUS(read_status(W.status, st, s));
     if (st.c64.status == KRR_ENONFINITE) return KRR_ENONFINITE;
@@ -243,7 +259,7 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
     }
     int last_iters = 0;
     while (result == KRR_NOT_CONVERGED) {
-        for (int k = 0; k < check; ++k) KRR_HIP_STATUS(cg_step<double>(P, KRR_FP64, gamma, c, W.parts, W.R, s));
+        for (int k = 0; k < check; ++k) KRR_HIP_STATUS(cg_step<double>(P, KRR_FP64, gamma, c, W.ksc, W.R, s));
         KRR_HIP_STATUS(read_status(W.status, st, s));
         mvp64 += st.c64.iters - last_iters;
         last_iters = st.c64.iters;
@@ -253,7 +269,7 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
         }
         if (st.c64.candidate || st.c64.active == 0) {
             // confirm with the true residual b - K x; restart from it if needed
-            KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, c.x, W.Ap64, W.parts, nullptr, s));
+            KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, c.x, W.Ap64, W.ksc, nullptr, s));
             ++mvp64;
             KRR_HIP_STATUS(cg_restart<double>(c, W.b, W.Ap64, W.R, s));
             KRR_HIP_STATUS(read_status(W.status, st, s));

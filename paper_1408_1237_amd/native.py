@@ -26,7 +26,7 @@ KRR_MAX_DIM = 64
 
 EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
-            "krr_solve")
+            "krr_solve", "krr_profile_begin", "krr_profile_end")
 
 
 class Points(ctypes.Structure):
@@ -38,6 +38,14 @@ class Opts(ctypes.Structure):
                 ("inner", ctypes.c_int32), ("inner_prec", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("gs", ctypes.c_int32),
                 ("cg_check", ctypes.c_int32)]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("pairs", ctypes.c_double)]
+
+
+class ProfileStats(ctypes.Structure):
+    _fields_ = [("prec", ProfileEntry * 3), ("dropped", ctypes.c_int64)]
 
 
 class Info(ctypes.Structure):
@@ -86,6 +94,10 @@ def load(path: str | None = None):
         lib.fgmres_solve.argtypes = [_P(Points), _dbl, _dbl, _vp, _vp, _P(Opts), _P(Info), _vp, _sz, _vp]
         lib.krr_solve.argtypes = [_P(Points), _i32, _P(_dbl), _P(_dbl), _i32, _P(_vp), _P(_i64), _P(_vp), _i32,
                                   _P(Opts), _P(Info), _vp, _sz, _vp]
+        lib.krr_profile_begin.argtypes = [_i32]
+        lib.krr_profile_begin.restype = ctypes.c_int
+        lib.krr_profile_end.argtypes = [_P(ProfileStats)]
+        lib.krr_profile_end.restype = ctypes.c_int
         for name in ("kmvp_gauss", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
                      "fgmres_solve", "krr_solve"):
             getattr(lib, name).restype = ctypes.c_int
@@ -121,3 +133,24 @@ def check(code: int, where: str, ok_positive: bool = True) -> int:
     if code < 0 or (code > 0 and not ok_positive):
         raise KrrError(code, where)
     return code
+
+
+class profile:
+    """Context manager timing every kernel-product launch (HIP events) made inside it."""
+
+    def __init__(self, max_launches: int = 65536):
+        self.max_launches = max_launches
+        self.stats = None
+
+    def __enter__(self):
+        check(load().krr_profile_begin(self.max_launches), "krr_profile_begin")
+        return self
+
+    def __exit__(self, *exc):
+        st = ProfileStats()
+        check(load().krr_profile_end(ctypes.byref(st)), "krr_profile_end")
+        names = ("fp64", "fp32", "bf16")
+        self.stats = {names[k]: dict(launches=st.prec[k].launches, total_ms=st.prec[k].total_ms,
+                                     pairs=st.prec[k].pairs) for k in range(3)}
+        self.stats["dropped"] = st.dropped
+        return False

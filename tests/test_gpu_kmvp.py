@@ -116,3 +116,63 @@ def test_kmvp_clustered_large_bf16_sampled_rows():
     rows = np.random.default_rng(13).choice(p.n, 16, replace=False)
     want = oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.delta)
     assert _relerr(y[rows], want) <= TOL["bf16"]
+
+
+def _gpu_cross(xt, xs, sigma, q, prec):
+    api = _api()
+    y = api.kmvp_gauss_cross(torch.from_numpy(xt).cuda(), torch.from_numpy(xs).cuda(), sigma,
+                             torch.from_numpy(q).to(DT[prec]).cuda(), prec=prec)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("nt,ns", [(1, 1), (1, 300), (300, 1), (257, 1000), (1000, 257), (3000, 2000)])
+def test_kmvp_cross(prec, nt, ns):
+    # prediction at new points: y = K_hat(targets, sources) q (eq. GPR_mean, eq. Kriging)
+    xs = workloads.random_points(500 + ns, ns, 3, 2.0)
+    xt = workloads.random_points(600 + nt, nt, 3, 2.0)
+    q = workloads.random_vector(700 + ns, ns)
+    y = _gpu_cross(xt, xs, 0.5, q, prec)
+    want = oracle.mvp(xt, 0.5, q, xs=xs)
+    assert y.shape == (nt,)
+    assert _relerr(y, want) <= TOL[prec]
+
+
+def test_kmvp_cross_equals_square_on_same_points():
+    x = workloads.random_points(21, 1500, 2, 1.0)
+    q = workloads.random_vector(22, 1500)
+    a = _gpu_cross(x, x, 0.1, q, "fp64")
+    b = _gpu_mvp(x, 0.1, q, 0.0, "fp64")
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+
+
+def test_kmvp_cross_shard_shape_clustered():
+    # one shard of a row-sharded product over 8 GPUs at the clustered 1e6 shape:
+    # 125,000 target rows x 1,000,000 sources, BF16 inputs, checked on 16 rows
+    p = workloads.clustered_large()
+    q = workloads.random_vector(7, p.n)
+    xt = np.ascontiguousarray(p.x[:125_000])
+    y = _gpu_cross(xt, p.x, p.sigma, q, "bf16")
+    rows = np.random.default_rng(14).choice(xt.shape[0], 16, replace=False)
+    want = oracle.mvp(xt[rows], p.sigma, q, xs=p.x)
+    assert _relerr(y[rows], want) <= TOL["bf16"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8, 16])
+def test_matrix_core_exponent_matches_valu_kernel(monkeypatch, prec, d):
+    # the FP32 / BF16 products use the matrix-core exponent kernel for d <= 16;
+    # KRR_KMVP_VALU=1 selects the VALU kernel; both must meet the oracle bar and
+    # agree with each other to FP32 rounding
+    n = 1500
+    x = workloads.random_points(70 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(71 + d, n)
+    sigma = 0.6 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _gpu_mvp(x, sigma, q, 0.05, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _gpu_mvp(x, sigma, q, 0.05, prec)
+    want = oracle.mvp(x, sigma, q, shift=0.05)
+    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    assert _relerr(a, b) <= 1e-5

@@ -1,0 +1,107 @@
+"""Parity of the matrix-core multi-RHS product with the FP64 oracle (GPU).
+
+Y = K_hat Q + shift Q for column-major Q (n x nrhs).  Bars as for the single
+product: FP64 1e-12, FP32 1e-5, BF16 inputs 1e-2, norm-wise per column.  For
+BF16 the reference is the exact product of the BF16-rounded Q (rounded by
+torch): with smooth kernels the rounding of Q alone moves K_hat Q by more than
+1e-2, which measures the input format, not the kernel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_1237_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}
+DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
+
+
+def _gpu_multi(x, sigma, Q, shift, prec):
+    from paper_1408_1237_amd import api
+    Qt = torch.from_numpy(np.ascontiguousarray(Q.T)).to(DT[prec]).cuda().t()
+    Y = api.kmvp_gauss_multi(torch.from_numpy(x).cuda(), sigma, Qt, shift=shift, prec=prec)
+    torch.cuda.synchronize()
+    return Y.double().cpu().numpy()
+
+
+def _ref(x, sigma, Q, shift, prec):
+    if prec == "bf16":
+        Q = torch.from_numpy(np.ascontiguousarray(Q)).to(torch.bfloat16).double().numpy()
+    return oracle.mvp_multi(x, sigma, Q, shift=shift)
+
+
+def _colerr(Y, W):
+    return max(np.linalg.norm(Y[:, r] - W[:, r]) / max(np.linalg.norm(W[:, r]), 1e-300) for r in range(W.shape[1]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (5, 16), (300, 3), (1000, 16), (1000, 17), (2049, 33)])
+def test_multi_sizes(prec, n, nrhs):
+    x = workloads.random_points(800 + n, n, 3, 2.0)
+    Q = workloads.random_vector(900 + n, n, nrhs)
+    Y = _gpu_multi(x, 0.6, Q, 0.05, prec)
+    W = _ref(x, 0.6, Q, 0.05, prec)
+    assert Y.shape == (n, nrhs)
+    assert _colerr(Y, W) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 4, 8, 16, 24, 40])
+def test_multi_dims(prec, d):
+    n = 600
+    x = workloads.random_points(1000 + d, n, d, 1.0, kind="normal")
+    sigma = np.sqrt(d)
+    Q = workloads.random_vector(1100 + d, n, 16)
+    Y = _gpu_multi(x, sigma, Q, 0.01, prec)
+    W = _ref(x, sigma, Q, 0.01, prec)
+    assert _colerr(Y, W) <= TOL[prec]
+
+
+def test_multi_far_points_identity():
+    # every tile wide: the direct path; K_hat = I
+    n = 700
+    x = np.zeros((n, 2))
+    x[:, 1] = np.arange(n) * 500.0
+    Q = workloads.random_vector(12, n, 16)
+    for prec in ("fp64", "fp32"):
+        Y = _gpu_multi(x, 1.0, Q, 0.5, prec)
+        assert _colerr(Y, 1.5 * Q) <= TOL[prec]
+
+
+def test_multi_matches_single_products():
+    from paper_1408_1237_amd import api
+    x = workloads.random_points(13, 3000, 4, 1.0, kind="normal")
+    Q = workloads.random_vector(14, 3000, 16)
+    Y = _gpu_multi(x, 2.0, Q, 0.1, "fp64")
+    xt = torch.from_numpy(x).cuda()
+    for r in (0, 7, 15):
+        y = api.kmvp_gauss(xt, 2.0, torch.from_numpy(np.ascontiguousarray(Q[:, r])).cuda(), shift=0.1, prec="fp64")
+        assert np.allclose(Y[:, r], y.cpu().numpy(), rtol=1e-12, atol=1e-12 * np.abs(y.cpu().numpy()).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_batched_shape_sampled_rows(prec):
+    # the largest batched system shape: N = 50,000, d = 8, 16 right-hand sides, sampled rows
+    rng = np.random.default_rng(15)
+    n = 50_000
+    x = np.ascontiguousarray(rng.standard_normal((n, 8)))
+    Q = np.asfortranarray(rng.standard_normal((n, 16)))
+    Y = _gpu_multi(x, np.sqrt(8.0), Q, 0.1, prec)
+    rows = rng.choice(n, 24, replace=False)
+    for r in (0, 9, 15):
+        want = oracle.mvp_rows(x, np.sqrt(8.0), np.ascontiguousarray(Q[:, r]), rows, shift=0.1)
+        assert np.linalg.norm(Y[rows, r] - want) / np.linalg.norm(want) <= TOL[prec]
+
+
+def test_multi_gp_regression_shape_sampled_rows():
+    # d = 16 at the GP-regression shape (N = 2e5), 16 right-hand sides, FP32, sampled rows
+    p = workloads.gp_regression()
+    Q = workloads.random_vector(16, p.n, 16)
+    Y = _gpu_multi(p.x, p.sigma, Q, 0.0, "fp32")
+    rows = np.random.default_rng(17).choice(p.n, 8, replace=False)
+    for r in (0, 15):
+        want = oracle.mvp_rows(p.x, p.sigma, np.ascontiguousarray(Q[:, r]), rows)
+        assert np.linalg.norm(Y[rows, r] - want) / np.linalg.norm(want) <= TOL["fp32"]

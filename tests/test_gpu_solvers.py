@@ -163,3 +163,74 @@ def test_krr_solve_several_systems_and_columns():
         Wn = W.cpu().numpy()
         for r in range(2):
             assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], Wn[:, r]) <= 1e-6
+
+
+def _fcol(a):
+    return torch.from_numpy(np.asfortranarray(a)).cuda()
+
+
+@pytest.mark.parametrize("inner_prec", ["fp32", "bf16"])
+def test_batched_mixed_dims_against_oracle(inner_prec):
+    # systems of different size and dimension advance together; every column
+    # must reach the true FP64 residual on its own
+    api = _api()
+    rng = np.random.default_rng(60)
+    shapes = [(700, 2), (300, 5), (1500, 3), (257, 8)]
+    xs = [np.ascontiguousarray(rng.uniform(0, 3, (n, d))) for n, d in shapes]
+    ys = [np.asfortranarray(rng.standard_normal((n, 3))) for n, _ in shapes]
+    sig = [0.4, 1.0, 0.3, 1.5]
+    gam = [1e-2, 1e-3, 1e-2, 1e-1]
+    Ws, infos = api.krr_solve([_t(x) for x in xs], sig, gam, [_fcol(y) for y in ys], mode="fgmres",
+                              inner_prec=inner_prec, restart_m=60, max_outer=2000)
+    assert len(infos) == 12 and all(i["status"] == 0 for i in infos), infos
+    for x, y, s, g, W in zip(xs, ys, sig, gam, Ws):
+        Wn = W.cpu().numpy()
+        for r in range(3):
+            assert oracle.true_relres(x, s, g, y[:, r], Wn[:, r]) <= 1e-6
+
+
+def test_batched_matches_single_solves_and_zero_column():
+    api = _api()
+    probs = workloads.batched(nsys=2, nmin=600, nmax=1200, nrhs=3)
+    probs[1].y[:, 1] = 0.0  # a zero right-hand side: w = 0 at once
+    Ws, infos = api.krr_solve([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+                              [_fcol(p.y) for p in probs], mode="fgmres")
+    assert all(i["status"] == 0 for i in infos)
+    assert np.all(Ws[1].cpu().numpy()[:, 1] == 0.0)
+    for p, W in zip(probs, Ws):
+        for r in range(3):
+            if not np.any(p.y[:, r]):
+                continue
+            w1, i1 = api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y[:, r]))
+            a, b = W.cpu().numpy()[:, r], w1.cpu().numpy()
+            # both solve to 1e-6; they agree to within the conditioning of K
+            assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-3
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], a) <= 1e-6
+
+
+def test_batched_gmres_mode():
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=300, nmax=800, nrhs=2)
+    Ws, infos = api.krr_solve([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+                              [_fcol(p.y) for p in probs], mode="gmres", restart_m=100, max_outer=3000)
+    assert all(i["status"] == 0 for i in infos)
+    for p, W in zip(probs, Ws):
+        for r in range(2):
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], W.cpu().numpy()[:, r]) <= 1e-6
+
+
+def test_batched_graph_replays_match_eager(monkeypatch):
+    # the inner CG of the batched solver is a recorded HIP graph replayed at every
+    # outer step, with eager kernels and host synchronisations between replays;
+    # the arithmetic is deterministic, so the graph and eager runs agree bitwise
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=400, nmax=900, nrhs=2)
+    args = ([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+            [_fcol(p.y) for p in probs])
+    monkeypatch.setenv("KRR_NO_GRAPH", "0")
+    Wg, ig = api.krr_solve(*args, mode="fgmres")
+    monkeypatch.setenv("KRR_NO_GRAPH", "1")
+    We, ie = api.krr_solve(*args, mode="fgmres")
+    assert ig[0]["outer_iters"] == ie[0]["outer_iters"] and ig[0]["outer_iters"] > 1
+    for a, b in zip(Wg, We):
+        assert torch.equal(a, b)
