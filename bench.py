@@ -39,21 +39,32 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 MFMA_F32_MACS = 157.3e12 / 2
 
 
-def product_peak(d: int) -> tuple[float, str, str]:
-    """Peak pairs/s of the FP32 product kernel that runs for dimension d.
+def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
+    """Peak pairs/s of the FP32 / BF16-input product kernel that runs for dimension d.
 
     d <= 16 (matrix-core exponent): per pair one exp2 and one FMA on the VALU and
     4 ceil((d+1)/4) FP32 MACs on the matrix cores; the smaller of the two rates.
     Otherwise (VALU kernel): d + 2 VALU issue slots per pair.
     """
+    tag = "BF16" if prec == "bf16" else "FP32"
     if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
         dk = (d + 4) // 4
         valu = VALU_LANE_OPS / 2
         mfma = MFMA_F32_MACS / (4 * dk)
         rule = ("min(256 CU x 64 lanes x 2.4 GHz / 2 VALU ops per pair, "
                 f"157.3 TFLOP/s / (2 x {4 * dk} MACs per pair))")
-        return min(valu, mfma), rule, f"k_kmvp_mg<{d}, FP32>"
-    return VALU_LANE_OPS / (d + 2), "256 CU x 64 lanes x 2.4 GHz / (d + 2) VALU slots per pair", f"k_kmvp<{d}, FP32>"
+        return min(valu, mfma), rule, f"k_kmvp_mg<{d}, {tag}>"
+    return VALU_LANE_OPS / (d + 2), "256 CU x 64 lanes x 2.4 GHz / (d + 2) VALU slots per pair", f"k_kmvp<{d}, {tag}>"
+
+
+def multi_peak(d: int) -> tuple[float, str, str]:
+    """Peak pair x RHS products/s of the FP32 16-RHS product: 16 MACs per pair on
+    the matrix cores (157.3 TFLOP/s), the kernel value on the VALU (d + 2 slots per
+    pair, shared by the 16 RHS); the smaller of the two."""
+    mfma = MFMA_F32_MACS  # one MAC per pair x RHS
+    valu = VALU_LANE_OPS / (d + 2) * 16
+    rule = "min(157.3 TFLOP/s / 2 FLOP per pair x RHS, 256 CU x 64 lanes x 2.4 GHz / (d + 2) slots x 16 RHS)"
+    return min(mfma, valu), rule, f"k_kmvp_multi<{d}, FP32>"
 
 
 
@@ -134,6 +145,158 @@ def kernel_only(api, native, workloads, torch, p, x, reps: int) -> int:
     return 0
 
 
+def product_rates(api, native, torch, x, sigma, shift, n, reps, precs=("fp64", "fp32", "bf16")) -> dict:
+    """Average product-kernel launch time and pair rate per precision (HIP events)."""
+    out = {}
+    for prec in precs:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        q = torch.randn(n, dtype=torch.float64, device=x.device, generator=None).to(dt)
+        api.kmvp_gauss(x, sigma, q, shift=shift, prec=prec)  # tunes the plan
+        torch.cuda.synchronize()
+        with native.profile() as prof:
+            for _ in range(reps):
+                api.kmvp_gauss(x, sigma, q, shift=shift, prec=prec)
+            torch.cuda.synchronize()
+        st = prof.stats[prec]
+        out[prec] = {"gpair_s": round(st["pairs"] / (st["total_ms"] * 1e-3) / 1e9, 1),
+                     "avg_launch_ms": round(st["total_ms"] / max(st["launches"], 1), 4), "launches": st["launches"]}
+    return out
+
+
+def workload_clustered(args, api, native, workloads, torch) -> dict:
+    """N = 1e6, d = 2 clustered points, BF16-input inner products: product rates
+    per precision and a bounded number of outer steps (the full solve and plain
+    FP64 CG take far longer than a benchmark run; the residual reached is reported)."""
+    p = workloads.clustered_large()
+    x = torch.from_numpy(p.x).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    torch.manual_seed(7)
+    rates = product_rates(api, native, torch, x, p.sigma, p.delta, p.n, 3)
+    log(f"clustered products: {rates}")
+    budget = args.max_outer or 8
+    opts = dict(inner_prec="bf16", inner_maxit=p.inner_maxit, inner_tol=p.inner_tol, delta=p.delta, restart_m=100,
+                tol=p.tol, max_outer=budget, gs="cgs2")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, **opts)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    log(f"fgmres bf16 inner, {info['outer_iters']} outer steps: relres {info['relres_true']:.3e}, {tf:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol,
+                                 max_outer=budget * (p.inner_maxit + 1), cg_check=16)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    log(f"cg64 at the same product budget, {ic['outer_iters']} iterations: relres {ic['relres_true']:.3e}, {tc:.2f} s")
+    peak_pairs, peak_rule, kname = product_peak(p.d, prec="bf16")
+    ach = rates["bf16"]["gpair_s"]
+    return {"metric": METRIC, "value": ach * 1e9, "unit": "pairs/s", "n_gpus": 1, "dtype": "bf16-input/f32",
+            "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
+            "config": {"workload": "clustered N=1e6 d=2 50-component mixture sigma=1 gamma=1e-4; BF16-input inner "
+                                   "products (10 its, tol 1e-5) on K_hat+1e-3 I", "n": p.n, "d": p.d},
+            "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak_pairs / 1e9, 1), "unit": "Gpair/s",
+                         "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None, "kernel": kname,
+                         "peak_rule": peak_rule},
+            "products": rates,
+            "fgmres_bounded": {"outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
+                               "relres_true": info["relres_true"], "time_s": tf,
+                               "s_per_outer_step": tf / max(info["outer_iters"], 1)},
+            "cg64_same_budget": {"iters": ic["outer_iters"], "relres_true": ic["relres_true"], "time_s": tc}}
+
+
+def workload_batched(args, api, native, workloads, torch) -> dict:
+    """64 systems (N_k ~ U{1000..50000}, d in {4, 8}) x 16 right-hand sides, one
+    batched FGMRES solve; the multi-RHS kernel rate on the largest system."""
+    import numpy as np
+
+    probs = workloads.batched()
+    xs = [torch.from_numpy(q.x).cuda() for q in probs]
+    Ys = [torch.from_numpy(np.asfortranarray(q.y)).cuda() for q in probs]
+    opts = dict(inner_prec="fp32", inner_maxit=10, inner_tol=0.0, restart_m=30, max_outer=args.max_outer or 3000)
+    torch.cuda.synchronize()
+    with native.profile(max_launches=200_000) as prof:
+        t0 = time.perf_counter()
+        Ws, infos = api.krr_solve(xs, [q.sigma for q in probs], [q.gamma for q in probs], Ys, mode="fgmres", **opts)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+    worst = max(i["relres_true"] for i in infos)
+    outer = infos[0]["outer_iters"]
+    log(f"batched: {len(infos)} columns, {outer} outer steps, worst relres {worst:.3e}, {tb:.2f} s")
+    big = max(range(len(probs)), key=lambda k: probs[k].n)
+    q = probs[big]
+    rates = {}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Q = torch.randn(16, q.n, dtype=torch.float64, device="cuda").to(dt).t()
+        api.kmvp_gauss_multi(xs[big], q.sigma, Q, shift=q.gamma, prec=prec)
+        torch.cuda.synchronize()
+        with native.profile() as pr:
+            for _ in range(5):
+                api.kmvp_gauss_multi(xs[big], q.sigma, Q, shift=q.gamma, prec=prec)
+            torch.cuda.synchronize()
+        st = pr.stats[prec]
+        rates[prec] = {"gpair_rhs_s": round(st["pairs"] / (st["total_ms"] * 1e-3) / 1e9, 1),
+                       "avg_launch_ms": round(st["total_ms"] / max(st["launches"], 1), 4)}
+    log(f"multi-RHS products on the largest system (n={q.n}, d={q.d}): {rates}")
+    peak_pairs, peak_rule, kname = multi_peak(q.d)
+    ach = rates["fp32"]["gpair_rhs_s"]
+    return {"metric": METRIC, "value": tb, "unit": "s (time to 1e-6 on all 1024 columns)", "n_gpus": 1,
+            "dtype": "f32+f64", "data": "synthetic", "higher_is_better": False, "vs_baseline": None,
+            "config": {"workload": "batched 64 systems N_k~U{1000..50000} d in {4,8} x 16 RHS; FGMRES(30), 10 FP32 "
+                                   "inner CG on K_hat+0.1 I, tol 1e-6 per column"},
+            "time_to_solution_s": tb, "outer_iters": outer, "worst_relres_true": worst,
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": round(peak_pairs / 1e9, 1),
+                         "unit": "Gpair-RHS/s", "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None,
+                         "kernel": kname, "peak_rule": peak_rule},
+            "multi_products_largest_system": rates}
+
+
+def workload_gp(args, api, native, workloads, torch) -> dict:
+    """N = 2e5, d = 16: forward solve, then the gradient pass of y^T K^-1 y
+    (lambda = w)."""
+    p = workloads.gp_regression()
+    x = torch.from_numpy(p.x).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, inner_prec="fp32", inner_maxit=p.inner_maxit,
+                               inner_tol=p.inner_tol, delta=p.delta, restart_m=100, gs="cgs2",
+                               max_outer=args.max_outer or 3000)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    log(f"gp forward solve: {info['outer_iters']} outer, relres {info['relres_true']:.3e}, {ts:.2f} s")
+    d = p.d
+    times = {}
+    for prec in ("fp64", "fp32"):
+        api.kmvp_grad(x, p.sigma, p.gamma, w, w, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            api.kmvp_grad(x, p.sigma, p.gamma, w, w, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        times[prec] = e0.elapsed_time(e1) / reps
+    rate = float(p.n) ** 2 / (times["fp64"] * 1e-3)
+    # FP64 pair loop: 3d + 3 slots plus the exp2_f64 sequence (clamp, rint, subtract,
+    # 10 FMAs, convert, ldexp: 15); FP32: 3d + 3
+    peak = VALU_LANE_OPS / (3 * d + 18)
+    log(f"gradient pass: fp64 {times['fp64']:.2f} ms ({rate / 1e9:.1f} Gpair/s), fp32 {times['fp32']:.2f} ms")
+    return {"metric": METRIC, "value": rate, "unit": "pairs/s", "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
+            "config": {"workload": "gp_regression N=2e5 d=16 sigma=4 gamma=1e-2: gradient of y^T K^-1 y", "n": p.n,
+                       "d": d},
+            "forward_solve": {"time_s": ts, "outer_iters": info["outer_iters"], "relres_true": info["relres_true"]},
+            "gradient_pass_ms": times,
+            "roofline": {"bound": "alu", "achieved": round(rate / 1e9, 1), "peak": round(peak / 1e9, 1),
+                         "unit": "Gpair/s", "frac": round(rate / peak, 4), "traffic": None,
+                         "kernel": f"k_grad<{d}, true, double>",
+                         "peak_rule": "256 CU x 64 lanes x 2.4 GHz / (3d + 18) FP64 VALU slots per pair "
+                                      "(time includes prep and the epilogue kernels)"}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +305,11 @@ def main() -> int:
     ap.add_argument("--no-cg", action="store_true", help="skip the FP64 CG comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
+    ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp"),
+                    help="kriging (default, the headline line); the others print their own line")
+    ap.add_argument("--max-outer", type=int, default=0,
+                    help="outer-step budget of the secondary workloads (clustered: default 8; others: "
+                         "default to convergence)")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
                     help="only K FP32 products on the workload's points plus one 256 MiB copy "
                          "(the short run used for rocprofv3 counter passes)")
@@ -159,6 +327,11 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     native.load()
+    others = {"clustered": workload_clustered, "batched": workload_batched, "gp": workload_gp}
+    if args.workload in others:
+        out = others[args.workload](args, api, native, workloads, torch)
+        print(json.dumps(out), flush=True)
+        return 0
     p = workloads.kriging(n=args.n)
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()

@@ -174,10 +174,13 @@ int kmvp_gauss_cross(const krr_points *targets /* host */, const krr_points *sou
  *   *g_loggamma   = -gamma lam^T w
  * gx is n x d row-major double (device); g_logsigma and g_loggamma are single
  * doubles in device memory.  lam may equal w (the case l = y^T K^{-1} y).
- * Products run in FP32 on the matrix cores; the reduction and epilogue in FP64. */
-int kmvp_grad(const krr_points *pts /* host */, double sigma, double gamma, const double *lam,
-              const double *w, double *gx, double *g_logsigma, double *g_loggamma,
-              void *ws, size_t ws_bytes, krr_stream_t stream);
+ * prec: KRR_FP64 (kernel values, differences and sums in FP64) or KRR_FP32
+ * (FP32 pair loop, FP64 epilogue); other values give KRR_EINVAL.  At the
+ * solution of an ill-conditioned system the row sums cancel heavily, so the
+ * FP32 pass loses accuracy well beyond FP32 rounding. */
+int kmvp_grad(const krr_points *pts /* host */, double sigma, double gamma, int32_t prec,
+              const double *lam, const double *w, double *gx, double *g_logsigma,
+              double *g_loggamma, void *ws, size_t ws_bytes, krr_stream_t stream);
 
 /* Truncated CG for the preconditioner system (K_hat + shift I) z = v from z = 0
  * (sections 4.3, 5.2): at most maxit iterations (>= 1), stopping early when the

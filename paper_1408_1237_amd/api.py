@@ -105,8 +105,10 @@ def kmvp_gauss_cross(xt: torch.Tensor, xs: torch.Tensor, sigma: float, q: torch.
 
 
 def kmvp_grad(x: torch.Tensor, sigma: float, gamma: float, lam: torch.Tensor, w: torch.Tensor,
-              ws: torch.Tensor | None = None):
-    """(gx (n, d), g_logsigma, g_loggamma) = -lam^T (dK/dtheta) w (device tensors)."""
+              prec="fp64", ws: torch.Tensor | None = None):
+    """(gx (n, d), g_logsigma, g_loggamma) = -lam^T (dK/dtheta) w (device tensors);
+    prec "fp64" (default) or "fp32" for the pair loop."""
+    p = _prec(prec)
     pts = _points(x)
     n, d = x.shape
     lam = _vec(lam, n, torch.float64, "lam")
@@ -116,7 +118,7 @@ def kmvp_grad(x: torch.Tensor, sigma: float, gamma: float, lam: torch.Tensor, w:
     need = N.workspace_size(N.KRR_WS_KMVP_GRAD, [(n, d)])
     if ws is None or ws.numel() < need:
         ws = workspace(need, x.device)
-    N.check(N.load().kmvp_grad(ctypes.byref(pts), float(sigma), float(gamma), lam.data_ptr(), w.data_ptr(),
+    N.check(N.load().kmvp_grad(ctypes.byref(pts), float(sigma), float(gamma), p, lam.data_ptr(), w.data_ptr(),
                                gx.data_ptr(), gs.data_ptr(), gs.data_ptr() + 8, ws.data_ptr(), ws.numel(),
                                _stream()), "kmvp_grad")
     return gx, gs[0], gs[1]

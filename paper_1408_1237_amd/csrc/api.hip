@@ -329,10 +329,11 @@ int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, doubl
     return KRR_OK;
 }
 
-int kmvp_grad(const krr_points *pts, double sigma, double gamma, const double *lam, const double *w, double *gx,
-              double *g_logsigma, double *g_loggamma, void *ws, size_t ws_bytes, krr_stream_t stream) {
+int kmvp_grad(const krr_points *pts, double sigma, double gamma, int32_t prec, const double *lam, const double *w,
+              double *gx, double *g_logsigma, double *g_loggamma, void *ws, size_t ws_bytes, krr_stream_t stream) {
     int rc;
     if ((rc = check_points(pts)) || (rc = check_sigma(sigma))) return rc;
+    if (prec != KRR_FP64 && prec != KRR_FP32) return KRR_EINVAL;
     if (!is_fin(gamma) || gamma < 0.0 || lam == nullptr || w == nullptr || gx == nullptr || g_logsigma == nullptr ||
         g_loggamma == nullptr)
         return KRR_EINVAL;
@@ -343,7 +344,7 @@ int kmvp_grad(const krr_points *pts, double sigma, double gamma, const double *l
     L = carve_grad(ws, pts->n, pts->d);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
-    KRR_HIP_STATUS(kmvp_grad_run(L.P, sigma, gamma, lam, w, gx, g_logsigma, g_loggamma, L.scratch, s));
+    KRR_HIP_STATUS(kmvp_grad_run(L.P, prec, sigma, gamma, lam, w, gx, g_logsigma, g_loggamma, L.scratch, s));
     return KRR_OK;
 }
 

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -26,8 +27,6 @@
 namespace krr {
 
 namespace {
-
-constexpr int NCNT = 8;  // reduction sites per column
 
 struct BCols {  // per-column device state (arrays of C entries unless noted)
     // CG
@@ -42,7 +41,6 @@ struct BCols {  // per-column device state (arrays of C entries unless noted)
     int *col_nchunk;   // [C]
     int64_t *col_off;  // [C] element offset of the column
     double *partials;  // [nchunks * 2]
-    unsigned *counters;  // [C * NCNT]
     int *summary;        // [4]: columns in cycle, columns active
 };
 
@@ -71,34 +69,36 @@ __device__ __forceinline__ void bblock_sum(double (&v)[NV]) {
         }
 }
 
-// Segmented sum: every block covers one chunk of column c.  Returns true in the
-// column's last block; there v holds the column totals (thread 0).
+// Segmented sums in two kernels, with no fences or atomics: a chunk kernel
+// (one block per 256-element chunk, every chunk inside one column) writes its
+// block sums to partials[chunk]; the column kernel that follows (one wave per
+// column) adds the column's chunk sums in a fixed order and runs the epilogue.
 template <int NV>
-__device__ bool seg_reduce(double (&v)[NV], const BCols &B, int c, int site) {
-    __shared__ int is_last;
+__device__ __forceinline__ void seg_partial(double (&v)[NV], const BCols &B) {
     bblock_sum(v);
-    const int c0 = B.col_chunk0[c], nc = B.col_nchunk[c];
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < NV; ++k) B.partials[static_cast<int64_t>(blockIdx.x) * 2 + k] = v[k];
-        __threadfence();
-        is_last = (atomicAdd(&B.counters[c * NCNT + site], 1u) == static_cast<unsigned>(nc - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    if (threadIdx.x == 0) {
+}
+
+// Column of this wave (-1 past the last column).
+__device__ __forceinline__ int wave_col(int C) {
+    const int c = blockIdx.x * (BLOCK / WAVE) + static_cast<int>(threadIdx.x) / WAVE;
+    return c < C ? c : -1;
+}
+
+// The column's totals, in every lane (lane l adds chunks l, l + 64, ...; then a
+// fixed butterfly).  Called by all lanes of the wave.
+template <int NV>
+__device__ __forceinline__ void col_total(const BCols &B, int c, double (&v)[NV]) {
+    const int c0 = B.col_chunk0[c], nc = B.col_nchunk[c];
+    const int lane = static_cast<int>(threadIdx.x) % WAVE;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int b = 0; b < nc; ++b)
-                s += __hip_atomic_load(&B.partials[static_cast<int64_t>(c0 + b) * 2 + k], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            v[k] = s;
-        }
-        B.counters[c * NCNT + site] = 0u;
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int q = lane; q < nc; q += WAVE) s += B.partials[static_cast<int64_t>(c0 + q) * 2 + k];
+        v[k] = bwave_sum(s);
     }
-    return true;
 }
 
 #define BCHUNK                                                        \
@@ -108,7 +108,7 @@ __device__ bool seg_reduce(double (&v)[NV], const BCols &B, int c, int site) {
 // ---------------------------------------------------------------- inner CG (FP32)
 
 __global__ __launch_bounds__(BLOCK) void kb_cg_init(BCols B, const double *__restrict__ vin, float *z, float *r,
-                                                    float *p, double tol2, int maxit) {
+                                                    float *p) {
     BCHUNK;
     if (!B.in_cycle[c]) return;
     const float v = static_cast<float>(vin[e]);
@@ -116,7 +116,15 @@ __global__ __launch_bounds__(BLOCK) void kb_cg_init(BCols B, const double *__res
     r[e] = v;
     p[e] = v;
     double acc[1] = {static_cast<double>(v) * v};
-    if (seg_reduce(acc, B, c, 0) && threadIdx.x == 0) {
+    seg_partial(acc, B);
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_cg_init_col(BCols B, int C, double tol2, int maxit) {
+    const int c = wave_col(C);
+    if (c < 0 || !B.in_cycle[c]) return;
+    double acc[1];
+    col_total(B, c, acc);
+    if (threadIdx.x % WAVE == 0) {
         const float rr = static_cast<float>(acc[0]);
         B.rr[c] = rr;
         B.rr0[c] = rr;
@@ -131,7 +139,15 @@ __global__ __launch_bounds__(BLOCK) void kb_cg_alpha(BCols B, const float *__res
     BCHUNK;
     if (!B.in_cycle[c] || !B.cg_active[c]) return;
     double acc[1] = {static_cast<double>(p[e]) * Ap[e]};
-    if (seg_reduce(acc, B, c, 1) && threadIdx.x == 0) {
+    seg_partial(acc, B);
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_cg_alpha_col(BCols B, int C) {
+    const int c = wave_col(C);
+    if (c < 0 || !B.in_cycle[c] || !B.cg_active[c]) return;
+    double acc[1];
+    col_total(B, c, acc);
+    if (threadIdx.x % WAVE == 0) {
         const float pAp = static_cast<float>(acc[0]);
         if (!(pAp > 0.f) || !isfinite(pAp))
             B.cg_active[c] = 0;
@@ -149,45 +165,59 @@ __global__ __launch_bounds__(BLOCK) void kb_cg_update(BCols B, float *z, float *
     const float ri = r[e] - a * Ap[e];
     r[e] = ri;
     double acc[1] = {static_cast<double>(ri) * ri};
-    if (seg_reduce(acc, B, c, 2) && threadIdx.x == 0) {
+    seg_partial(acc, B);
+}
+
+// Also retires a column whose CG reached maxit (keeps the products of the next
+// iteration off it).
+__global__ __launch_bounds__(BLOCK) void kb_cg_update_col(BCols B, int C, int maxit) {
+    const int c = wave_col(C);
+    if (c < 0 || !B.in_cycle[c] || !B.cg_active[c]) return;
+    double acc[1];
+    col_total(B, c, acc);
+    if (threadIdx.x % WAVE == 0) {
         const float rr = static_cast<float>(acc[0]);
         B.beta[c] = rr / B.rr[c];
         B.rr[c] = rr;
-        B.cg_iters[c] += 1;
-        if (!isfinite(rr) || rr <= B.thresh[c]) B.cg_active[c] = 0;
+        const int it = B.cg_iters[c] + 1;
+        B.cg_iters[c] = it;
+        if (!isfinite(rr) || rr <= B.thresh[c] || it >= maxit) B.cg_active[c] = 0;
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void kb_cg_pupdate(BCols B, const float *__restrict__ r, float *p, int maxit) {
+__global__ __launch_bounds__(BLOCK) void kb_cg_pupdate(BCols B, const float *__restrict__ r, float *p) {
     BCHUNK;
     if (!B.in_cycle[c] || !B.cg_active[c]) return;
-    if (B.cg_iters[c] >= maxit) return;
     p[e] = r[e] + B.beta[c] * p[e];
-}
-
-// A column whose CG reached maxit stops in the update's epilogue only through
-// this flag pass (keeps the products of the next iteration harmless).
-__global__ void kb_cg_cap(BCols B, int C, int maxit) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < C && B.cg_active[c] && B.cg_iters[c] >= maxit) B.cg_active[c] = 0;
 }
 
 // ---------------------------------------------------------------- FGMRES (FP64)
 
 // r = b - Kx (Kx may be null), per column beta, bnorm, est; starts the cycle of
-// every valid column that is above the tolerance.
+// every valid column that is above the tolerance.  At a cycle end (Kx given)
+// a column that took no step keeps its state: its x, and so its residual, did
+// not change (its product was skipped).
 __global__ __launch_bounds__(BLOCK) void kb_residual(BCols B, const double *__restrict__ b, const double *Kx,
-                                                     double *r, int m, double tol) {
+                                                     double *r) {
     BCHUNK;
     if (!B.valid[c]) {
         r[e] = 0.0;
         return;
     }
+    if (Kx != nullptr && B.kcol[c] == 0) return;
     const double bi = b[e];
     const double v = Kx ? bi - Kx[e] : bi;
     r[e] = v;
     double acc[2] = {v * v, bi * bi};
-    if (seg_reduce(acc, B, c, 3) && threadIdx.x == 0) {
+    seg_partial(acc, B);
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_residual_col(BCols B, int C, int cycle_end, int m, double tol) {
+    const int c = wave_col(C);
+    if (c < 0 || !B.valid[c] || (cycle_end && B.kcol[c] == 0)) return;
+    double acc[2];
+    col_total(B, c, acc);
+    if (threadIdx.x % WAVE == 0) {
         const double beta = sqrt(acc[0]), bn = sqrt(acc[1]);
         B.beta_o[c] = beta;
         B.bnorm[c] = bn;
@@ -221,38 +251,64 @@ __global__ __launch_bounds__(BLOCK) void kb_copy(BCols B, const double *__restri
     bout[e] = a[e];
 }
 
+// Modified Gram-Schmidt, one pass per basis vector: h_0 = w.v_0 (and ||w||),
+// then for i = 0..j-1: w -= h_i v_i, h_{i+1} = w.v_{i+1}; last: w -= h_j v_j,
+// h_{j+1} = ||w||.  site: 0 first, 1 step, 2 last.
 __global__ __launch_bounds__(BLOCK) void kb_mgs_first(BCols B, const double *__restrict__ w,
-                                                      const double *__restrict__ v0, int m) {
+                                                      const double *__restrict__ v0) {
     BCHUNK;
     if (!B.in_cycle[c]) return;
     const double wi = w[e];
     double acc[2] = {wi * v0[e], wi * wi};
-    if (seg_reduce(acc, B, c, 4) && threadIdx.x == 0) {
-        B.hcol[static_cast<int64_t>(c) * (m + 2)] = acc[0];
-        B.wnorm0[c] = sqrt(acc[1]);
-    }
+    seg_partial(acc, B);
 }
 
 __global__ __launch_bounds__(BLOCK) void kb_mgs_step(BCols B, double *w, const double *__restrict__ vi,
                                                      const double *__restrict__ vnext, int i_, int m) {
     BCHUNK;
     if (!B.in_cycle[c]) return;
-    double *hc = B.hcol + static_cast<int64_t>(c) * (m + 2);
+    const double *hc = B.hcol + static_cast<int64_t>(c) * (m + 2);
     const double wi = w[e] - hc[i_] * vi[e];
     w[e] = wi;
     double acc[1] = {wi * vnext[e]};
-    if (seg_reduce(acc, B, c, 5) && threadIdx.x == 0) hc[i_ + 1] = acc[0];
+    seg_partial(acc, B);
 }
 
 __global__ __launch_bounds__(BLOCK) void kb_mgs_last(BCols B, double *w, const double *__restrict__ vj, int j,
                                                      int m) {
     BCHUNK;
     if (!B.in_cycle[c]) return;
-    double *hc = B.hcol + static_cast<int64_t>(c) * (m + 2);
+    const double *hc = B.hcol + static_cast<int64_t>(c) * (m + 2);
     const double wi = w[e] - hc[j] * vj[e];
     w[e] = wi;
     double acc[1] = {wi * wi};
-    if (seg_reduce(acc, B, c, 6) && threadIdx.x == 0) hc[j + 1] = sqrt(acc[0]);
+    seg_partial(acc, B);
+}
+
+// Column epilogue of the three Gram-Schmidt passes: writes hcol[idx] (site 0:
+// also ||w|| before orthogonalisation; site 2: the norm).
+__global__ __launch_bounds__(BLOCK) void kb_mgs_col(BCols B, int C, int site, int idx, int m) {
+    const int c = wave_col(C);
+    if (c < 0 || !B.in_cycle[c]) return;
+    double acc[2];
+    if (site == 0) {
+        col_total(B, c, acc);
+    } else {
+        double one[1];
+        col_total(B, c, one);
+        acc[0] = one[0];
+    }
+    if (threadIdx.x % WAVE == 0) {
+        double *hc = B.hcol + static_cast<int64_t>(c) * (m + 2);
+        if (site == 0) {
+            hc[0] = acc[0];
+            B.wnorm0[c] = sqrt(acc[1]);
+        } else if (site == 1) {
+            hc[idx] = acc[0];
+        } else {
+            hc[idx] = sqrt(acc[0]);
+        }
+    }
 }
 
 // Givens step of every column in its cycle (one thread per column); a column
@@ -350,10 +406,6 @@ __global__ void kb_summary(BCols B, int C) {
 __global__ void kb_fill_i(int *p, int n, int v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-__global__ void kb_fill_u(unsigned *p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
 }
 
 // Gather system k's right-hand sides (original order, column-major, ld) into
@@ -464,7 +516,6 @@ BatchLayout carve_batch(void *ws, const krr_points *probs, int nprob, int nrhs, 
     B.col_nchunk = cv.take<int>(C);
     B.col_off = cv.take<int64_t>(C);
     B.partials = cv.take<double>(static_cast<size_t>(L.nchunks) * 2);
-    B.counters = cv.take<unsigned>(static_cast<size_t>(C) * NCNT);
     B.summary = cv.take<int>(4);
     L.total = cv.off + 256;
     return L;
@@ -503,6 +554,7 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
     const int64_t LL = L.L;
     const int nb = L.nchunks;
     const int cb = (C + BLOCK - 1) / BLOCK;
+    const int ccb = (C + BLOCK / WAVE - 1) / (BLOCK / WAVE);  // one wave per column
 
     // host-built chunk and column maps
     {
@@ -526,7 +578,6 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
         BH(hipMemcpyAsync(B.valid, valid.data(), sizeof(int) * C, hipMemcpyHostToDevice, s));
         BH(hipStreamSynchronize(s));  // host vectors go out of scope
     }
-    hipLaunchKernelGGL(kb_fill_u, dim3((C * NCNT + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, B.counters, C * NCNT);
     hipLaunchKernelGGL(kb_fill_i, dim3(cb), dim3(BLOCK), 0, s, B.nonfinite, C, 0);
     hipLaunchKernelGGL(kb_fill_i, dim3(cb), dim3(BLOCK), 0, s, B.kcol, C, 0);
     hipLaunchKernelGGL(kb_fill_i, dim3(cb), dim3(BLOCK), 0, s, B.in_cycle, C, 0);
@@ -584,6 +635,7 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
                 const int local = end - pos;
                 fill_msys(hin[end], S.P, inner_prec, Rp, S.pscratch, S.base, S.delta, S.gamma);
                 fill_msys(hout[end], S.P, KRR_FP64, Rp, S.pscratch, S.base, S.delta, S.gamma);
+                hin[end].col0 = hout[end].col0 = order[end] * Rp;
                 for (int bx = 0; bx < S.P.ntiles; ++bx)
                     for (int by = 0; by < hin[end].a.splits; ++by)
                         for (int rb = 0; rb < nrb; ++rb) items.push_back(MItem{local, bx, by, rb});
@@ -605,23 +657,29 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
         BH(hipMemcpyAsync(L.d_items, items.data(), sizeof(MItem) * items.size(), hipMemcpyHostToDevice, s));
         BH(hipStreamSynchronize(s));
     }
-    auto products = [&](const void *Q, void *Yo, bool inner, hipStream_t st) -> hipError_t {
+    // Products run only on the columns that use them: the inner CG's on columns
+    // in their cycle with an active CG, the Arnoldi step's on columns in their
+    // cycle, the cycle-end residual's on columns that took a step this cycle.
+    const ColGate gate_inner{B.in_cycle, B.cg_active}, gate_arnoldi{B.in_cycle, nullptr},
+        gate_cycle_end{B.kcol, nullptr};
+    auto products = [&](const void *Q, void *Yo, bool inner, ColGate gate, hipStream_t st) -> hipError_t {
         for (size_t c = 0; c < bp_in.size(); ++c)
-            KRR_HIP(batched_product(inner ? bp_in[c] : bp_out[c], Q, Yo, inner ? 1 : 0, st));
+            KRR_HIP(batched_product(inner ? bp_in[c] : bp_out[c], Q, Yo, inner ? 1 : 0, gate, st));
         return hipSuccess;
     };
 
     // the inner CG on fixed buffers (vin -> z32), recorded once as a graph
     const double tol2 = o.inner_tol * o.inner_tol;
     auto inner_seq = [&](hipStream_t st) -> hipError_t {
-        hipLaunchKernelGGL(kb_cg_init, dim3(nb), dim3(BLOCK), 0, st, B, L.vin, L.z32, L.r32, L.p32, tol2,
-                           o.inner_maxit);
+        hipLaunchKernelGGL(kb_cg_init, dim3(nb), dim3(BLOCK), 0, st, B, L.vin, L.z32, L.r32, L.p32);
+        hipLaunchKernelGGL(kb_cg_init_col, dim3(ccb), dim3(BLOCK), 0, st, B, C, tol2, o.inner_maxit);
         for (int it = 0; it < o.inner_maxit; ++it) {
-            KRR_HIP(products(L.p32, L.Ap32, true, st));
+            KRR_HIP(products(L.p32, L.Ap32, true, gate_inner, st));
             hipLaunchKernelGGL(kb_cg_alpha, dim3(nb), dim3(BLOCK), 0, st, B, L.p32, L.Ap32);
+            hipLaunchKernelGGL(kb_cg_alpha_col, dim3(ccb), dim3(BLOCK), 0, st, B, C);
             hipLaunchKernelGGL(kb_cg_update, dim3(nb), dim3(BLOCK), 0, st, B, L.z32, L.r32, L.p32, L.Ap32);
-            hipLaunchKernelGGL(kb_cg_cap, dim3(cb), dim3(BLOCK), 0, st, B, C, o.inner_maxit);
-            hipLaunchKernelGGL(kb_cg_pupdate, dim3(nb), dim3(BLOCK), 0, st, B, L.r32, L.p32, o.inner_maxit);
+            hipLaunchKernelGGL(kb_cg_update_col, dim3(ccb), dim3(BLOCK), 0, st, B, C, o.inner_maxit);
+            hipLaunchKernelGGL(kb_cg_pupdate, dim3(nb), dim3(BLOCK), 0, st, B, L.r32, L.p32);
         }
         return hipGetLastError();
     };
@@ -683,7 +741,8 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
         }                                  \
     } while (0)
 
-    hipLaunchKernelGGL(kb_residual, dim3(nb), dim3(BLOCK), 0, s, B, L.b, nullptr, L.r, m, o.tol);
+    hipLaunchKernelGGL(kb_residual, dim3(nb), dim3(BLOCK), 0, s, B, L.b, nullptr, L.r);
+    hipLaunchKernelGGL(kb_residual_col, dim3(ccb), dim3(BLOCK), 0, s, B, C, 0, m, o.tol);
     BHC(read_summary());
     if (host[1] > 0) {
         cleanup();
@@ -702,27 +761,35 @@ int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, cons
                 hipLaunchKernelGGL(kb_cast_z, dim3(nb), dim3(BLOCK), 0, s, B, L.z32, Zj);
                 mvp_in += o.inner_maxit;
             }
-            BHC(products(Zj, L.w, false, s));
+            BHC(products(Zj, L.w, false, gate_arnoldi, s));
             ++mvp64;
-            hipLaunchKernelGGL(kb_mgs_first, dim3(nb), dim3(BLOCK), 0, s, B, L.w, L.V, m);
-            for (int i = 0; i < j; ++i)
+            hipLaunchKernelGGL(kb_mgs_first, dim3(nb), dim3(BLOCK), 0, s, B, L.w, L.V);
+            hipLaunchKernelGGL(kb_mgs_col, dim3(ccb), dim3(BLOCK), 0, s, B, C, 0, 0, m);
+            for (int i = 0; i < j; ++i) {
                 hipLaunchKernelGGL(kb_mgs_step, dim3(nb), dim3(BLOCK), 0, s, B, L.w, L.V + i * LL,
                                    L.V + (i + 1) * LL, i, m);
+                hipLaunchKernelGGL(kb_mgs_col, dim3(ccb), dim3(BLOCK), 0, s, B, C, 1, i + 1, m);
+            }
             hipLaunchKernelGGL(kb_mgs_last, dim3(nb), dim3(BLOCK), 0, s, B, L.w, Vj, j, m);
+            hipLaunchKernelGGL(kb_mgs_col, dim3(ccb), dim3(BLOCK), 0, s, B, C, 2, j + 1, m);
             // normalise before the Givens step decides whether the column leaves its cycle
             hipLaunchKernelGGL(kb_normalize, dim3(nb), dim3(BLOCK), 0, s, B, L.w, L.V + (j + 1) * LL, j, m);
             hipLaunchKernelGGL(kb_givens, dim3(cb), dim3(BLOCK), 0, s, B, C, j, m, o.tol);
             ++outer;
             BHC(read_summary());
+            if (progress_every() && outer % progress_every() == 0)
+                std::fprintf(stderr, "krr batched fgmres: outer %d cycle %d columns in their cycle %d of %d\n", outer,
+                             cycles + 1, host[0], nprob * nrhs);
             if (host[0] == 0) break;
         }
         // x += Z y per column, then the true residual restarts the unconverged ones
         hipLaunchKernelGGL(kb_backsolve, dim3(cb), dim3(BLOCK), 0, s, B, C, m);
         hipLaunchKernelGGL(kb_update_x, dim3(nb), dim3(BLOCK), 0, s, B, L.Z, LL, m, L.x);
         ++cycles;
-        BHC(products(L.x, L.w, false, s));
+        BHC(products(L.x, L.w, false, gate_cycle_end, s));
         ++mvp64;
-        hipLaunchKernelGGL(kb_residual, dim3(nb), dim3(BLOCK), 0, s, B, L.b, L.w, L.r, m, o.tol);
+        hipLaunchKernelGGL(kb_residual, dim3(nb), dim3(BLOCK), 0, s, B, L.b, L.w, L.r);
+        hipLaunchKernelGGL(kb_residual_col, dim3(ccb), dim3(BLOCK), 0, s, B, C, 1, m, o.tol);
         BHC(read_summary());
         if (host[1] > 0) {
             result = KRR_BREAKDOWN;

@@ -21,30 +21,6 @@
 
 namespace krr {
 
-// 2^a in FP64 for a <= 1023.  a = n + f with n = rint(a) and |f| <= 1/2 (the
-// subtraction is exact), 2^f = e^(f ln 2) from its Taylor series to degree 12
-// (truncation error below 2.4e-16 for |f ln 2| <= 0.347), scaled by 2^n.
-// Arguments below -1100 are clamped (the result then underflows to 0).
-__device__ __forceinline__ double exp2_f64(double a) {
-    a = fmax(a, -1100.0);
-    const double n = __builtin_rint(a);
-    const double f = a - n;
-    double p = 2.5678435993488206e-11;
-    p = __builtin_fma(p, f, 4.4455382718708116e-10);
-    p = __builtin_fma(p, f, 7.054911620801123e-09);
-    p = __builtin_fma(p, f, 1.01780860092397e-07);
-    p = __builtin_fma(p, f, 1.321548679014431e-06);
-    p = __builtin_fma(p, f, 1.5252733804059841e-05);
-    p = __builtin_fma(p, f, 0.0001540353039338161);
-    p = __builtin_fma(p, f, 0.0013333558146428443);
-    p = __builtin_fma(p, f, 0.009618129107628477);
-    p = __builtin_fma(p, f, 0.05550410866482158);
-    p = __builtin_fma(p, f, 0.24022650695910072);
-    p = __builtin_fma(p, f, 0.6931471805599453);
-    p = __builtin_fma(p, f, 1.0);
-    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
-}
-
 // Block index remap: consecutive hardware block ids are dealt round-robin to
 // the 8 XCDs; give each XCD a contiguous range of logical blocks so that the
 // blocks sharing a column range (and its source data in L2) run on one XCD.
@@ -225,137 +201,205 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
 
 // ---------------------------------------------------------------- matrix-core exponent
 //
-// FP32 / BF16 products with the exponent on the matrix cores.  The folded
-// exponent of a pair is an inner product of length d + 1,
+// Products with the exponent on the matrix cores.  The folded exponent of a
+// pair is an inner product of length d + 1,
 //   arg_ij = [2 t_i, c_i] . [o_j, 1],   t_i = x_i - a_J, c_i = -||t_i||^2 - N_J,
-// so v_mfma_f32_16x16x4f32 forms it for 16 x 16 pairs at once (DK = ceil((d+1)/4)
-// instructions): A = the 16 sources x 4 coordinates (lane l: source l % 16,
-// coordinate l / 16 of the chunk), B = the 4 coordinates x 16 targets (lane l:
-// target l % 16), and the accumulator gives lane l the exponents of target
-// l % 16 against sources 4 (l / 16) + v, v < 4.  The VALU then does exp2 and one
-// fused multiply-add per pair, accumulating each target's sum in the four lanes
-// that hold it (added by two cross-lane steps at the end).  A wave owns 4 groups
-// of 16 targets (64 rows), a block one 256-row tile.  Wide tiles use the direct
-// form on the VALU.
+// so one v_mfma_{f32,f64}_16x16x4 per 4 coordinates (DK = ceil((d+1)/4) of
+// them) forms it for 16 x 16 pairs at once: A = the 16 sources x 4 coordinates
+// (one value per lane: row l % 16, coordinate l / 16 of the chunk), B = the 4
+// coordinates x 16 targets (lane l: target l % 16).  The accumulator gives lane
+// l target l % 16 against four sources: rows 4 (l / 16) + v of the block in FP32,
+// rows l / 16 + 4 v in FP64; for FP64 the A rows hold the sources in the order
+// 0, 4, 8, 12, 1, 5, ... so that the four sources of lane l are 4 (l / 16) + v in
+// both precisions (their q w values are then one contiguous 4-vector).  The VALU
+// does exp2 and one fused multiply-add per pair, accumulating each target's sum in
+// the four lanes that hold it (added by two cross-lane steps at the end).  A wave
+// owns 4 groups of 16 targets (64 rows), a block one 256-row tile.  Wide tiles
+// use the direct form on the VALU.
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+struct MG;
+template <>
+struct MG<KRR_FP64> {
+    using T = double;
+    using V4 = doublex4_t;
+    static constexpr bool permute_rows = true;
+    static __device__ __forceinline__ V4 mfma(T a, T b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ T fma(T a, T b, T c) { return __builtin_fma(a, b, c); }
+};
+template <>
+struct MG<KRR_FP32> {
+    using T = float;
+    using V4 = floatx4_t;
+    static constexpr bool permute_rows = false;
+    static __device__ __forceinline__ V4 mfma(T a, T b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ T fma(T a, T b, T c) { return __builtin_fmaf(a, b, c); }
+};
+template <>
+struct MG<KRR_BF16> : MG<KRR_FP32> {};
 
 template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
+    using M = MG<PREC>;
+    using T = typename M::T;
+    using V4 = typename M::V4;
     using Off = typename P::Off;
     using Q = typename P::Q;
     constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
     constexpr int RG = 4;
+    constexpr int UNR = (DK > 2 || PREC == KRR_FP64) ? 1 : 3;  // unroll of the column-step loop
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
-    const float *__restrict__ qw = static_cast<const float *>(a.qw);
+    const T *__restrict__ qw = static_cast<const T *>(a.qw);
     const int64_t n_pad = a.n_pad;
 
     const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int lane = threadIdx.x % WAVE;
     const int r16 = lane % 16, g = lane / 16;
+    // source of A row r16 within a 16-column step
+    const int asrc = M::permute_rows ? (r16 % 4) * 4 + r16 / 4 : r16;
     const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (threadIdx.x / WAVE) * 64;
 
     double aI[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
-    float oi[RG][D];
+    // the lane's target offsets stay in registers when they fit in 64 VGPRs,
+    // else they are re-read once per column tile
+    constexpr bool KEEP = RG * D * sizeof(T) <= 256;
+    T oi[KEEP ? RG : 1][KEEP ? D : 1];
+    if constexpr (KEEP) {
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg)
+        for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
-        for (int k = 0; k < D; ++k) oi[rg][k] = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
-    float acc[RG];
+            for (int k = 0; k < D; ++k) oi[rg][k] = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
+    }
+    T acc[RG];
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.f;
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = T(0);
 
     const int J0 = by * a.tps;
     const int J1 = min(a.ntiles, J0 + a.tps);
     for (int J = J0; J < J1; ++J) {
         const double r2 = a.tile_r2[J];
         const double nj = a.tile_nj[J];
-        float t[RG][D];
-        float bval[RG][DK];
+        T t[RG][D];
+        T bval[RG][DK];
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
             double tt = 0.0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                t[rg][k] = static_cast<float>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
-                                              static_cast<double>(oi[rg][k]));
+                T o;
+                if constexpr (KEEP)
+                    o = oi[rg][k];
+                else
+                    o = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
+                t[rg][k] = static_cast<T>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
+                                          static_cast<double>(o));
                 const double tk = static_cast<double>(t[rg][k]);
                 tt = __builtin_fma(tk, tk, tt);
             }
-            const float c = static_cast<float>(-tt - nj);
+            const T c = static_cast<T>(-tt - nj);
             // coordinate 4 kc + g of [2t, c, 0...] for this lane's chunk slots
 #pragma unroll
             for (int kc = 0; kc < DK; ++kc) {
                 const int dim = 4 * kc + g;
-                float v = (dim == D) ? c : 0.f;
+                T v = (dim == D) ? c : T(0);
 #pragma unroll
-                for (int k = 0; k < D; ++k) v = (dim == k) ? 2.f * t[rg][k] : v;
+                for (int k = 0; k < D; ++k) v = (dim == k) ? T(2) * t[rg][k] : v;
                 bval[rg][kc] = v;
             }
         }
         const int64_t j0 = static_cast<int64_t>(J) * TILE;
         if (r2 <= P::wide) {
-#pragma unroll 2
-            for (int cb = 0; cb < TILE; cb += 16) {
+            // Software pipeline over the 16 column steps of the tile: the matrix
+            // cores form the exponents of step cb + 16 (own accumulators) while
+            // the VALU exponentiates and accumulates step cb.
+            auto load_step = [&](int cb, T (&av)[DK], V4 &qv) {
                 const int64_t col = j0 + cb;
-                float aval[DK];
 #pragma unroll
                 for (int kc = 0; kc < DK; ++kc) {
                     const int dim = 4 * kc + g;
                     const int dsafe = dim < D ? dim : D - 1;
-                    const float o = P::off(off[dsafe * n_pad + col + r16]);
-                    aval[kc] = dim < D ? o : (dim == D ? 1.f : 0.f);
+                    const T o = P::off(off[dsafe * n_pad + col + asrc]);
+                    av[kc] = dim < D ? o : (dim == D ? T(1) : T(0));
                 }
-                const floatx4_t qv = *reinterpret_cast<const floatx4_t *>(qw + col + 4 * g);
+                qv = *reinterpret_cast<const V4 *>(qw + col + 4 * g);
+            };
+            auto exponents = [&](const T (&av)[DK], V4 (&G)[RG]) {
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) {
-                    floatx4_t G = {0.f, 0.f, 0.f, 0.f};
+                    G[rg] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-                    for (int kc = 0; kc < DK; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(aval[kc], bval[rg][kc], G, 0, 0, 0);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[v]), qv[v], acc[rg]);
+                    for (int kc = 0; kc < DK; ++kc) G[rg] = M::mfma(av[kc], bval[rg][kc], G[rg]);
                 }
+            };
+            auto accumulate = [&](const V4 (&G)[RG], const V4 &qv) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg) acc[rg] = M::fma(P::ex2(G[rg][v]), qv[v], acc[rg]);
+            };
+            T av[DK];
+            V4 qv, G[RG];
+            load_step(0, av, qv);
+            exponents(av, G);
+#pragma unroll UNR
+            for (int cb = 16; cb < TILE; cb += 16) {
+                T avn[DK];
+                V4 qn, Gn[RG];
+                load_step(cb, avn, qn);
+                exponents(avn, Gn);
+                accumulate(G, qv);
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) G[rg] = Gn[rg];
+                qv = qn;
             }
+            accumulate(G, qv);
         } else {
             for (int cb = 0; cb < TILE; cb += 16) {
                 const int64_t col = j0 + cb + 4 * g;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    float oc[D];
+                    T oc[D];
 #pragma unroll
                     for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + col + v]);
-                    const float qj = P::q(q[col + v]);
+                    const T qj = P::q(q[col + v]);
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg) {
-                        float ss = 0.f;
+                        T ss = T(0);
 #pragma unroll
                         for (int k = 0; k < D; ++k) {
-                            const float dd = t[rg][k] - oc[k];
-                            ss = __builtin_fmaf(dd, dd, ss);
+                            const T dd = t[rg][k] - oc[k];
+                            ss = M::fma(dd, dd, ss);
                         }
-                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), qj, acc[rg]);
+                        acc[rg] = M::fma(P::ex2(-ss), qj, acc[rg]);
                     }
                 }
             }
         }
     }
-    float *out = static_cast<float *>(a.out);
+    T *out = static_cast<T *>(a.out);
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
-        float sum = acc[rg];
+        T sum = acc[rg];
         sum += __shfl_xor(sum, 16, WAVE);
         sum += __shfl_xor(sum, 32, WAVE);
         const int64_t i = row0 + rg * 16 + r16;
         if (g == 0) {
             if (a.splits == 1) {
-                if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
-                out[i] = (i < a.n_rows) ? sum : 0.f;
+                if (i < a.n_rows && a.square) sum += static_cast<T>(a.shift) * P::q(q[i]);
+                out[i] = (i < a.n_rows) ? sum : T(0);
             } else {
                 out[static_cast<int64_t>(by) * a.n_pad_rows + i] = sum;
             }
@@ -478,9 +522,8 @@ KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
     return k;
 }
 
-// FP32 / BF16 products up to d = 16 take the matrix-core exponent kernel; FP64
-// and larger d the VALU kernel.  KRR_KMVP_VALU=1 forces the VALU kernel (used to
-// cross-check the two).
+// Products up to d = 16 take the matrix-core exponent kernel, larger d the VALU
+// kernel.  KRR_KMVP_VALU=1 forces the VALU kernel (used to cross-check the two).
 static bool use_valu_kernel() {
     const char *v = std::getenv("KRR_KMVP_VALU");
     return v && v[0] == '1';
@@ -488,7 +531,7 @@ static bool use_valu_kernel() {
 
 template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, hipStream_t s) {
-    if constexpr (PREC != KRR_FP64 && D <= 16) {
+    if constexpr (D <= 16) {
         if (!use_valu_kernel()) {
             hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
@@ -696,6 +739,15 @@ thread_local bool g_prof_suspended = false;
 }
 
 void profile_suspend(bool on) { g_prof_suspended = on; }
+
+int progress_every() {
+    static const int every = [] {
+        const char *v = std::getenv("KRR_PROGRESS");
+        const int k = v ? std::atoi(v) : 0;
+        return k > 0 ? k : 0;
+    }();
+    return every;
+}
 
 bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop) {
     if (!g_prof.on || g_prof_suspended) return false;

@@ -30,6 +30,16 @@ struct MSysB {
     int64_t base;
     const void *w;
     double shift_in, shift_out;
+    int col0;  // index of the system's first column in the solver's column arrays
+};
+
+// Which columns of a batched product are needed: column c is live when
+// a[c] != 0 and b[c] != 0 (a null array counts as all ones).  A block of 16
+// right-hand sides without a live column is skipped, and the outputs of dead
+// columns are left as they were (their consumers skip them too).
+struct ColGate {
+    const int *a = nullptr;
+    const int *b = nullptr;
 };
 
 constexpr int BATCH_TPS = 32;  // column tiles per work item of a batched product
@@ -48,7 +58,9 @@ struct BatchedProduct {
 size_t batched_product_scratch_bytes(const Prepared &P, int nrhs);
 void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, int64_t base, double shift_in,
                double shift_out);
-// Y = K_hat Q + shift Q for every system of bp (inner != 0: shift_in).
-hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s);
+// Y = K_hat Q + shift Q for every system of bp (inner != 0: shift_in), on the
+// live columns of gate.
+hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, ColGate gate,
+                           hipStream_t s);
 
 }  // namespace krr

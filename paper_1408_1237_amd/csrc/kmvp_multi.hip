@@ -18,26 +18,6 @@ namespace krr {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double exp2_f64m(double a) {
-    a = fmax(a, -1100.0);
-    const double n = __builtin_rint(a);
-    const double f = a - n;
-    double p = 2.5678435993488206e-11;
-    p = __builtin_fma(p, f, 4.4455382718708116e-10);
-    p = __builtin_fma(p, f, 7.054911620801123e-09);
-    p = __builtin_fma(p, f, 1.01780860092397e-07);
-    p = __builtin_fma(p, f, 1.321548679014431e-06);
-    p = __builtin_fma(p, f, 1.5252733804059841e-05);
-    p = __builtin_fma(p, f, 0.0001540353039338161);
-    p = __builtin_fma(p, f, 0.0013333558146428443);
-    p = __builtin_fma(p, f, 0.009618129107628477);
-    p = __builtin_fma(p, f, 0.05550410866482158);
-    p = __builtin_fma(p, f, 0.24022650695910072);
-    p = __builtin_fma(p, f, 0.6931471805599453);
-    p = __builtin_fma(p, f, 1.0);
-    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
-}
-
 __device__ __forceinline__ int xcd_remap_m(int b, int nb) {
     const int tall = nb / 8, extra = nb % 8;
     const int xcd = b % 8, local = b / 8;
@@ -53,7 +33,7 @@ struct MP<KRR_FP64> {
     using Acc = doublex4;
     static constexpr double wide = WIDE_R2_FP64;
     static __device__ __forceinline__ T off(Off v) { return v; }
-    static __device__ __forceinline__ T ex2(T a) { return exp2_f64m(a); }
+    static __device__ __forceinline__ T ex2(T a) { return exp2_f64(a); }
     static __device__ __forceinline__ T fma(T a, T b, T c) { return __builtin_fma(a, b, c); }
     static __device__ __forceinline__ Acc mfma(T a, T b, Acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -205,11 +185,20 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_multi(MArgs a) {
 
 // Batched over many systems of one dimension: block b runs work item b
 // (system, row tile, column chunk, RHS block) with that system's arguments.
+__device__ __forceinline__ bool gate_live(const ColGate &g, int c) {
+    return (g.a == nullptr || g.a[c] != 0) && (g.b == nullptr || g.b[c] != 0);
+}
+
 template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_multi_batched(const MSysB *__restrict__ sys,
-                                                              const MItem *__restrict__ items) {
+                                                              const MItem *__restrict__ items, ColGate gate) {
     const MItem it = items[blockIdx.x];
-    multi_body<D, PREC>(sys[it.sys].a, it.bx, it.by, it.rbk);
+    const MSysB &m = sys[it.sys];
+    if (gate.a != nullptr || gate.b != nullptr) {
+        const int live = threadIdx.x < 16 ? gate_live(gate, m.col0 + it.rbk * 16 + threadIdx.x) : 0;
+        if (!__syncthreads_or(live)) return;  // block-uniform
+    }
+    multi_body<D, PREC>(m.a, it.bx, it.by, it.rbk);
 }
 
 // Q'[rbk][j][r % 16] = Q[p_j + r ldq] * weff_j for r < nrhs (0 beyond), where
@@ -274,7 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_finish(int64_t n, int64_t n_pad
 // base_k + r n_pad_k.
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_multi_prescale_b(const MSysB *__restrict__ S, const void *Qall_,
-                                                            int nrhs) {
+                                                            int nrhs, ColGate gate) {
     using T = typename MP<PREC>::T;
     const MSysB &m = S[blockIdx.y];
     const int64_t n_pad = m.a.n_pad;
@@ -287,6 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_prescale_b(const MSysB *__restr
     const int r16 = static_cast<int>(idx % 16);
     const int64_t j = (idx / 16) % n_pad;
     const int r = static_cast<int>(idx / (16 * n_pad)) * 16 + r16;
+    if (!gate_live(gate, m.col0 + r)) return;
     T v = T(0);
     if (r < nrhs) {
         v = Q[j + static_cast<int64_t>(r) * n_pad];
@@ -299,7 +289,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_prescale_b(const MSysB *__restr
 
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_multi_finish_b(const MSysB *__restrict__ S, const void *Qall_, void *Yall_,
-                                                          int nrhs, int inner) {
+                                                          int nrhs, int inner, ColGate gate) {
     using T = typename MP<PREC>::T;
     const MSysB &m = S[blockIdx.y];
     const int64_t n_pad = m.a.n_pad;
@@ -307,6 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_multi_finish_b(const MSysB *__restric
     if (idx >= n_pad * nrhs) return;
     const int64_t i = idx % n_pad;
     const int r = static_cast<int>(idx / n_pad);
+    if (!gate_live(gate, m.col0 + r)) return;
     T *Y = static_cast<T *>(Yall_) + m.base;
     if (i >= m.a.n) {
         Y[idx] = T(0);
@@ -356,53 +347,57 @@ void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, i
     m.base = base;
     m.shift_in = shift_in;
     m.shift_out = shift_out;
+    m.col0 = 0;
 }
 
 template <int D, int PREC>
-static hipError_t launch_multi_b(const MSysB *S, const MItem *items, int nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC>), dim3(nitems), dim3(BLOCK), 0, s, S, items);
+static hipError_t launch_multi_b(const MSysB *S, const MItem *items, int nitems, ColGate gate, hipStream_t s) {
+    hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC>), dim3(nitems), dim3(BLOCK), 0, s, S, items, gate);
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_multi_b_d(int dpad, const MSysB *S, const MItem *items, int nitems, hipStream_t s) {
+static hipError_t launch_multi_b_d(int dpad, const MSysB *S, const MItem *items, int nitems, ColGate gate,
+                                   hipStream_t s) {
     switch (dpad) {
-        case 1: return launch_multi_b<1, PREC>(S, items, nitems, s);
-        case 2: return launch_multi_b<2, PREC>(S, items, nitems, s);
-        case 3: return launch_multi_b<3, PREC>(S, items, nitems, s);
-        case 4: return launch_multi_b<4, PREC>(S, items, nitems, s);
-        case 6: return launch_multi_b<6, PREC>(S, items, nitems, s);
-        case 8: return launch_multi_b<8, PREC>(S, items, nitems, s);
-        case 12: return launch_multi_b<12, PREC>(S, items, nitems, s);
-        case 16: return launch_multi_b<16, PREC>(S, items, nitems, s);
-        case 24: return launch_multi_b<24, PREC>(S, items, nitems, s);
-        case 32: return launch_multi_b<32, PREC>(S, items, nitems, s);
-        case 48: return launch_multi_b<48, PREC>(S, items, nitems, s);
-        case 64: return launch_multi_b<64, PREC>(S, items, nitems, s);
+        case 1: return launch_multi_b<1, PREC>(S, items, nitems, gate, s);
+        case 2: return launch_multi_b<2, PREC>(S, items, nitems, gate, s);
+        case 3: return launch_multi_b<3, PREC>(S, items, nitems, gate, s);
+        case 4: return launch_multi_b<4, PREC>(S, items, nitems, gate, s);
+        case 6: return launch_multi_b<6, PREC>(S, items, nitems, gate, s);
+        case 8: return launch_multi_b<8, PREC>(S, items, nitems, gate, s);
+        case 12: return launch_multi_b<12, PREC>(S, items, nitems, gate, s);
+        case 16: return launch_multi_b<16, PREC>(S, items, nitems, gate, s);
+        case 24: return launch_multi_b<24, PREC>(S, items, nitems, gate, s);
+        case 32: return launch_multi_b<32, PREC>(S, items, nitems, gate, s);
+        case 48: return launch_multi_b<48, PREC>(S, items, nitems, gate, s);
+        case 64: return launch_multi_b<64, PREC>(S, items, nitems, gate, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int PREC>
-static hipError_t batched_run(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s) {
+static hipError_t batched_run(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, ColGate gate,
+                              hipStream_t s) {
     const dim3 g((bp.max_elems + BLOCK - 1) / BLOCK, bp.nsys);
-    hipLaunchKernelGGL(k_multi_prescale_b<PREC>, g, dim3(BLOCK), 0, s, bp.d_sys, Qall, bp.nrhs);
+    hipLaunchKernelGGL(k_multi_prescale_b<PREC>, g, dim3(BLOCK), 0, s, bp.d_sys, Qall, bp.nrhs, gate);
     KRR_HIP(hipGetLastError());
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool timed = profile_slot(PREC, bp.pairs * bp.nrhs, &ev0, &ev1);
     if (timed) KRR_HIP(hipEventRecord(ev0, s));
-    KRR_HIP(launch_multi_b_d<PREC>(bp.dpad, bp.d_sys, bp.d_items, bp.nitems, s));
+    KRR_HIP(launch_multi_b_d<PREC>(bp.dpad, bp.d_sys, bp.d_items, bp.nitems, gate, s));
     if (timed) KRR_HIP(hipEventRecord(ev1, s));
     const dim3 gf((bp.max_rows + BLOCK - 1) / BLOCK, bp.nsys);
-    hipLaunchKernelGGL(k_multi_finish_b<PREC>, gf, dim3(BLOCK), 0, s, bp.d_sys, Qall, Yall, bp.nrhs, inner);
+    hipLaunchKernelGGL(k_multi_finish_b<PREC>, gf, dim3(BLOCK), 0, s, bp.d_sys, Qall, Yall, bp.nrhs, inner, gate);
     return hipGetLastError();
 }
 
-hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, hipStream_t s) {
+hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, ColGate gate,
+                           hipStream_t s) {
     switch (bp.prec) {
-        case KRR_FP64: return batched_run<KRR_FP64>(bp, Qall, Yall, inner, s);
-        case KRR_FP32: return batched_run<KRR_FP32>(bp, Qall, Yall, inner, s);
-        case KRR_BF16: return batched_run<KRR_BF16>(bp, Qall, Yall, inner, s);
+        case KRR_FP64: return batched_run<KRR_FP64>(bp, Qall, Yall, inner, gate, s);
+        case KRR_FP32: return batched_run<KRR_FP32>(bp, Qall, Yall, inner, gate, s);
+        case KRR_BF16: return batched_run<KRR_BF16>(bp, Qall, Yall, inner, gate, s);
         default: return hipErrorInvalidValue;
     }
 }

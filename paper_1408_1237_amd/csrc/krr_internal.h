@@ -37,6 +37,29 @@ constexpr int VEC_BLOCKS = 512; // blocks of the vector (reduction) kernels
 constexpr double WIDE_R2_FP32 = 64.0;
 constexpr double WIDE_R2_FP64 = 512.0;
 
+// 2^a in FP64 for a <= 1023 (device).  a = n + f with n = rint(a) and
+// |f| <= 1/2 (the subtraction is exact); 2^f by a near-minimax polynomial of
+// degree 10 (Chebyshev fit, coefficients from exp2_coeffs.py; relative error
+// about 3e-16 before rounding of the evaluation), scaled by 2^n.  Arguments
+// below -1100 are clamped (the result then underflows to 0).
+__device__ __forceinline__ double exp2_f64(double a) {
+    a = fmax(a, -1100.0);
+    const double n = __builtin_rint(a);
+    const double f = a - n;
+    double p = 7.072585949269223e-09;
+    p = __builtin_fma(p, f, 1.0208690299958306e-07);
+    p = __builtin_fma(p, f, 1.321544258792169e-06);
+    p = __builtin_fma(p, f, 1.5252657260200837e-05);
+    p = __builtin_fma(p, f, 0.0001540353044173605);
+    p = __builtin_fma(p, f, 0.0013333558230164974);
+    p = __builtin_fma(p, f, 0.009618129107606888);
+    p = __builtin_fma(p, f, 0.05550410866444772);
+    p = __builtin_fma(p, f, 0.24022650695910097);
+    p = __builtin_fma(p, f, 0.69314718055995);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+}
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Bump allocator over the caller's workspace; with base == nullptr it only
@@ -134,8 +157,8 @@ hipError_t kmvp_multi(const Prepared &P, int prec, int nrhs, double shift, const
 // Gradient pass (grad.hip): gx (n x d, original order), g_logsigma, g_loggamma
 // (device scalars) of -lam^T (dK/dtheta) w.  scratch: grad_scratch_bytes(P).
 size_t grad_scratch_bytes(const Prepared &P);
-hipError_t kmvp_grad_run(const Prepared &P, double sigma, double gamma, const double *lam, const double *w,
-                         double *gx, double *g_ls, double *g_lg, void *scratch, hipStream_t s);
+hipError_t kmvp_grad_run(const Prepared &P, int prec, double sigma, double gamma, const double *lam,
+                         const double *w, double *gx, double *g_ls, double *g_lg, void *scratch, hipStream_t s);
 // Autotuner: time the candidate column splits for (prec, d, N) on this point
 // set once per process (and KRR_TUNE_CACHE file) and keep the fastest.
 hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s);
@@ -174,6 +197,10 @@ bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop);
 int profile_begin(int max_launches);
 void profile_suspend(bool on);  // while on, profile_slot hands out no events
 int profile_end(krr_profile_stats *out);
+
+// Progress lines on stderr: KRR_PROGRESS=k prints one line every k outer steps
+// of a solve (0 or unset: silent).
+int progress_every();
 
 // bf16 conversion of a float vector (round to nearest even).
 hipError_t to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s);

@@ -10,6 +10,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <cstdio>
+
 #include "solvers.h"
 
 namespace krr {
@@ -189,6 +191,8 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
             KRR_HIP_STATUS(read_status(W.status, st, s));
             ++outer;
             k = j + 1;
+            if (progress_every() && outer % progress_every() == 0)
+                std::fprintf(stderr, "krr fgmres: outer %d cycle %d est %.3e\n", outer, cycles + 1, st.F.est);
             if (o.inner != KRR_INNER_NONE) {
                 const int it = o.inner_prec == KRR_FP64 ? st.c64.iters : st.c32.iters;
                 inner_total += it;
@@ -262,6 +266,9 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
         for (int k = 0; k < check; ++k) KRR_HIP_STATUS(cg_step<double>(P, KRR_FP64, gamma, c, W.ksc, W.R, s));
         KRR_HIP_STATUS(read_status(W.status, st, s));
         mvp64 += st.c64.iters - last_iters;
+        if (progress_every() && st.c64.iters / progress_every() != last_iters / progress_every())
+            std::fprintf(stderr, "krr cg64: iteration %d rel. residual (recursive) %.3e\n", st.c64.iters,
+                         std::sqrt(st.c64.rr / st.c64.rr0));
         last_iters = st.c64.iters;
         if (st.c64.status == KRR_BREAKDOWN) {
             result = KRR_BREAKDOWN;

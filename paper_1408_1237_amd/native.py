@@ -89,7 +89,7 @@ def load(path: str | None = None):
         lib.kmvp_gauss.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp, _sz, _vp]
         lib.kmvp_gauss_multi.argtypes = [_P(Points), _dbl, _dbl, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _sz, _vp]
         lib.kmvp_gauss_cross.argtypes = [_P(Points), _P(Points), _dbl, _i32, _vp, _vp, _vp, _sz, _vp]
-        lib.kmvp_grad.argtypes = [_P(Points), _dbl, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        lib.kmvp_grad.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         lib.cg_inner_solve.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _i32, _dbl, _P(Info), _vp, _sz, _vp]
         lib.fgmres_solve.argtypes = [_P(Points), _dbl, _dbl, _vp, _vp, _P(Opts), _P(Info), _vp, _sz, _vp]
         lib.krr_solve.argtypes = [_P(Points), _i32, _P(_dbl), _P(_dbl), _i32, _P(_vp), _P(_i64), _P(_vp), _i32,

@@ -39,8 +39,6 @@ def test_kriging_full_size_fgmres():
     assert _sampled_residual_ok(p.x, p.sigma, p.gamma, p.y, w.cpu().numpy())
 
 
-@pytest.mark.skip(reason="runs several minutes without output; enabled once the batched solve skips "
-                         "finished systems and reports progress")
 def test_batched_full_size():
     # 64 systems, N_k ~ U{1000..50000}, d in {4, 8}, 16 right-hand sides each
     from paper_1408_1237_amd import api
