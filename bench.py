@@ -122,24 +122,25 @@ def cpu_baseline(p, target_s: float = 12.0) -> dict:
             "sample": f"{nrows} rows x {p.n} sources of (K_hat + gamma I) q, FP64 on-the-fly loop, {dt:.1f} s"}
 
 
-def kernel_only(api, native, workloads, torch, p, x, reps: int) -> int:
-    """Repeated FP32 products (through the C ABI, which also prepares the points
-    each call) and one plain copy of known size for counter calibration."""
-    q = torch.from_numpy(workloads.random_vector(7, p.n)).float().cuda()
+def kernel_only(api, native, workloads, torch, p, x, reps: int, prec: str = "fp32") -> int:
+    """Repeated products (through the C ABI, which also prepares the points each
+    call) and one plain copy of known size for counter calibration."""
+    q = torch.from_numpy(workloads.random_vector(7, p.n)).cuda()
+    q = q if prec == "fp64" else q.float()
     ws = api.workspace(native.workspace_size(native.KRR_WS_KMVP, [(p.n, p.d)]), x.device)
-    api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec="fp32", ws=ws)  # tunes the plan
+    api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec=prec, ws=ws)  # tunes the plan
     torch.cuda.synchronize()
     with native.profile() as prof:
         for _ in range(reps):
-            api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec="fp32", ws=ws)
+            api.kmvp_gauss(x, p.sigma, q, shift=p.delta, prec=prec, ws=ws)
         torch.cuda.synchronize()
     a = torch.ones(64 << 20, dtype=torch.float32, device=x.device)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    st = prof.stats["fp32"]
+    st = prof.stats[prec]
     ach = st["pairs"] / (st["total_ms"] * 1e-3) / 1e9
-    print(json.dumps({"mode": "kernel-only", "n": p.n, "d": p.d, "launches": st["launches"],
+    print(json.dumps({"mode": "kernel-only", "prec": prec, "n": p.n, "d": p.d, "launches": st["launches"],
                       "avg_launch_ms": st["total_ms"] / max(st["launches"], 1), "gpair_s": ach,
                       "copy_bytes": 2 * a.numel() * 4}), flush=True)
     return 0
@@ -305,6 +306,8 @@ def main() -> int:
     ap.add_argument("--no-cg", action="store_true", help="skip the FP64 CG comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
+    ap.add_argument("--kernel-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
+                    help="precision of the --kernel-only products")
     ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
@@ -336,7 +339,7 @@ def main() -> int:
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
     if args.kernel_only:
-        return kernel_only(api, native, workloads, torch, p, x, args.kernel_only)
+        return kernel_only(api, native, workloads, torch, p, x, args.kernel_only, args.kernel_prec)
     opts = dict(inner_prec="fp32", inner_maxit=p.inner_maxit, inner_tol=0.0, delta=p.delta, restart_m=100,
                 tol=p.tol, max_outer=5000, gs="cgs2")
     paper_opts = dict(inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol, delta=p.delta, restart_m=1000,

@@ -82,7 +82,8 @@ struct KArgs {
     const double *row_anchor;
     const void *row_off;
     int64_t n_pad;               // sources
-    int ntiles, splits, tps;
+    int ntiles, splits, tps;     // tps: tiles per block, a multiple of gtiles
+    int gtiles, ngroups;         // column tiles per partial-sum group, groups
     const double *anchor;
     const double *tile_r2;
     const double *tile_nj;
@@ -96,17 +97,21 @@ struct KArgs {
 };
 
 template <int D, int PREC>
-__global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
+// The source arrays and the output are separate noalias kernel arguments: the
+// group partial sums are stored inside the tile loop, and only non-aliasing
+// arguments let the compiler keep the wave-uniform source reads on the scalar
+// unit.
+__global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a, const typename Prec<PREC>::Off *__restrict__ off,
+                                                const typename Prec<PREC>::T *__restrict__ qw,
+                                                const double *__restrict__ anchor,
+                                                typename Prec<PREC>::T *__restrict__ out) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
     using T = typename P::T;
-    using Off = typename P::Off;
     using Q = typename P::Q;
+    using Off = typename P::Off;
     constexpr int U = unroll_cols<D, PREC>();
-    const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
-    const T *__restrict__ qw = static_cast<const T *>(a.qw);
-    const double *__restrict__ anchor = a.anchor;
     const int64_t n_pad = a.n_pad;
 
     const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
@@ -189,13 +194,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a) {
                 }
             }
         }
-    }
-    T *out = static_cast<T *>(a.out);
-    if (a.splits == 1) {
-        if (i < a.n_rows && a.square) acc += static_cast<T>(a.shift) * P::q(q[i]);
-        out[i] = (i < a.n_rows) ? acc : T(0);
-    } else {
-        out[static_cast<int64_t>(by) * a.n_pad_rows + i] = acc;
+        // close a partial-sum group (fixed tile ranges: the result does not
+        // depend on how groups are dealt to blocks)
+        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
+            if (a.ngroups == 1) {
+                if (i < a.n_rows && a.square) acc += static_cast<T>(a.shift) * P::q(q[i]);
+                out[i] = (i < a.n_rows) ? acc : T(0);
+            } else {
+                out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = acc;
+            }
+            acc = T(0);
+        }
     }
 }
 
@@ -255,7 +264,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     using Q = typename P::Q;
     constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
     constexpr int RG = 4;
-    constexpr int UNR = (DK > 2 || PREC == KRR_FP64) ? 1 : 3;  // unroll of the column-step loop
+    constexpr int DR = 4 * DK;       // coordinate rows in LDS: d offsets, the constant 1, zeros
+    constexpr int LDO = TILE + 16;  // padded LDS row: coordinate rows start 16 banks apart
+    // The sources of the current column tile (offsets, and q w on folded tiles or
+    // q on wide ones) are staged in LDS, double-buffered: the block loads tile
+    // J + 1 from memory while it computes tile J.
+    __shared__ T s_off[2][DR][LDO];
+    __shared__ __align__(16) T s_q[2][TILE];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -264,11 +279,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 
     const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
-    const int lane = threadIdx.x % WAVE;
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE;
     const int r16 = lane % 16, g = lane / 16;
     // source of A row r16 within a 16-column step
     const int asrc = M::permute_rows ? (r16 % 4) * 4 + r16 / 4 : r16;
-    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (threadIdx.x / WAVE) * 64;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (tid / WAVE) * 64;
 
     double aI[D];
 #pragma unroll
@@ -286,10 +302,36 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     T acc[RG];
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) acc[rg] = T(0);
+    T *__restrict__ out = static_cast<T *>(a.out);
 
     const int J0 = by * a.tps;
     const int J1 = min(a.ntiles, J0 + a.tps);
+    // staging registers: this thread's source of the next tile
+    T st_o[D], st_q;
+    auto stage_load = [&](int J) {
+        const int64_t j = static_cast<int64_t>(J) * TILE + tid;
+#pragma unroll
+        for (int k = 0; k < D; ++k) st_o[k] = P::off(off[k * n_pad + j]);
+        st_q = a.tile_r2[J] > P::wide ? static_cast<T>(P::q(q[j])) : qw[j];
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) s_off[buf][k][tid] = st_o[k];
+        s_q[buf][tid] = st_q;
+    };
+    // rows d .. 4 DK - 1 of both buffers: the constant coordinate 1, then zeros
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int k = D; k < DR; ++k) s_off[b][k][tid] = (k == D) ? T(1) : T(0);
+    if (J0 < J1) {
+        stage_load(J0);
+        stage_store(0);
+    }
+    __syncthreads();
     for (int J = J0; J < J1; ++J) {
+        const int buf = (J - J0) & 1;
+        if (J + 1 < J1) stage_load(J + 1);
         const double r2 = a.tile_r2[J];
         const double nj = a.tile_nj[J];
         T t[RG][D];
@@ -320,21 +362,14 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 bval[rg][kc] = v;
             }
         }
-        const int64_t j0 = static_cast<int64_t>(J) * TILE;
         if (r2 <= P::wide) {
             // Software pipeline over the 16 column steps of the tile: the matrix
             // cores form the exponents of step cb + 16 (own accumulators) while
             // the VALU exponentiates and accumulates step cb.
             auto load_step = [&](int cb, T (&av)[DK], V4 &qv) {
-                const int64_t col = j0 + cb;
 #pragma unroll
-                for (int kc = 0; kc < DK; ++kc) {
-                    const int dim = 4 * kc + g;
-                    const int dsafe = dim < D ? dim : D - 1;
-                    const T o = P::off(off[dsafe * n_pad + col + asrc]);
-                    av[kc] = dim < D ? o : (dim == D ? T(1) : T(0));
-                }
-                qv = *reinterpret_cast<const V4 *>(qw + col + 4 * g);
+                for (int kc = 0; kc < DK; ++kc) av[kc] = s_off[buf][4 * kc + g][cb + asrc];
+                qv = *reinterpret_cast<const V4 *>(&s_q[buf][cb + 4 * g]);
             };
             auto exponents = [&](const T (&av)[DK], V4 (&G)[RG]) {
 #pragma unroll
@@ -350,31 +385,28 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg) acc[rg] = M::fma(P::ex2(G[rg][v]), qv[v], acc[rg]);
             };
-            T av[DK];
-            V4 qv, G[RG];
-            load_step(0, av, qv);
-            exponents(av, G);
-#pragma unroll UNR
-            for (int cb = 16; cb < TILE; cb += 16) {
-                T avn[DK];
-                V4 qn, Gn[RG];
-                load_step(cb, avn, qn);
-                exponents(avn, Gn);
-                accumulate(G, qv);
+            // 16 column steps, fully unrolled with two register sets so the
+            // pipeline needs no copies
+            T av[2][DK];
+            V4 qv[2], G[2][RG];
+            load_step(0, av[0], qv[0]);
+            exponents(av[0], G[0]);
 #pragma unroll
-                for (int rg = 0; rg < RG; ++rg) G[rg] = Gn[rg];
-                qv = qn;
+            for (int st = 1; st < TILE / 16; ++st) {
+                load_step(st * 16, av[st & 1], qv[st & 1]);
+                exponents(av[st & 1], G[st & 1]);
+                accumulate(G[(st - 1) & 1], qv[(st - 1) & 1]);
             }
-            accumulate(G, qv);
+            accumulate(G[(TILE / 16 - 1) & 1], qv[(TILE / 16 - 1) & 1]);
         } else {
             for (int cb = 0; cb < TILE; cb += 16) {
-                const int64_t col = j0 + cb + 4 * g;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
+                    const int cj = cb + 4 * g + v;
                     T oc[D];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + col + v]);
-                    const T qj = P::q(q[col + v]);
+                    for (int k = 0; k < D; ++k) oc[k] = s_off[buf][k][cj];
+                    const T qj = s_q[buf][cj];
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg) {
                         T ss = T(0);
@@ -388,22 +420,28 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 }
             }
         }
-    }
-    T *out = static_cast<T *>(a.out);
+        // close a partial-sum group (fixed tile ranges: the result does not
+        // depend on how groups are dealt to blocks)
+        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-        T sum = acc[rg];
-        sum += __shfl_xor(sum, 16, WAVE);
-        sum += __shfl_xor(sum, 32, WAVE);
-        const int64_t i = row0 + rg * 16 + r16;
-        if (g == 0) {
-            if (a.splits == 1) {
-                if (i < a.n_rows && a.square) sum += static_cast<T>(a.shift) * P::q(q[i]);
-                out[i] = (i < a.n_rows) ? sum : T(0);
-            } else {
-                out[static_cast<int64_t>(by) * a.n_pad_rows + i] = sum;
+            for (int rg = 0; rg < RG; ++rg) {
+                T sum = acc[rg];
+                sum += __shfl_xor(sum, 16, WAVE);
+                sum += __shfl_xor(sum, 32, WAVE);
+                acc[rg] = T(0);
+                const int64_t i = row0 + rg * 16 + r16;
+                if (g == 0) {
+                    if (a.ngroups == 1) {
+                        if (i < a.n_rows && a.square) sum += static_cast<T>(a.shift) * P::q(q[i]);
+                        out[i] = (i < a.n_rows) ? sum : T(0);
+                    } else {
+                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
+                    }
+                }
             }
         }
+        if (J + 1 < J1) stage_store(buf ^ 1);
+        __syncthreads();
     }
 }
 
@@ -423,7 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_prescale(int64_t n_pad, const void *q
 
 // y_i = sum_s parts[s][i] (+ shift q_i when square) for i < n, 0 on the padding.
 template <int PREC>
-__global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad, int splits, const void *parts_,
+__global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad, int ngroups, const void *parts_,
                                                        const void *q_, double shift, int square, void *y_,
                                                        const int *active) {
     if (active != nullptr && *active == 0) return;
@@ -439,26 +477,37 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad,
         return;
     }
     T s = parts[i];
-    for (int k = 1; k < splits; ++k) s += parts[static_cast<int64_t>(k) * n_pad + i];
+    for (int k = 1; k < ngroups; ++k) s += parts[static_cast<int64_t>(k) * n_pad + i];
     y[i] = square ? s + static_cast<T>(shift) * P::q(q[i]) : s;
 }
 
 // ---------------------------------------------------------------- plans and tuning
 
-// Column splits: enough blocks to fill the chip several times over for small
-// N; few splits once the row tiles alone give thousands of blocks.
-int kmvp_max_splits(const Prepared &P) {
-    int m = P.ntiles / 2 > 1 ? P.ntiles / 2 : 1;
-    const int cap = P.ntiles >= 2048 ? 4 : 32;
-    return m < cap ? m : cap;
+// Partial-sum groups: the sources are cut into groups of gtiles consecutive
+// column tiles (a function of the source count only), each group's sum is
+// formed in one block in a fixed order and the groups are added in order, so a
+// product's result does not depend on the launch shape the autotuner picks.
+int kmvp_group_tiles(const Prepared &C) {
+    const int g = C.ntiles / 32;
+    return g < 1 ? 1 : (g > 16 ? 16 : g);
 }
+
+int kmvp_ngroups(const Prepared &C) {
+    const int gt = kmvp_group_tiles(C);
+    return (C.ntiles + gt - 1) / gt;
+}
+
+// Column splits (blocks per row tile): from 1 to the group count.
+int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
 static KmvpPlan plan_for(const Prepared &P, int splits) {
     KmvpPlan pl;
+    const int ng = kmvp_ngroups(P), gt = kmvp_group_tiles(P);
     if (splits < 1) splits = 1;
-    if (splits > kmvp_max_splits(P)) splits = kmvp_max_splits(P);
-    pl.tiles_per_split = (P.ntiles + splits - 1) / splits;
-    pl.splits = (P.ntiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
+    if (splits > ng) splits = ng;
+    const int gpb = (ng + splits - 1) / splits;  // groups per block
+    pl.tiles_per_split = gpb * gt;
+    pl.splits = (ng + gpb - 1) / gpb;
     return pl;
 }
 
@@ -503,6 +552,12 @@ void tune_cache_append(const TuneKey &k, int splits) {
 }  // namespace
 
 KmvpPlan kmvp_plan(const Prepared &P, int prec) {
+    // KRR_KMVP_SPLITS=k forces k column splits (used to check that results do
+    // not depend on the launch shape)
+    if (const char *v = std::getenv("KRR_KMVP_SPLITS")) {
+        const int k = std::atoi(v);
+        if (k > 0) return plan_for(P, k);
+    }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
     auto it = g_tuned.find(TuneKey{prec, P.dpad, P.ntiles});
@@ -537,7 +592,10 @@ static hipError_t launch_kmvp(const KArgs &a, hipStream_t s) {
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+    using P = Prec<PREC>;
+    hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                       static_cast<const typename P::Off *>(a.off), static_cast<const typename P::T *>(a.qw),
+                       a.anchor, static_cast<typename P::T *>(a.out));
     return hipGetLastError();
 }
 
@@ -575,6 +633,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.ntiles = C.ntiles;
     a.splits = pl.splits;
     a.tps = pl.tiles_per_split;
+    a.gtiles = kmvp_group_tiles(C);
+    a.ngroups = kmvp_ngroups(C);
     a.anchor = C.anchor;
     a.tile_r2 = C.tile_r2;
     a.tile_nj = C.tile_nj;
@@ -583,7 +643,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.shift = square ? shift : 0.0;
     a.square = square ? 1 : 0;
     a.active = active;
-    a.out = pl.splits > 1 ? sc.parts : y;
+    a.out = a.ngroups > 1 ? sc.parts : y;
     const void *w = prec == KRR_FP64 ? static_cast<const void *>(C.w64)
                     : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
                                        : static_cast<const void *>(C.w16);
@@ -619,19 +679,20 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     }
     KRR_HIP(e);
     if (timed) KRR_HIP(hipEventRecord(ev1, s));
-    if (pl.splits > 1) {
+    if (a.ngroups > 1) {
         const int sq = square ? 1 : 0;
+        const int ng = a.ngroups;
         switch (prec) {
             case KRR_FP64:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
                                    q, shift, sq, y, active);
                 break;
             case KRR_FP32:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
                                    q, shift, sq, y, active);
                 break;
             default:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, pl.splits, sc.parts,
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
                                    q, shift, sq, y, active);
                 break;
         }
@@ -650,13 +711,7 @@ hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q,
 hipError_t kmvp_cross_sorted(const Prepared &T, const Prepared &S, int prec, const void *q, void *y,
                              const KmvpScratch &sc, hipStream_t s) {
     const int target_blocks = 4096;
-    int splits = (target_blocks + T.ntiles - 1) / T.ntiles;
-    const int mx = kmvp_max_splits(S);
-    if (splits > mx) splits = mx;
-    if (splits < 1) splits = 1;
-    KmvpPlan pl;
-    pl.tiles_per_split = (S.ntiles + splits - 1) / splits;
-    pl.splits = (S.ntiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
+    const KmvpPlan pl = plan_for(S, (target_blocks + T.ntiles - 1) / T.ntiles);
     return kmvp_run(T, S, prec, pl, 0.0, q, y, sc, nullptr, true, s);
 }
 

@@ -69,6 +69,22 @@ constexpr int multi_rb() {
     return (PREC == KRR_FP64 ? 2 : 1) * D <= 16 ? 4 : (PREC == KRR_FP64 ? 2 : 1) * D <= 32 ? 2 : 1;
 }
 
+// Global-address-space view of a pointer (the batched kernel reads its
+// arguments from device memory, where the compiler cannot infer the space).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gp(const void *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+// Columns staged per LDS chunk: the two buffers of offsets and 16 prescaled
+// right-hand sides stay within about 40 KB, so several blocks share a CU.
+template <int D, int PREC>
+constexpr int multi_chunk() {
+    constexpr int bytes = (D + 16) * (PREC == KRR_FP64 ? 8 : 4);
+    constexpr int fit = 20480 / bytes;
+    return fit >= 256 ? 256 : fit >= 128 ? 128 : fit >= 64 ? 64 : 32;
+}
+
 template <int D, int PREC>
 __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int rbk) {
     using P = MP<PREC>;
@@ -76,20 +92,64 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
     using Off = typename P::Off;
     using Acc = typename P::Acc;
     constexpr int RB = multi_rb<D, PREC>();
-    const Off *__restrict__ off = static_cast<const Off *>(a.off);
-    const T *__restrict__ qwt = static_cast<const T *>(a.qwt);
+    constexpr int SC = multi_chunk<D, PREC>();
+    constexpr int CPT = TILE / SC;  // chunks per column tile
+    constexpr int LDO = SC + 16;
+    constexpr int UN = D > 16 ? 1 : 4;  // unroll of the column steps (register budget)
+    // The sources of the current column chunk (offsets and the 16 prescaled
+    // right-hand sides) are staged in LDS, double-buffered: the block loads
+    // chunk c + 1 from memory while it computes chunk c.
+    __shared__ T s_off[2][D][LDO];
+    __shared__ __align__(16) T s_b[2][SC][16];
+    const auto off = gp<Off>(a.off);
+    const auto qb = gp<T>(a.qwt) + static_cast<int64_t>(rbk) * a.n_pad * 16;
+    const auto anchor = gp<double>(a.anchor);
+    const auto tile_r2 = gp<double>(a.tile_r2);
+    const auto tile_nj = gp<double>(a.tile_nj);
     const int64_t n_pad = a.n_pad;
-    const int wave = threadIdx.x / WAVE;
-    const int lane = threadIdx.x % WAVE;
+    const int tid = threadIdx.x;
+    const int wave = tid / WAVE;
+    const int lane = tid % WAVE;
     const int r16 = lane % 16, g = lane / 16;
-    const T *qb = qwt + static_cast<int64_t>(rbk) * n_pad * 16;
     T *parts = static_cast<T *>(a.parts) + (static_cast<int64_t>(by) * a.nrb + rbk) * n_pad * 16;
-    const int J0 = by * a.tps;
-    const int J1 = min(a.ntiles, J0 + a.tps);
+    const int C0 = by * a.tps * CPT;
+    const int C1 = min(a.ntiles, (by + 1) * a.tps) * CPT;
 
     double aI[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) aI[k] = a.anchor[static_cast<int64_t>(bx) * D + k];
+    for (int k = 0; k < D; ++k) aI[k] = anchor[static_cast<int64_t>(bx) * D + k];
+
+    // staging: thread tid loads (source, coordinate / right-hand side) entries
+    // of the chunk; SC * (D + 16) entries over the 256 threads
+    constexpr int NO = (SC * D + BLOCK - 1) / BLOCK;   // offsets per thread
+    constexpr int NB = (SC * 16 + BLOCK - 1) / BLOCK;  // rhs values per thread
+    T st_o[NO], st_b[NB];
+    auto stage_load = [&](int cidx) {
+        const int64_t j0 = static_cast<int64_t>(cidx) * SC;
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int e = u * BLOCK + tid;  // e = k * SC + col
+            const int k = e / SC, col = e % SC;
+            st_o[u] = (e < SC * D) ? P::off(off[k * n_pad + j0 + col]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = u * BLOCK + tid;  // e = col * 16 + r
+            st_b[u] = qb[j0 * 16 + e];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int e = u * BLOCK + tid;
+            if (e < SC * D) s_off[buf][e / SC][e % SC] = st_o[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = u * BLOCK + tid;
+            s_b[buf][e / 16][e % 16] = st_b[u];
+        }
+    };
 
     for (int pass = 0; pass < 4 / RB; ++pass) {
         const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + wave * 64 + pass * RB * 16;
@@ -102,9 +162,17 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
 
-        for (int J = J0; J < J1; ++J) {
-            const double r2 = a.tile_r2[J];
-            const double nj = a.tile_nj[J];
+        if (C0 < C1) {
+            stage_load(C0);
+            stage_store(0);
+        }
+        __syncthreads();
+        for (int ci = C0; ci < C1; ++ci) {
+            const int buf = (ci - C0) & 1;
+            if (ci + 1 < C1) stage_load(ci + 1);
+            const int J = ci / CPT;
+            const double r2 = tile_r2[J];
+            const double nj = tile_nj[J];
             T t[RB][D];
             T c[RB];
 #pragma unroll
@@ -113,26 +181,25 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     const double td =
-                        (aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rb][k]);
+                        (aI[k] - anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rb][k]);
                     t[rb][k] = static_cast<T>(td);
                     const double tk = static_cast<double>(t[rb][k]);
                     tt = __builtin_fma(tk, tk, tt);
                 }
                 c[rb] = static_cast<T>(-tt - nj);
             }
-            const int64_t j0 = static_cast<int64_t>(J) * TILE + g;
             if (r2 <= P::wide) {
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int k = 0; k < D; ++k) t[rb][k] = t[rb][k] + t[rb][k];
-#pragma unroll 4
-                for (int s = 0; s < TILE; s += 4) {
-                    const int64_t j = j0 + s;
+#pragma unroll UN
+                for (int st = 0; st < SC; st += 4) {
+                    const int cj = st + g;
                     T oc[D];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + j]);
-                    const T b = qb[j * 16 + r16];
+                    for (int k = 0; k < D; ++k) oc[k] = s_off[buf][k][cj];
+                    const T b = s_b[buf][cj][r16];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
                         T arg = P::fma(t[rb][0], oc[0], c[rb]);
@@ -142,13 +209,13 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
                     }
                 }
             } else {
-#pragma unroll 2
-                for (int s = 0; s < TILE; s += 4) {
-                    const int64_t j = j0 + s;
+#pragma unroll 1
+                for (int st = 0; st < SC; st += 4) {
+                    const int cj = st + g;
                     T oc[D];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) oc[k] = P::off(off[k * n_pad + j]);
-                    const T b = qb[j * 16 + r16];
+                    for (int k = 0; k < D; ++k) oc[k] = s_off[buf][k][cj];
+                    const T b = s_b[buf][cj][r16];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
                         T ss = T(0);
@@ -161,6 +228,8 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
                     }
                 }
             }
+            if (ci + 1 < C1) stage_store(buf ^ 1);
+            __syncthreads();
         }
         // accumulator layout: FP32 lane l holds rows 4 (l / 16) + v; FP64 lane l
         // holds rows l / 16 + 4 v (right-hand side l % 16 in both)

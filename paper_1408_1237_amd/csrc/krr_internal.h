@@ -128,7 +128,8 @@ struct KmvpPlan {
     int splits = 1;          // column splits
     int tiles_per_split = 0;
 };
-// Scratch of one product: partial sums (kmvp_max_splits x n_pad, 8 bytes each)
+// Scratch of one product: group partial sums (kmvp_max_splits = group count x
+// n_pad, 8 bytes each)
 // and the prescaled sources q_j w_j (n_pad, 8 bytes each).
 struct KmvpScratch {
     void *parts = nullptr;

@@ -176,3 +176,22 @@ def test_matrix_core_exponent_matches_valu_kernel(monkeypatch, prec, d):
     want = oracle.mvp(x, sigma, q, shift=0.05)
     assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
     assert _relerr(a, b) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,d", [(9000, 3), (20000, 2), (5000, 16), (3000, 20)])
+def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
+    # partial sums are formed over fixed groups of column tiles, so the product
+    # is bitwise the same for every split count the autotuner may pick
+    x = workloads.random_points(80 + d, n, d, 3.0)
+    q = workloads.random_vector(81 + d, n)
+    sigma = 0.5 * np.sqrt(d)
+    outs = []
+    for k in ("1", "2", "5", "1000"):
+        monkeypatch.setenv("KRR_KMVP_SPLITS", k)
+        outs.append(_gpu_mvp(x, sigma, q, 0.01, prec))
+    monkeypatch.delenv("KRR_KMVP_SPLITS")
+    outs.append(_gpu_mvp(x, sigma, q, 0.01, prec))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert _relerr(outs[0], oracle.mvp(x, sigma, q, shift=0.01)) <= TOL[prec]
