@@ -33,39 +33,54 @@ if ROOT not in sys.path:
 
 METRIC = "kernel-MVP pairs/s + time to 1e-6 residual, mixed-prec FGMRES vs FP64 CG"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes issue one FP32 VALU op per lane per clock
-# (packed FP32 excluded) at 2.4 GHz; FP32 matrix cores 157.3 TFLOP/s dense.
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-MFMA_F32_MACS = 157.3e12 / 2
+# MI355X issue model, from the unit counts (256 CUs x 4 SIMDs, 16 lanes each,
+# 2.4 GHz): a wave64 VALU instruction occupies its SIMD 4 cycles (FP32 and FP64
+# FMA alike; packed FP32 is not used), a transcendental (v_exp_f32) 8 cycles
+# (half rate), a v_mfma_f32_16x16x4f32 32 cycles and a v_mfma_f64_16x16x4f64
+# 64 cycles (157.3 and 78.6 TFLOP/s dense).  Matrix-core and VALU instructions
+# of one SIMD are counted one after the other: the issue-rate probe
+# (krr_probe_issue_rates) measures their mix at the serial sum, not at the
+# larger of the two.
+SIMD_CYCLES_S = 256 * 4 * 2.4e9
+VALU_LANE_OPS = SIMD_CYCLES_S * 16          # FMA lane-ops/s
+C_FMA, C_EXP, C_MFMA32, C_MFMA64 = 4, 8, 32, 64
+C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
-    """Peak pairs/s of the FP32 / BF16-input product kernel that runs for dimension d.
+    """Peak pairs/s of the product kernel that runs for dimension d and precision.
 
-    d <= 16 (matrix-core exponent): per pair one exp2 and one FMA on the VALU and
-    4 ceil((d+1)/4) FP32 MACs on the matrix cores; the smaller of the two rates.
-    Otherwise (VALU kernel): d + 2 VALU issue slots per pair.
+    d <= 16 (matrix-core exponent kernel), per 1024 pairs (one wave, one 16-column
+    step): 4 ceil((d+1)/4) 16x16x4 matrix-core operations plus, per lane, 16
+    exponentials and 16 FMAs.  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs
+    and one exponential per lane.
     """
-    tag = "BF16" if prec == "bf16" else "FP32"
+    tag = {"fp64": "FP64", "bf16": "BF16"}.get(prec, "FP32")
     if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
         dk = (d + 4) // 4
-        valu = VALU_LANE_OPS / 2
-        mfma = MFMA_F32_MACS / (4 * dk)
-        rule = ("min(256 CU x 64 lanes x 2.4 GHz / 2 VALU ops per pair, "
-                f"157.3 TFLOP/s / (2 x {4 * dk} MACs per pair))")
-        return min(valu, mfma), rule, f"k_kmvp_mg<{d}, {tag}>"
-    return VALU_LANE_OPS / (d + 2), "256 CU x 64 lanes x 2.4 GHz / (d + 2) VALU slots per pair", f"k_kmvp<{d}, {tag}>"
+        if prec == "fp64":
+            cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64 + C_FMA)
+        else:
+            cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
+        rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
+                f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mg<{d}, {tag}>"
+    if prec == "fp64":
+        cyc = (d + 1) * C_FMA + C_EXP2_F64
+    else:
+        cyc = (d + 1) * C_FMA + C_EXP
+    rule = f"64 pairs per {cyc} SIMD cycles: (d + 1) FMAs + exp2 per lane; 1024 SIMDs x 2.4 GHz"
+    return SIMD_CYCLES_S * 64 / cyc, rule, f"k_kmvp<{d}, {tag}>"
 
 
 def multi_peak(d: int) -> tuple[float, str, str]:
-    """Peak pair x RHS products/s of the FP32 16-RHS product: 16 MACs per pair on
-    the matrix cores (157.3 TFLOP/s), the kernel value on the VALU (d + 2 slots per
-    pair, shared by the 16 RHS); the smaller of the two."""
-    mfma = MFMA_F32_MACS  # one MAC per pair x RHS
-    valu = VALU_LANE_OPS / (d + 2) * 16
-    rule = "min(157.3 TFLOP/s / 2 FLOP per pair x RHS, 256 CU x 64 lanes x 2.4 GHz / (d + 2) slots x 16 RHS)"
-    return min(mfma, valu), rule, f"k_kmvp_multi<{d}, FP32>"
-
+    """Peak pair x RHS products/s of the FP32 16-RHS product: per 4 columns x 64
+    rows (one wave step) 4 matrix-core operations (16 x 4 x 16 MACs each) and,
+    per lane, d FMAs and one exponential, serial issue."""
+    cyc = 4 * C_MFMA32 + 4 * (d * C_FMA + C_EXP)
+    rule = (f"4096 pair x RHS per {cyc} SIMD cycles: 4 16x16x4 matrix-core ops + 4 x (d FMAs + exp2) per lane, "
+            "serial issue; 1024 SIMDs x 2.4 GHz")
+    return SIMD_CYCLES_S * 4096 / cyc, rule, f"k_kmvp_multi<{d}, FP32>"
 
 
 def log(msg: str) -> None:
@@ -73,10 +88,11 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the product kernels' source; the committed counter summary is used
+    only while it matches."""
     h = hashlib.sha256()
-    for f in ("kmvp.hip", "krr_internal.h"):
-        with open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", "kmvp.hip"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -283,7 +299,7 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
     rate = float(p.n) ** 2 / (times["fp64"] * 1e-3)
     # FP64 pair loop: 3d + 3 slots plus the exp2_f64 sequence (clamp, rint, subtract,
     # 10 FMAs, convert, ldexp: 15); FP32: 3d + 3
-    peak = VALU_LANE_OPS / (3 * d + 18)
+    peak = SIMD_CYCLES_S * 64 / ((3 * d + 3) * C_FMA + C_EXP2_F64)
     log(f"gradient pass: fp64 {times['fp64']:.2f} ms ({rate / 1e9:.1f} Gpair/s), fp32 {times['fp32']:.2f} ms")
     return {"metric": METRIC, "value": rate, "unit": "pairs/s", "n_gpus": 1, "dtype": "f64",
             "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
@@ -294,8 +310,8 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
             "roofline": {"bound": "alu", "achieved": round(rate / 1e9, 1), "peak": round(peak / 1e9, 1),
                          "unit": "Gpair/s", "frac": round(rate / peak, 4), "traffic": None,
                          "kernel": f"k_grad<{d}, true, double>",
-                         "peak_rule": "256 CU x 64 lanes x 2.4 GHz / (3d + 18) FP64 VALU slots per pair "
-                                      "(time includes prep and the epilogue kernels)"}}
+                         "peak_rule": "64 pairs per (3d + 3) FMA + exp2_f64 SIMD cycles (4 each, exp2_f64 60); "
+                                      "1024 SIMDs x 2.4 GHz (time includes prep and the epilogue kernels)"}}
 
 
 def main() -> int:
@@ -379,16 +395,22 @@ def main() -> int:
     achieved = f32["pairs"] / (f32["total_ms"] * 1e-3) / 1e9
     peak_pairs, peak_rule, kname = product_peak(p.d)
     peak = peak_pairs / 1e9
+    peak64, _, kname64 = product_peak(p.d, "fp64")
+    ach64 = f64["pairs"] / max(f64["total_ms"], 1e-9) / 1e6
     traffic = read_traffic("kmvp_fp32_d3_kriging_counters.txt")
+    probe = api.probe_issue_rates()
     roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gpair/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": kname, "launches": f32["launches"],
                 "avg_launch_ms": round(f32["total_ms"] / max(f32["launches"], 1), 4),
                 "peak_rule": peak_rule,
-                "fp64_kernel_gpair_s": round(f64["pairs"] / max(f64["total_ms"], 1e-9) / 1e6, 1),
-                "fp64_avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4)}
+                "fp64_kernel": kname64, "fp64_achieved": round(ach64, 1), "fp64_peak": round(peak64 / 1e9, 1),
+                "fp64_frac": round(ach64 * 1e9 / peak64, 4),
+                "fp64_avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4),
+                "issue_probe": {k: float(f"{v:.4g}") for k, v in probe.items()}}
     log(f"kernel fp32: {f32['launches']} launches, {roofline['avg_launch_ms']} ms avg, {achieved:.0f} Gpair/s "
-        f"({100 * achieved / peak:.1f}% of {peak:.0f}); fp64: {roofline['fp64_kernel_gpair_s']} Gpair/s")
+        f"({100 * achieved / peak:.1f}% of {peak:.0f}); fp64: {ach64:.0f} Gpair/s "
+        f"({100 * roofline['fp64_frac']:.1f}% of {peak64 / 1e9:.0f}); probe {roofline['issue_probe']}")
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

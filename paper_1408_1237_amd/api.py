@@ -192,3 +192,15 @@ def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | N
     N.check(rc, "krr_solve")
     Ws = [W.reshape(-1) if Y.dim() == 1 else W for W, Y in zip(Ws, Ys)]
     return Ws, [i.as_dict() for i in infos]
+
+
+def probe_issue_rates(device="cuda") -> dict:
+    """Measured issue rates of the device (see krr_probe_issue_rates): FMA
+    lane-ops/s, exp2+FMA pairs/s, matrix-core pairs/s, matrix-core exponent mix
+    pairs/s."""
+    lib = N.load()
+    ws = workspace(int(lib.krr_probe_workspace_size()), torch.device(device))
+    rates = (ctypes.c_double * 4)()
+    N.check(lib.krr_probe_issue_rates(rates, ws.data_ptr(), ws.numel(), _stream()), "krr_probe_issue_rates")
+    return {"fma_lane_ops_s": rates[0], "exp_fma_pairs_s": rates[1], "mfma_pairs_s": rates[2],
+            "mg_mix_pairs_s": rates[3]}

@@ -475,4 +475,14 @@ int krr_profile_begin(int32_t max_launches) { return profile_begin(max_launches)
 
 int krr_profile_end(krr_profile_stats *out) { return profile_end(out); }
 
+size_t krr_probe_workspace_size(void) { return probe_workspace_bytes() + 256; }
+
+int krr_probe_issue_rates(double *rates, void *ws, size_t ws_bytes, krr_stream_t stream) {
+    if (rates == nullptr) return KRR_EINVAL;
+    if (ws == nullptr || ws_bytes < krr_probe_workspace_size()) return KRR_EWORKSPACE;
+    ws = align_ws(ws, ws_bytes);
+    KRR_HIP_STATUS(probe_issue_rates(rates, ws, reinterpret_cast<hipStream_t>(stream)));
+    return KRR_OK;
+}
+
 }  // extern "C"

@@ -199,6 +199,11 @@ int profile_begin(int max_launches);
 void profile_suspend(bool on);  // while on, profile_slot hands out no events
 int profile_end(krr_profile_stats *out);
 
+// Issue-rate probe (probe.hip): FMA lane-ops/s, exp2+FMA pairs/s, matrix-core
+// pairs/s, matrix-core exponent mix pairs/s.  ws: probe_workspace_bytes().
+size_t probe_workspace_bytes();
+hipError_t probe_issue_rates(double *rates, void *ws, hipStream_t s);
+
 // Progress lines on stderr: KRR_PROGRESS=k prints one line every k outer steps
 // of a solve (0 or unset: silent).
 int progress_every();

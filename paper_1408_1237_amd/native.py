@@ -26,7 +26,8 @@ KRR_MAX_DIM = 64
 
 EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
-            "krr_solve", "krr_profile_begin", "krr_profile_end")
+            "krr_solve", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
+            "krr_probe_issue_rates")
 
 
 class Points(ctypes.Structure):
@@ -97,6 +98,10 @@ def load(path: str | None = None):
         lib.krr_profile_begin.argtypes = [_i32]
         lib.krr_profile_begin.restype = ctypes.c_int
         lib.krr_profile_end.argtypes = [_P(ProfileStats)]
+        lib.krr_probe_workspace_size.restype = _sz
+        lib.krr_probe_workspace_size.argtypes = []
+        lib.krr_probe_issue_rates.restype = ctypes.c_int
+        lib.krr_probe_issue_rates.argtypes = [_P(_dbl), _vp, _sz, _vp]
         lib.krr_profile_end.restype = ctypes.c_int
         for name in ("kmvp_gauss", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
                      "fgmres_solve", "krr_solve"):

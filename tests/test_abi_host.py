@@ -91,3 +91,11 @@ def test_invalid_arguments_rejected_before_any_launch():
     wp = (ctypes.c_void_p * 1)(0x3000)
     assert lib.krr_solve(ctypes.byref(p), 1, sig, gam, 1, yp, None, wp, 9, None, None, ws, 1 << 30, None) == N.KRR_EINVAL
     assert lib.krr_solve(ctypes.byref(p), 1, sig, gam, 0, yp, None, wp, 0, None, None, ws, 1 << 30, None) == N.KRR_EINVAL
+
+
+def test_probe_rejects_bad_arguments_on_the_host():
+    lib = N.load()
+    assert lib.krr_probe_workspace_size() > 0
+    rates = (ctypes.c_double * 4)()
+    assert lib.krr_probe_issue_rates(rates, None, 0, None) == N.KRR_EWORKSPACE
+    assert lib.krr_probe_issue_rates(None, None, 0, None) == N.KRR_EINVAL
