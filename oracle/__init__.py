@@ -68,6 +68,11 @@ def _load():
                                       _dp, _dp, _dp, _ip]
             lib.or_grad.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _dp, _dp, _dp, _dp]
             lib.or_grad_rows.argtypes = [_i64, _int, _dp, _dbl, _dp, _dp, _i64, _lp, _dp]
+            lib.or_matern.restype = _dbl
+            lib.or_matern.argtypes = [_dp, _dp, _int, _dbl]
+            lib.or_matern_matrix.argtypes = [_i64, _i64, _int, _dp, _dp, _dbl, _dp]
+            lib.or_matern_mvp.argtypes = [_i64, _i64, _int, _dp, _dp, _dbl, _dbl, _dp, _dp]
+            lib.or_matern_mvp_rows.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _i64, _lp, _dp]
             _lib = lib
     return _lib
 
@@ -256,3 +261,57 @@ def true_relres(x, sigma: float, gamma: float, y, w) -> float:
     """||y - (K_hat + gamma I) w|| / ||y|| with the on-the-fly FP64 product."""
     r = _f64(y) - mvp(x, sigma, _f64(w), gamma)
     return float(np.linalg.norm(r) / np.linalg.norm(y))
+
+
+# ---------------------------------------------------------------- Matern-3/2 (section 6)
+
+def matern(a, b, h: float) -> float:
+    """k(a, b) = (1 + sqrt(3) r) exp(-sqrt(3) r), r = ||a - b|| / h (eq. MaternKernel)."""
+    a = _f64(a).ravel()
+    b = _f64(b).ravel()
+    return _load().or_matern(_p(a), _p(b), a.size, float(h))
+
+
+def matern_matrix(xt, h: float, xs=None) -> np.ndarray:
+    """Explicit Matern K_hat; K[i, j] = k(xt_i, xs_j), xs defaults to xt."""
+    xt, nt, d = _pts(xt)
+    xs, ns, ds = _pts(xt if xs is None else xs)
+    assert ds == d
+    K = np.empty((nt, ns))
+    _load().or_matern_matrix(nt, ns, d, _p(xt), _p(xs), float(h), _p(K))
+    return K
+
+
+def matern_mvp(x, h: float, q, shift: float = 0.0, xs=None) -> np.ndarray:
+    """On-the-fly Matern y = K_hat q + shift q (square), or K_hat(x, xs) q."""
+    xt, nt, d = _pts(x)
+    if xs is None:
+        xs_, ns = xt, nt
+    else:
+        xs_, ns, ds = _pts(xs)
+        assert ds == d
+        if shift != 0.0:
+            raise ValueError("shift requires a square product")
+    q = _f64(q)
+    assert q.shape == (ns,)
+    y = np.empty(nt)
+    _load().or_matern_mvp(nt, ns, d, _p(xt), _p(xs_), float(h), float(shift), _p(q), _p(y))
+    return y
+
+
+def matern_mvp_rows(x, h: float, q, rows, shift: float = 0.0) -> np.ndarray:
+    """((K_hat + shift I) q)[rows] with the Matern kernel."""
+    x, n, d = _pts(x)
+    q = _f64(q)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty(rows.size)
+    _load().or_matern_mvp_rows(n, d, _p(x), float(h), float(shift), _p(q), rows.size,
+                               rows.ctypes.data_as(_lp), _p(out))
+    return out
+
+
+def matern_direct_solve(x, h: float, gamma: float, y) -> np.ndarray:
+    """w = (K_hat + gamma I)^{-1} y with the explicit Matern matrix and Cholesky."""
+    K = matern_matrix(x, h)
+    K[np.diag_indices_from(K)] += gamma
+    return chol_solve(cholesky(K), y)

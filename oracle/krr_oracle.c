@@ -18,7 +18,8 @@
  * Notation follows the paper: X = {x_1..x_N} in R^d, K_hat_ij = k(x_i, x_j)
  * (eq. kernelMatrix, section 1) with the Gaussian k (eq. Gaussian, section 1),
  * K = K_hat + gamma I (eq. RegKernel), preconditioner M = K_hat + delta I
- * (section 5, the proposed preconditioner).
+ * (section 5, the proposed preconditioner).  The Matern kernel of section 6
+ * (eq. MaternKernel) has its own kernel sums (or_matern_*).
  */
 #include <math.h>
 #include <stdint.h>
@@ -110,6 +111,60 @@ void or_mvp_multi(int64_t n, int d, const double *x, double sigma, double shift,
 {
     for (int r = 0; r < nrhs; ++r)
         or_mvp(n, n, d, x, x, sigma, shift, Q + r * ldq, Y + r * ldy);
+}
+
+/* Matern kernel with smoothness 3/2, eq. (MaternKernel), section 6 (the
+ * non-Gaussian kernel of Table 2):
+ *   k(a, b) = (1 + sqrt(3) r) exp(-sqrt(3) r),  r = ||a - b|| / h. */
+double or_matern(const double *a, const double *b, int d, double h)
+{
+    double r2 = 0.0;
+    for (int t = 0; t < d; ++t) {
+        double diff = a[t] - b[t];
+        r2 += diff * diff;
+    }
+    double s = sqrt(3.0) * sqrt(r2) / h;
+    return (1.0 + s) * exp(-s);
+}
+
+/* Explicit Matern kernel matrix (eq. kernelMatrix with eq. MaternKernel),
+ * K[i*ns + j] = k(xt_i, xs_j). */
+void or_matern_matrix(int64_t nt, int64_t ns, int d, const double *xt,
+                      const double *xs, double h, double *K)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; ++i)
+        for (int64_t j = 0; j < ns; ++j)
+            K[i * ns + j] = or_matern(xt + i * d, xs + j * d, d, h);
+}
+
+/* On-the-fly Matern sum y_i = sum_j k(xt_i, xs_j) q_j (+ shift q_i when the
+ * two point sets are the same set, as in or_mvp). */
+void or_matern_mvp(int64_t nt, int64_t ns, int d, const double *xt, const double *xs,
+                   double h, double shift, const double *q, double *y)
+{
+    const int square = (nt == ns && xt == xs);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; ++i) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < ns; ++j)
+            acc += or_matern(xt + i * d, xs + j * d, d, h) * q[j];
+        y[i] = square ? acc + shift * q[i] : acc;
+    }
+}
+
+/* ((K_hat + shift I) q)_{rows[k]} with the Matern kernel. */
+void or_matern_mvp_rows(int64_t n, int d, const double *x, double h, double shift,
+                        const double *q, int64_t nrows, const int64_t *rows, double *y_rows)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k];
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            acc += or_matern(x + i * d, x + j * d, d, h) * q[j];
+        y_rows[k] = acc + shift * q[i];
+    }
 }
 
 static double dot(int64_t n, const double *a, const double *b)

@@ -373,3 +373,54 @@ def test_workload_shapes_and_determinism():
     assert all(pp.y.shape == (pp.n, 16) for pp in b)
     g = workloads.gp_regression(n=1000)
     assert g.x.shape == (1000, 16) and g.sigma == 4.0
+
+
+# ---------------------------------------------------------------- Matern-3/2 (eq. MaternKernel, section 6)
+
+def test_matern_two_point_hand_values():
+    rows = [l for l in open(os.path.join(GOLDEN, "matern_two_point.txt")) if not l.startswith("#")]
+    ax, ay, bx, by, h, k, q0, q1, s, y0, y1 = [float(v) for v in rows[0].split()]
+    a, b = np.array([ax, ay]), np.array([bx, by])
+    assert oracle.matern(a, b, h) == pytest.approx(k, rel=1e-15)
+    x = np.stack([a, b])
+    y = oracle.matern_mvp(x, h, np.array([q0, q1]), shift=s)
+    assert y == pytest.approx([y0, y1], rel=1e-15)
+
+
+def test_matern_matches_scikit_learn():
+    # an independent implementation of the same kernel (nu = 3/2)
+    from sklearn.gaussian_process.kernels import Matern
+    x = workloads.random_points(90, 60, 4, 2.0)
+    xs = workloads.random_points(91, 45, 4, 2.0)
+    h = 1.7
+    want = Matern(length_scale=h, nu=1.5)(x, xs)
+    assert np.allclose(oracle.matern_matrix(x, h, xs), want, rtol=1e-13, atol=1e-15)
+
+
+def test_matern_special_cases_and_positive_definiteness():
+    # coincident points: K_hat = 1 1^T; far points: K_hat = I; random sets: SPD
+    x0 = np.zeros((5, 3))
+    assert np.array_equal(oracle.matern_matrix(x0, 0.7), np.ones((5, 5)))
+    far = np.arange(6, dtype=float).reshape(-1, 1) * 1e3
+    assert np.allclose(oracle.matern_matrix(far, 1.0), np.eye(6), atol=1e-300)
+    x = workloads.random_points(92, 300, 2, 1.0)
+    K = oracle.matern_matrix(x, 0.3)
+    assert np.array_equal(K, K.T)
+    assert np.linalg.eigvalsh(K).min() > -1e-12
+    oracle.cholesky(K + 1e-10 * np.eye(300))
+
+
+def test_matern_on_the_fly_equals_explicit_and_direct_solve():
+    x = workloads.random_points(93, 400, 3, 1.0)
+    q = workloads.random_vector(94, 400)
+    h, g = 0.4, 1e-2
+    K = oracle.matern_matrix(x, h)
+    assert np.allclose(oracle.matern_mvp(x, h, q, shift=g), K @ q + g * q, rtol=1e-12, atol=1e-12)
+    rows = np.array([0, 17, 399])
+    assert np.allclose(oracle.matern_mvp_rows(x, h, q, rows, shift=g), (K @ q + g * q)[rows], rtol=1e-12)
+    w = oracle.matern_direct_solve(x, h, g, q)
+    assert np.linalg.norm(K @ w + g * w - q) <= 1e-10 * np.linalg.norm(q)
+    # the rectangular sum has no shift term
+    xs = workloads.random_points(95, 50, 3, 1.0)
+    qs = workloads.random_vector(96, 50)
+    assert np.allclose(oracle.matern_mvp(x, h, qs, xs=xs), oracle.matern_matrix(x, h, xs) @ qs, rtol=1e-12)
