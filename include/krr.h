@@ -83,6 +83,15 @@ typedef enum {
  * in Algorithm 1, or classical Gram-Schmidt applied twice. */
 typedef enum { KRR_GS_MGS = 0, KRR_GS_CGS2 = 1 } krr_gs;
 
+/* Kernel of K_hat: the Gaussian of eq. Gaussian (section 1), with sigma its
+ * bandwidth, or the Matern kernel with smoothness 3/2 of eq. MaternKernel
+ * (section 6), k = (1 + sqrt(3) d) exp(-sqrt(3) d), d = ||x_i - x_j|| / h, with
+ * the length scale h passed where the calls take sigma.  The Matern kernel is
+ * available in kmvp_matern and in the solvers (fgmres_solve, krr_solve; several
+ * systems or columns are then solved one after the other); the multi-RHS, cross
+ * and gradient calls are Gaussian. */
+typedef enum { KRR_KERNEL_GAUSS = 0, KRR_KERNEL_MATERN32 = 1 } krr_kernel;
+
 /* Options of the flexible solver.  krr_default_opts() fills the paper's rules
  * (section 6): outer tolerance 1e-6, inner tolerance ten times the outer
  * tolerance, delta ten times gamma (1e-3 when gamma = 0).  Fields with a
@@ -98,6 +107,7 @@ typedef struct {
     double inner_tol;    /* inner stop at ||r|| / ||v|| <= inner_tol; < 0: 10 tol; 0: run to the cap */
     int32_t gs;          /* krr_gs; default KRR_GS_MGS */
     int32_t cg_check;    /* plain CG: iterations between host checks of the stop flag; default 16 */
+    int32_t kernel;      /* krr_kernel of K_hat; default KRR_KERNEL_GAUSS */
 } krr_fgmres_opts;
 
 /* Per-solve report (host struct, caller-owned). */
@@ -149,6 +159,13 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
  * or not finite, shift not finite, NULL pointers), KRR_EWORKSPACE. */
 int kmvp_gauss(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
                const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* The same product with the Matern-3/2 kernel (eq. MaternKernel, section 6):
+ * y = K_hat q + shift q, K_hat_ij = (1 + sqrt(3) d_ij) exp(-sqrt(3) d_ij),
+ * d_ij = ||x_i - x_j|| / h.  Arguments, layouts and errors as in kmvp_gauss
+ * (h in place of sigma, h > 0; the KRR_WS_KMVP workspace size). */
+int kmvp_matern(const krr_points *pts /* host */, double h, double shift, int32_t prec,
+                const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream);
 
 /* Y[:, r] = K_hat Q[:, r] + shift Q[:, r] for r < nrhs (several right-hand
  * sides, the multi-RHS need of the posterior variance, section 2.1).  Q and Y are

@@ -52,6 +52,8 @@ def make_opts(**kw) -> N.Opts:
             v = {"cg": N.KRR_INNER_CG, "none": N.KRR_INNER_NONE}[v]
         if k == "gs" and isinstance(v, str):
             v = {"mgs": N.KRR_GS_MGS, "cgs2": N.KRR_GS_CGS2}[v]
+        if k == "kernel" and isinstance(v, str):
+            v = N.KERNEL[v]
         setattr(o, k, v)
     return o
 
@@ -59,6 +61,16 @@ def make_opts(**kw) -> N.Opts:
 def kmvp_gauss(x: torch.Tensor, sigma: float, q: torch.Tensor, shift: float = 0.0, prec="fp64",
                ws: torch.Tensor | None = None) -> torch.Tensor:
     """y = K_hat q + shift q, computed on the fly on the GPU."""
+    return _kmvp_single("kmvp_gauss", x, sigma, q, shift, prec, ws)
+
+
+def kmvp_matern(x: torch.Tensor, h: float, q: torch.Tensor, shift: float = 0.0, prec="fp64",
+                ws: torch.Tensor | None = None) -> torch.Tensor:
+    """y = K_hat q + shift q with the Matern-3/2 kernel of length scale h."""
+    return _kmvp_single("kmvp_matern", x, h, q, shift, prec, ws)
+
+
+def _kmvp_single(name, x, sigma, q, shift, prec, ws):
     p = _prec(prec)
     pts = _points(x)
     n = x.shape[0]
@@ -67,8 +79,8 @@ def kmvp_gauss(x: torch.Tensor, sigma: float, q: torch.Tensor, shift: float = 0.
     need = N.workspace_size(N.KRR_WS_KMVP, [(n, x.shape[1])])
     if ws is None or ws.numel() < need:
         ws = workspace(need, x.device)
-    N.check(N.load().kmvp_gauss(ctypes.byref(pts), float(sigma), float(shift), p, q.data_ptr(), y.data_ptr(),
-                                ws.data_ptr(), ws.numel(), _stream()), "kmvp_gauss")
+    N.check(getattr(N.load(), name)(ctypes.byref(pts), float(sigma), float(shift), p, q.data_ptr(), y.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream()), name)
     return y
 
 

@@ -40,6 +40,7 @@ int resolve_opts(const krr_fgmres_opts *in, double gamma, SolverOpts &o) {
     o.inner_tol = u.inner_tol < 0 ? 10.0 * o.tol : u.inner_tol;
     o.gs = u.gs < 0 ? d.gs : u.gs;
     o.cg_check = u.cg_check <= 0 ? d.cg_check : u.cg_check;
+    o.kernel = u.kernel;
     if (o.restart_m < 1 || o.restart_m > 1000) return KRR_EINVAL;
     if (o.max_outer < 1) return KRR_EINVAL;
     if (!is_fin(o.tol) || o.tol <= 0.0) return KRR_EINVAL;
@@ -49,6 +50,7 @@ int resolve_opts(const krr_fgmres_opts *in, double gamma, SolverOpts &o) {
     if (o.inner == KRR_INNER_CG && o.inner_maxit < 1) return KRR_EINVAL;
     if (!is_fin(o.inner_tol) || o.inner_tol < 0.0) return KRR_EINVAL;
     if (o.gs != KRR_GS_MGS && o.gs != KRR_GS_CGS2) return KRR_EINVAL;
+    if (o.kernel != KRR_KERNEL_GAUSS && o.kernel != KRR_KERNEL_MATERN32) return KRR_EINVAL;
     return KRR_OK;
 }
 
@@ -184,6 +186,7 @@ void krr_default_opts(krr_fgmres_opts *o) {
     o->inner_tol = -1.0;
     o->gs = KRR_GS_MGS;
     o->cg_check = 16;
+    o->kernel = KRR_KERNEL_GAUSS;
 }
 
 const char *krr_status_string(int s) {
@@ -245,8 +248,8 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
     }
 }
 
-int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, const void *q, void *y, void *ws,
-               size_t ws_bytes, krr_stream_t stream) {
+static int kmvp_single(const krr_points *pts, int kernel, double sigma, double shift, int32_t prec, const void *q,
+                       void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
     int rc;
     if ((rc = check_points(pts)) || (rc = check_sigma(sigma)) || (rc = check_prec(prec))) return rc;
     if (!is_fin(shift) || q == nullptr || y == nullptr || q == y) return KRR_EINVAL;
@@ -257,7 +260,7 @@ int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, 
     if (L.total > ws_bytes) return KRR_EWORKSPACE;
     L = carve(ws, pts->n, pts->d, o, K_MVP);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s, kernel));
     if (prec == KRR_FP64) {
         KRR_HIP_STATUS((gather_sorted<double, double>(L.P, static_cast<const double *>(q), static_cast<double *>(L.q), s)));
         KRR_HIP_STATUS(kmvp_tune(L.P, prec, L.q, L.y, L.W.ksc, s));
@@ -276,6 +279,16 @@ int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, 
         KRR_HIP_STATUS((scatter_sorted<float, float>(L.P, static_cast<float *>(L.y), static_cast<float *>(y), s)));
     }
     return KRR_OK;
+}
+
+int kmvp_gauss(const krr_points *pts, double sigma, double shift, int32_t prec, const void *q, void *y, void *ws,
+               size_t ws_bytes, krr_stream_t stream) {
+    return kmvp_single(pts, KRR_KERNEL_GAUSS, sigma, shift, prec, q, y, ws, ws_bytes, stream);
+}
+
+int kmvp_matern(const krr_points *pts, double h, double shift, int32_t prec, const void *q, void *y, void *ws,
+                size_t ws_bytes, krr_stream_t stream) {
+    return kmvp_single(pts, KRR_KERNEL_MATERN32, h, shift, prec, q, y, ws, ws_bytes, stream);
 }
 
 int kmvp_gauss_multi(const krr_points *pts, double sigma, double shift, int32_t prec, int32_t nrhs, const void *Q,
@@ -388,7 +401,7 @@ static int solve_one(const krr_points *pts, double sigma, double gamma, const do
     Layout L = carve(nullptr, pts->n, pts->d, o, kind);
     if (L.total > ws_bytes) return KRR_EWORKSPACE;
     L = carve(ws, pts->n, pts->d, o, kind);
-    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s, o.kernel));
     int flags = 0;
     KRR_HIP_STATUS(hipMemcpyAsync(&flags, L.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     KRR_HIP_STATUS(hipStreamSynchronize(s));
@@ -446,7 +459,9 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     if (ws == nullptr) return KRR_EWORKSPACE;
     ws = align_ws(ws, ws_bytes);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (mode != KRR_MODE_CG64 && (nprob > 1 || nrhs > 1)) {
+    SolverOpts o0;
+    resolve_opts(opts, gamma[0], o0);
+    if (mode != KRR_MODE_CG64 && (nprob > 1 || nrhs > 1) && o0.kernel == KRR_KERNEL_GAUSS) {
         // all systems and columns advance together (one product launch per system
         // per step for all columns, per-column solver state on the device)
         SolverOpts o;

@@ -208,6 +208,72 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a, const typename Prec<PRE
     }
 }
 
+// ---------------------------------------------------------------- Matern kernel
+//
+// The Matern-3/2 product (eq. MaternKernel, section 6): with coordinates scaled
+// by sqrt(3) / h the kernel of a pair is (1 + s) e^(-s), s = ||x~_i - x~_j||.
+// One lane per target row; per pair d differences and FMAs for s^2, one square
+// root, one exp2 (of -s log2 e) and two FMAs; sources at wave-uniform addresses
+// (scalar loads), partial sums over fixed column-tile groups as in k_kmvp.
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_matern(KArgs a, const typename Prec<PREC>::Off *__restrict__ off,
+                                                       const typename Prec<PREC>::Q *__restrict__ q,
+                                                       const double *__restrict__ anchor,
+                                                       typename Prec<PREC>::T *__restrict__ out) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using T = typename P::T;
+    using Off = typename P::Off;
+    constexpr int U = unroll_cols<D, PREC>();
+    constexpr double LOG2E = 1.4426950408889634074;
+    const int64_t n_pad = a.n_pad;
+    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    double aI[D];
+    T oi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
+        oi[k] = P::off(row_off[k * a.n_pad_rows + i]);
+    }
+    T acc = T(0);
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    for (int J = J0; J < J1; ++J) {
+        T t[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            t[k] = static_cast<T>((aI[k] - anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[k]));
+        const int64_t j0 = static_cast<int64_t>(J) * TILE;
+        for (int jb = 0; jb < TILE; jb += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = j0 + jb + u;
+                T r2 = T(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const T dd = t[k] - P::off(off[k * n_pad + j]);
+                    r2 = fma_t(dd, dd, r2);
+                }
+                const T sd = sqrt(r2);
+                const T e = P::ex2(-sd * static_cast<T>(LOG2E));
+                acc = fma_t(fma_t(sd, e, e), P::q(q[j]), acc);
+            }
+        }
+        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
+            if (a.ngroups == 1) {
+                if (i < a.n_rows && a.square) acc += static_cast<T>(a.shift) * P::q(q[i]);
+                out[i] = (i < a.n_rows) ? acc : T(0);
+            } else {
+                out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = acc;
+            }
+            acc = T(0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- matrix-core exponent
 //
 // Products with the exponent on the matrix cores.  The folded exponent of a
@@ -518,7 +584,7 @@ static KmvpPlan heuristic_plan(const Prepared &P) {
 
 namespace {
 struct TuneKey {
-    int prec, dpad, ntiles;
+    int prec, dpad, ntiles;  // prec: krr_prec + 16 x krr_kernel
     bool operator<(const TuneKey &o) const {
         return prec != o.prec ? prec < o.prec : dpad != o.dpad ? dpad < o.dpad : ntiles < o.ntiles;
     }
@@ -560,7 +626,7 @@ KmvpPlan kmvp_plan(const Prepared &P, int prec) {
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
-    auto it = g_tuned.find(TuneKey{prec, P.dpad, P.ntiles});
+    auto it = g_tuned.find(TuneKey{prec + 16 * P.kernel, P.dpad, P.ntiles});
     if (it != g_tuned.end()) return plan_for(P, it->second);
     return heuristic_plan(P);
 }
@@ -585,14 +651,20 @@ static bool use_valu_kernel() {
 }
 
 template <int D, int PREC>
-static hipError_t launch_kmvp(const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
+    using P = Prec<PREC>;
+    if (kernel == KRR_KERNEL_MATERN32) {
+        hipLaunchKernelGGL((k_kmvp_matern<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                           static_cast<const typename P::Off *>(a.off), static_cast<const typename P::Q *>(a.q),
+                           a.anchor, static_cast<typename P::T *>(a.out));
+        return hipGetLastError();
+    }
     if constexpr (D <= 16) {
         if (!use_valu_kernel()) {
             hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }
-    using P = Prec<PREC>;
     hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
                        static_cast<const typename P::Off *>(a.off), static_cast<const typename P::T *>(a.qw),
                        a.anchor, static_cast<typename P::T *>(a.out));
@@ -600,20 +672,20 @@ static hipError_t launch_kmvp(const KArgs &a, hipStream_t s) {
 }
 
 template <int PREC>
-static hipError_t launch_kmvp_d(int dpad, const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp_d(int dpad, const KArgs &a, int kernel, hipStream_t s) {
     switch (dpad) {
-        case 1: return launch_kmvp<1, PREC>(a, s);
-        case 2: return launch_kmvp<2, PREC>(a, s);
-        case 3: return launch_kmvp<3, PREC>(a, s);
-        case 4: return launch_kmvp<4, PREC>(a, s);
-        case 6: return launch_kmvp<6, PREC>(a, s);
-        case 8: return launch_kmvp<8, PREC>(a, s);
-        case 12: return launch_kmvp<12, PREC>(a, s);
-        case 16: return launch_kmvp<16, PREC>(a, s);
-        case 24: return launch_kmvp<24, PREC>(a, s);
-        case 32: return launch_kmvp<32, PREC>(a, s);
-        case 48: return launch_kmvp<48, PREC>(a, s);
-        case 64: return launch_kmvp<64, PREC>(a, s);
+        case 1: return launch_kmvp<1, PREC>(a, kernel, s);
+        case 2: return launch_kmvp<2, PREC>(a, kernel, s);
+        case 3: return launch_kmvp<3, PREC>(a, kernel, s);
+        case 4: return launch_kmvp<4, PREC>(a, kernel, s);
+        case 6: return launch_kmvp<6, PREC>(a, kernel, s);
+        case 8: return launch_kmvp<8, PREC>(a, kernel, s);
+        case 12: return launch_kmvp<12, PREC>(a, kernel, s);
+        case 16: return launch_kmvp<16, PREC>(a, kernel, s);
+        case 24: return launch_kmvp<24, PREC>(a, kernel, s);
+        case 32: return launch_kmvp<32, PREC>(a, kernel, s);
+        case 48: return launch_kmvp<48, PREC>(a, kernel, s);
+        case 64: return launch_kmvp<64, PREC>(a, kernel, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -648,12 +720,14 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
                     : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
                                        : static_cast<const void *>(C.w16);
     const dim3 gc((C.n_pad + BLOCK - 1) / BLOCK), gr((R.n_pad + BLOCK - 1) / BLOCK);
-    switch (prec) {
-        case KRR_FP64: hipLaunchKernelGGL(k_prescale<KRR_FP64>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
-        case KRR_FP32: hipLaunchKernelGGL(k_prescale<KRR_FP32>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
-        default: hipLaunchKernelGGL(k_prescale<KRR_BF16>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+    if (C.kernel == KRR_KERNEL_GAUSS) {  // the Matern product reads q itself
+        switch (prec) {
+            case KRR_FP64: hipLaunchKernelGGL(k_prescale<KRR_FP64>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+            case KRR_FP32: hipLaunchKernelGGL(k_prescale<KRR_FP32>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+            default: hipLaunchKernelGGL(k_prescale<KRR_BF16>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
+        }
+        KRR_HIP(hipGetLastError());
     }
-    KRR_HIP(hipGetLastError());
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool timed =
         timed_slot && profile_slot(prec, static_cast<double>(R.n) * static_cast<double>(C.n), &ev0, &ev1);
@@ -663,17 +737,17 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
         case KRR_FP64:
             a.off = C.off64;
             a.row_off = R.off64;
-            e = launch_kmvp_d<KRR_FP64>(C.dpad, a, s);
+            e = launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
             break;
         case KRR_FP32:
             a.off = C.off32;
             a.row_off = R.off32;
-            e = launch_kmvp_d<KRR_FP32>(C.dpad, a, s);
+            e = launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
             break;
         case KRR_BF16:
             a.off = C.off16;
             a.row_off = R.off16;
-            e = launch_kmvp_d<KRR_BF16>(C.dpad, a, s);
+            e = launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -730,7 +804,7 @@ KmvpScratch carve_kmvp_cross_scratch(Carver &cv, const Prepared &T, const Prepar
 // Time every candidate split count on this point set and keep the fastest.
 // q must be a valid input vector of the precision; y is overwritten.
 hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s) {
-    const TuneKey key{prec, P.dpad, P.ntiles};
+    const TuneKey key{prec + 16 * P.kernel, P.dpad, P.ntiles};  // kernel type in the key
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();

@@ -102,6 +102,7 @@ struct Prepared {
     float *w16 = nullptr;
     double *sq64 = nullptr;   // n_pad: ||o_j||^2 (FP64 offsets)
     int *flags = nullptr;     // [0]: non-finite input seen
+    int kernel = KRR_KERNEL_GAUSS;  // krr_kernel of the products on this set
 };
 
 // Sizes of a prepared set.
@@ -113,8 +114,10 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d);
 
 // Build the prepared layout from FP64 row-major points; temp is scratch of
 // prep_temp_bytes(n).  Returns a HIP error code.
+// sigma: the Gaussian bandwidth, or the Matern length scale h (kernel ==
+// KRR_KERNEL_MATERN32: coordinates scaled by sqrt(3) / h).
 hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp, size_t temp_bytes,
-                          hipStream_t s);
+                          hipStream_t s, int kernel = KRR_KERNEL_GAUSS);
 
 // Gather an original-order vector into sorted order (padding 0), and back.
 template <typename Tin, typename Tout>

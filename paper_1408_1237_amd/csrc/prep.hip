@@ -185,10 +185,14 @@ __global__ void k_fill_int(int *p, int n, int v) {
 }
 
 hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp, size_t temp_bytes,
-                          hipStream_t s) {
+                          hipStream_t s, int kernel) {
     const int64_t n = P.n;
     const int d = P.d;
-    P.scale = std::sqrt(std::log2(std::exp(1.0))) / (sigma * std::sqrt(2.0));
+    P.kernel = kernel;
+    // Gaussian: exp(-r^2 / (2 sigma^2)) = 2^(-||x~_i - x~_j||^2); Matern: the
+    // scaled distance ||x~_i - x~_j|| is sqrt(3) r / h
+    P.scale = kernel == KRR_KERNEL_MATERN32 ? std::sqrt(3.0) / sigma
+                                            : std::sqrt(std::log2(std::exp(1.0))) / (sigma * std::sqrt(2.0));
     Carver cv(temp);
     uint64_t *k0 = cv.take<uint64_t>(n);
     uint64_t *k1 = cv.take<uint64_t>(n);

@@ -24,6 +24,7 @@ struct SolverOpts {
     double inner_tol = 1e-5;
     int gs = KRR_GS_MGS;
     int cg_check = 16;
+    int kernel = KRR_KERNEL_GAUSS;
 };
 
 // Buffers of one solve, carved from the workspace.  b and x are the right-hand

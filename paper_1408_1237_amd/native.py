@@ -19,12 +19,14 @@ KRR_OK, KRR_NOT_CONVERGED, KRR_BREAKDOWN = 0, 1, 2
 KRR_EINVAL, KRR_ENONFINITE, KRR_EWORKSPACE, KRR_EHIP, KRR_EUNSUPPORTED = -1, -2, -3, -4, -5
 KRR_INNER_CG, KRR_INNER_NONE = 0, 1
 KRR_GS_MGS, KRR_GS_CGS2 = 0, 1
+KRR_KERNEL_GAUSS, KRR_KERNEL_MATERN32 = 0, 1
+KERNEL = {"gauss": KRR_KERNEL_GAUSS, "matern32": KRR_KERNEL_MATERN32}
 KRR_MODE_FGMRES, KRR_MODE_CG64, KRR_MODE_GMRES = 0, 1, 2
 (KRR_WS_KMVP, KRR_WS_KMVP_MULTI, KRR_WS_KMVP_GRAD, KRR_WS_CG_INNER, KRR_WS_FGMRES, KRR_WS_SOLVE,
  KRR_WS_KMVP_CROSS) = range(7)
 KRR_MAX_DIM = 64
 
-EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss",
+EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss", "kmvp_matern",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
             "krr_solve", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
             "krr_probe_issue_rates")
@@ -38,7 +40,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("restart_m", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("inner", ctypes.c_int32), ("inner_prec", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("gs", ctypes.c_int32),
-                ("cg_check", ctypes.c_int32)]
+                ("cg_check", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -88,6 +90,7 @@ def load(path: str | None = None):
         lib.krr_workspace_size.argtypes = [_i32, _P(Points), _i32, _i32, _P(Opts)]
         lib.krr_workspace_size.restype = _sz
         lib.kmvp_gauss.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp, _sz, _vp]
+        lib.kmvp_matern.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp, _sz, _vp]
         lib.kmvp_gauss_multi.argtypes = [_P(Points), _dbl, _dbl, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _sz, _vp]
         lib.kmvp_gauss_cross.argtypes = [_P(Points), _P(Points), _dbl, _i32, _vp, _vp, _vp, _sz, _vp]
         lib.kmvp_grad.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -103,7 +106,7 @@ def load(path: str | None = None):
         lib.krr_probe_issue_rates.restype = ctypes.c_int
         lib.krr_probe_issue_rates.argtypes = [_P(_dbl), _vp, _sz, _vp]
         lib.krr_profile_end.restype = ctypes.c_int
-        for name in ("kmvp_gauss", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
+        for name in ("kmvp_gauss", "kmvp_matern", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
                      "fgmres_solve", "krr_solve"):
             getattr(lib, name).restype = ctypes.c_int
         if path is None:

@@ -138,6 +138,22 @@ def gp_regression(seed: int = 5, n: int = 200_000, d: int = 16) -> Problem:
                    inner_maxit=10, inner_tol=1e-5)
 
 
+def matern_classification(seed: int = 6, n: int = 100_000, d: int = 8) -> Problem:
+    """GPR on binary labels with the Matern-3/2 kernel (the classification sets of
+    Table 2 are absent; this stands in for their shape at a larger N).
+
+    x ~ N(0, I_d), labels y = sign(x . w + 0.3 e) in {-1, +1} with w ~ N(0, I/d),
+    e ~ N(0, 1); length scale h = sqrt(d) (passed as sigma), gamma = 1e-2,
+    delta = 10 gamma.
+    """
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d))
+    wv = rng.standard_normal(d) / np.sqrt(d)
+    y = np.where(x @ wv + 0.3 * rng.standard_normal(n) >= 0.0, 1.0, -1.0)
+    return Problem("matern_classification", _c(x), _c(y), sigma=float(np.sqrt(d)), gamma=1e-2, delta=1e-1,
+                   inner_maxit=10, inner_tol=1e-5)
+
+
 def random_points(seed: int, n: int, d: int, scale: float = 1.0, kind: str = "uniform") -> np.ndarray:
     """Plain random point sets for parity tests: uniform on [0, scale]^d or N(0, scale^2 I)."""
     rng = np.random.default_rng(seed)

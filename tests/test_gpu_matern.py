@@ -1,0 +1,106 @@
+"""The Matern-3/2 kernel (eq. MaternKernel, section 6) on the GPU.
+
+Products in every precision against the oracle's on-the-fly FP64 sum
+(norm-wise bars: FP64 1e-12, FP32 1e-5, BF16-input 1e-2), special cases, and
+solves (flexible GMRES, plain FP64 CG, several systems) against the oracle's
+Cholesky solve with the explicit Matern matrix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1408_1237_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}
+DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _mvp(x, h, q, shift, prec):
+    from paper_1408_1237_amd import api
+    y = api.kmvp_matern(_t(x), h, _t(q).to(DT[prec]), shift=shift, prec=prec)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,d", [(1, 2), (257, 1), (2000, 2), (1500, 3), (3000, 8), (700, 17)])
+def test_matern_product_matches_oracle(prec, n, d):
+    x = workloads.random_points(100 + n + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(101 + n, n)
+    h = 0.7 * np.sqrt(d)
+    assert _rel(_mvp(x, h, q, 0.05, prec), oracle.matern_mvp(x, h, q, shift=0.05)) <= TOL[prec]
+
+
+def test_matern_special_cases_and_kernel_selection():
+    from paper_1408_1237_amd import api
+    q = workloads.random_vector(110, 300)
+    y = _mvp(np.zeros((300, 3)), 1.0, q, 0.5, "fp64")       # coincident: K_hat = 1 1^T
+    assert np.allclose(y, q.sum() + 0.5 * q, rtol=1e-12)
+    far = np.arange(300, dtype=float).reshape(-1, 1) * 100.0  # far apart: K_hat = I
+    assert np.allclose(_mvp(far, 1.0, q, 0.0, "fp64"), q, rtol=1e-14)
+    x = workloads.random_points(111, 500, 2, 1.0)
+    qt = _t(workloads.random_vector(112, 500))
+    g = api.kmvp_gauss(_t(x), 0.3, qt, prec="fp64").cpu().numpy()
+    m = api.kmvp_matern(_t(x), 0.3, qt, prec="fp64").cpu().numpy()
+    assert _rel(m, g) > 1e-2  # two different kernels
+
+
+def test_matern_sampled_rows_at_1e5():
+    p = workloads.matern_classification(n=100_000)
+    q = workloads.random_vector(113, p.n)
+    for prec in ("fp64", "fp32"):
+        y = _mvp(p.x, p.sigma, q, p.gamma, prec)
+        rows = np.random.default_rng(7).choice(p.n, 48, replace=False)
+        want = oracle.matern_mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+        assert _rel(y[rows], want) <= 10 * TOL[prec]
+
+
+@pytest.mark.parametrize("inner_prec", ["fp32", "bf16"])
+def test_matern_fgmres_matches_direct_solve(inner_prec):
+    from paper_1408_1237_amd import api
+    p = workloads.matern_classification(n=1500, d=5)
+    w, info = api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y), kernel="matern32", inner_prec=inner_prec,
+                               inner_maxit=20, restart_m=50, max_outer=500)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-6
+    wn = w.cpu().numpy()
+    r = p.y - oracle.matern_mvp(p.x, p.sigma, wn, shift=p.gamma)
+    assert np.linalg.norm(r) <= 1.01e-6 * np.linalg.norm(p.y)
+    ws = oracle.matern_direct_solve(p.x, p.sigma, p.gamma, p.y)
+    K = oracle.matern_matrix(p.x, p.sigma) + p.gamma * np.eye(p.n)
+    kappa = np.linalg.cond(K)
+    assert np.linalg.norm(wn - ws) <= 2 * kappa * 1e-6 * np.linalg.norm(ws)
+
+
+def test_matern_cg64_and_several_systems():
+    from paper_1408_1237_amd import api
+    probs = [workloads.matern_classification(seed=120 + k, n=800 + 300 * k, d=4) for k in range(3)]
+    Ws, infos = api.krr_solve([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+                              [_t(p.y) for p in probs], mode="fgmres", kernel="matern32", inner_maxit=20,
+                              restart_m=50, max_outer=500)
+    for p, w, i in zip(probs, Ws, infos):
+        assert i["status"] == 0
+        r = p.y - oracle.matern_mvp(p.x, p.sigma, w.cpu().numpy(), shift=p.gamma)
+        assert np.linalg.norm(r) <= 1.01e-6 * np.linalg.norm(p.y)
+    (w64,), (i64,) = api.krr_solve([_t(probs[1].x)], [probs[1].sigma], [probs[1].gamma], [_t(probs[1].y)],
+                                   mode="cg64", kernel="matern32", max_outer=20000)
+    assert i64["status"] == 0
+    r = probs[1].y - oracle.matern_mvp(probs[1].x, probs[1].sigma, w64.cpu().numpy(), shift=probs[1].gamma)
+    assert np.linalg.norm(r) <= 1.01e-6 * np.linalg.norm(probs[1].y)
+
+
+def test_matern_unknown_kernel_rejected():
+    from paper_1408_1237_amd import api, native
+    p = workloads.matern_classification(n=200, d=2)
+    with pytest.raises(native.KrrError):
+        api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y), kernel=7)
