@@ -68,6 +68,9 @@ def _load():
                                       _dp, _dp, _dp, _ip]
             lib.or_grad.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _dp, _dp, _dp, _dp]
             lib.or_grad_rows.argtypes = [_i64, _int, _dp, _dbl, _dp, _dp, _i64, _lp, _dp]
+            lib.or_fcg.restype = _int
+            lib.or_fcg.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _dp, _int, _int, _dbl, _int, _dbl, _int,
+                                   _dbl, _ip, _dp, _dp, _dp]
             lib.or_matern.restype = _dbl
             lib.or_matern.argtypes = [_dp, _dp, _int, _dbl]
             lib.or_matern_matrix.argtypes = [_i64, _i64, _int, _dp, _dp, _dbl, _dp]
@@ -230,6 +233,32 @@ def fgmres(x, sigma: float, gamma: float, b, *, m: int = 30, max_outer: int = 30
     if want_basis:
         k = kk.value
         out.update(V=V[: k + 1].T.copy(), Z=Z[:k].T.copy(), H=H[: k + 1, :k].copy(), k=k)
+    return out
+
+
+def fcg(x, sigma: float, gamma: float, b, *, mmax: int = 30, max_outer: int = 300, tol: float = 1e-6,
+        inner: str = "cg", delta: float | None = None, inner_maxit: int = 10, inner_tol: float | None = None,
+        want_directions: bool = False) -> dict:
+    """Flexible CG with re-orthogonalisation over the last mmax directions (see or_fcg)."""
+    x, n, d = _pts(x)
+    b = _f64(b)
+    if delta is None:
+        delta = 10.0 * gamma if gamma > 0 else 1e-3
+    if inner_tol is None:
+        inner_tol = 10.0 * tol
+    mode = {"none": 0, "cg": 1}[inner]
+    w = np.zeros(n)
+    info = np.zeros(2, dtype=np.intc)
+    hist = np.full(max_outer + 1, np.nan)
+    rel = ctypes.c_double(0.0)
+    D = np.zeros((max_outer, n)) if want_directions else None
+    st = _load().or_fcg(n, d, _p(x), float(sigma), float(gamma), _p(b), _p(w), int(mmax), int(max_outer),
+                        float(tol), mode, float(delta), int(inner_maxit), float(inner_tol),
+                        info.ctypes.data_as(_ip), _p(hist), _p(D) if want_directions else None, ctypes.byref(rel))
+    out = dict(w=w, status=int(st), outer=int(info[0]), inner=int(info[1]), relres=rel.value,
+               hist=hist[: info[0] + 1])
+    if want_directions:
+        out["D"] = D
     return out
 
 

@@ -444,6 +444,103 @@ done:
     return status;
 }
 
+/* Flexible CG for K w = b, K = K_hat + gamma I, from w = 0: the flexible
+ * Krylov alternative to Algorithm 1 that section 4.2 and section 5.4 compare
+ * it with.  With a preconditioner that changes from step to step, the new
+ * search direction is made K-orthogonal to the previous ones explicitly (the
+ * re-orthogonalisation the paper attributes to Notay); at most mmax previous
+ * directions are kept:
+ *   r_0 = b
+ *   for i = 0, 1, ...:
+ *     z_i = inner preconditioner solve M z = r_i       (as in or_fgmres)
+ *     d_i = z_i - sum_{k in window} ((z_i . q_k) / (d_k . q_k)) d_k,  q_k = K d_k
+ *     q_i = K d_i
+ *     alpha_i = (d_i . r_i) / (d_i . q_i)
+ *     w += alpha_i d_i,   r_{i+1} = r_i - alpha_i q_i
+ * the window being the last min(i, mmax) directions.  When the recursive
+ * residual reaches ||r|| / ||b|| <= tol the true residual b - K w is computed;
+ * above tol the iteration restarts from it with an empty window.
+ * Outputs: info[0] outer iterations, info[1] inner CG iterations;
+ * hist (length >= max_outer + 1, may be NULL) the recursive relative residual
+ * before each iteration and after the last; D_out (n x max_outer, may be NULL)
+ * the directions d_i of the last restart, column i at D_out + i*n; *relres the
+ * final true relative residual.  Returns 0 converged, 1 not converged within
+ * max_outer, 2 on a breakdown (d.q <= 0 or not finite). */
+int or_fcg(int64_t n, int d, const double *x_pts, double sigma, double gamma,
+           const double *b, double *w, int mmax, int max_outer, double tol,
+           int inner_mode, double delta, int inner_maxit, double inner_tol,
+           int *info, double *hist, double *D_out, double *relres)
+{
+    if (mmax < 1) mmax = 1;
+    double *D = (double *)calloc((size_t)n * mmax, sizeof(double));
+    double *Q = (double *)calloc((size_t)n * mmax, sizeof(double));
+    double *dq = (double *)calloc((size_t)mmax, sizeof(double));
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *z = (double *)malloc((size_t)n * sizeof(double));
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    double bn = nrm2(n, b);
+    int it = 0, inner_total = 0, status = 1, cnt = 0, head = 0, restart_i = 0;
+    double rel = 0.0;
+    for (int64_t i = 0; i < n; ++i) { w[i] = 0.0; r[i] = b[i]; }
+    if (bn == 0.0) { status = 0; goto done; }
+    rel = nrm2(n, r) / bn;
+    if (hist) hist[0] = rel;
+    while (it < max_outer) {
+        if (rel <= tol) {
+            /* confirm with the true residual; restart from it if needed */
+            or_mvp(n, n, d, x_pts, x_pts, sigma, gamma, w, q);
+            for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+            rel = nrm2(n, r) / bn;
+            if (rel <= tol) { status = 0; break; }
+            cnt = 0;
+            head = 0;
+            restart_i = it;
+        }
+        if (inner_mode == 0) {
+            for (int64_t i = 0; i < n; ++i) z[i] = r[i];
+        } else {
+            int it_in = 0;
+            double rr_in = 0.0;
+            or_cg(n, d, x_pts, sigma, delta, r, z, inner_maxit, inner_tol, 0, &it_in, &rr_in, NULL);
+            inner_total += it_in;
+        }
+        /* d = z - sum_k (z.q_k / d_k.q_k) d_k over the window (oldest first) */
+        double *dn = D + (int64_t)head * n;
+        double *qn = Q + (int64_t)head * n;
+        for (int64_t i = 0; i < n; ++i) q[i] = z[i];
+        for (int c = cnt; c >= 1; --c) {
+            int k = (head - c + mmax) % mmax;
+            double beta = dot(n, z, Q + (int64_t)k * n) / dq[k];
+            for (int64_t i = 0; i < n; ++i) q[i] -= beta * D[(int64_t)k * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) dn[i] = q[i];
+        or_mvp(n, n, d, x_pts, x_pts, sigma, gamma, dn, qn);
+        double dqi = dot(n, dn, qn);
+        if (!(dqi > 0.0) || !isfinite(dqi)) { status = 2; break; }
+        dq[head] = dqi;
+        double alpha = dot(n, dn, r) / dqi;
+        for (int64_t i = 0; i < n; ++i) { w[i] += alpha * dn[i]; r[i] -= alpha * qn[i]; }
+        if (D_out && it - restart_i < max_outer)
+            memcpy(D_out + (int64_t)(it - restart_i) * n, dn, sizeof(double) * (size_t)n);
+        head = (head + 1) % mmax;
+        if (cnt < mmax) ++cnt;
+        ++it;
+        rel = nrm2(n, r) / bn;
+        if (hist) hist[it] = rel;
+    }
+    if (status == 1 && rel <= tol) {
+        or_mvp(n, n, d, x_pts, x_pts, sigma, gamma, w, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        rel = nrm2(n, r) / bn;
+        if (rel <= tol) status = 0;
+    }
+done:
+    if (info) { info[0] = it; info[1] = inner_total; }
+    if (relres) *relres = rel;
+    free(D); free(Q); free(dq); free(r); free(z); free(q);
+    return status;
+}
+
 /* Gradient of a scalar loss l(w), w = K^{-1} y, with respect to the points,
  * log sigma and log gamma (hyperparameters are set by maximum likelihood,
  * section 2.1 and section 6.1).  With lambda = K^{-1} (dl/dw), matrix calculus

@@ -424,3 +424,45 @@ def test_matern_on_the_fly_equals_explicit_and_direct_solve():
     xs = workloads.random_points(95, 50, 3, 1.0)
     qs = workloads.random_vector(96, 50)
     assert np.allclose(oracle.matern_mvp(x, h, qs, xs=xs), oracle.matern_matrix(x, h, xs) @ qs, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- flexible CG (section 4.2, section 5.4)
+
+def test_fcg_without_preconditioner_is_cg():
+    # M = I: the re-orthogonalised directions are CG's (Hestenes-Stiefel), so the
+    # residual histories agree while rounding is small
+    x = workloads.random_points(130, 400, 2, 1.0)
+    b = workloads.random_vector(131, 400)
+    sigma, gamma = 0.1, 0.1
+    f = oracle.fcg(x, sigma, gamma, b, mmax=5, max_outer=40, tol=1e-12, inner="none")
+    c = oracle.cg(x, sigma, gamma, b, 40, 1e-12, confirm=False)
+    k = min(len(f["hist"]), len(c[4]), 25)
+    assert np.allclose(f["hist"][:k], c[4][:k], rtol=1e-7, atol=0)
+
+
+def test_fcg_directions_are_K_conjugate_and_solution_matches_cholesky():
+    x = workloads.random_points(132, 300, 2, 1.0)
+    b = workloads.random_vector(133, 300)
+    sigma, gamma = 0.15, 1e-2
+    f = oracle.fcg(x, sigma, gamma, b, mmax=100, max_outer=100, tol=1e-10, inner="cg", delta=1e-2,
+                   inner_maxit=5, want_directions=True)
+    assert f["status"] == 0
+    K = oracle.kernel_matrix(x, sigma) + gamma * np.eye(300)
+    D = f["D"][: f["outer"]]
+    G = D @ K @ D.T
+    dg = np.sqrt(np.diag(G))
+    C = np.abs(G) / np.outer(dg, dg)
+    np.fill_diagonal(C, 0.0)
+    assert C.max() <= 1e-8
+    ws = oracle.direct_solve(x, sigma, gamma, b)
+    assert np.linalg.norm(f["w"] - ws) <= np.linalg.cond(K) * 1e-10 * np.linalg.norm(ws)
+    assert oracle.true_relres(x, sigma, gamma, b, f["w"]) <= 1e-10
+
+
+def test_fcg_exact_inner_solve_converges_at_once():
+    # M = K (delta = gamma, inner CG run to a tight tolerance): one outer step
+    x = workloads.random_points(134, 200, 2, 1.0)
+    b = workloads.random_vector(135, 200)
+    f = oracle.fcg(x, 0.2, 0.05, b, mmax=10, max_outer=10, tol=1e-8, delta=0.05, inner_maxit=2000,
+                   inner_tol=1e-13)
+    assert f["status"] == 0 and f["outer"] <= 2
