@@ -126,7 +126,9 @@ typedef struct {
 typedef enum {
     KRR_MODE_FGMRES = 0, /* mixed precision flexible GMRES (the paper's method) */
     KRR_MODE_CG64 = 1,   /* plain FP64 conjugate gradient (the paper's baseline) */
-    KRR_MODE_GMRES = 2   /* FGMRES with inner = KRR_INNER_NONE */
+    KRR_MODE_GMRES = 2,  /* FGMRES with inner = KRR_INNER_NONE */
+    KRR_MODE_FCG = 3     /* flexible CG (sections 4.2, 5.4): each new direction K-orthogonalised
+                            against up to restart_m - 1 previous ones, same inner solver */
 } krr_mode;
 
 /* Which call a workspace is sized for (krr_workspace_size). */

@@ -179,7 +179,8 @@ def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | N
     column-major float64 tensors (same nrhs for all).  Returns (list of W_k, list of
     info dicts ordered system-major).
     """
-    modes = {"fgmres": N.KRR_MODE_FGMRES, "cg64": N.KRR_MODE_CG64, "gmres": N.KRR_MODE_GMRES}
+    modes = {"fgmres": N.KRR_MODE_FGMRES, "cg64": N.KRR_MODE_CG64, "gmres": N.KRR_MODE_GMRES,
+             "fcg": N.KRR_MODE_FCG}
     k = len(xs)
     pts = (N.Points * k)(*[_points(x) for x in xs])
     Ys2 = [Y.reshape(-1, 1) if Y.dim() == 1 else Y for Y in Ys]

@@ -414,6 +414,8 @@ static int solve_one(const krr_points *pts, double sigma, double gamma, const do
     int rc;
     if (mode == KRR_MODE_CG64) {
         rc = cg64_sorted(L.P, gamma, o, L.W, &tmp, s);
+    } else if (mode == KRR_MODE_FCG) {
+        rc = fcg_sorted(L.P, gamma, o, L.W, &tmp, s);
     } else {
         SolverOpts oo = o;
         if (mode == KRR_MODE_GMRES) oo.inner = KRR_INNER_NONE;
@@ -447,7 +449,8 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     if (probs == nullptr || nprob < 1 || sigma == nullptr || gamma == nullptr || nrhs < 1 || Y == nullptr ||
         W == nullptr)
         return KRR_EINVAL;
-    if (mode != KRR_MODE_FGMRES && mode != KRR_MODE_CG64 && mode != KRR_MODE_GMRES) return KRR_EINVAL;
+    if (mode != KRR_MODE_FGMRES && mode != KRR_MODE_CG64 && mode != KRR_MODE_GMRES && mode != KRR_MODE_FCG)
+        return KRR_EINVAL;
     int rc;
     for (int k = 0; k < nprob; ++k) {
         if ((rc = check_points(&probs[k])) || (rc = check_sigma(sigma[k]))) return rc;
@@ -461,7 +464,8 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     SolverOpts o0;
     resolve_opts(opts, gamma[0], o0);
-    if (mode != KRR_MODE_CG64 && (nprob > 1 || nrhs > 1) && o0.kernel == KRR_KERNEL_GAUSS) {
+    if ((mode == KRR_MODE_FGMRES || mode == KRR_MODE_GMRES) && (nprob > 1 || nrhs > 1) &&
+        o0.kernel == KRR_KERNEL_GAUSS) {
         // all systems and columns advance together (one product launch per system
         // per step for all columns, per-column solver state on the device)
         SolverOpts o;

@@ -50,5 +50,13 @@ hipError_t fg_normalize(int64_t n_pad, const double *w, double *vnext, const dou
                         const FgmresScalars *F, hipStream_t s);
 hipError_t fg_update_x(int64_t n_pad, int k, int m, const double *H, const double *g, double *y, const double *Z,
                        double *x, hipStream_t s);
+// Flexible CG: z -= D beta over nslots stored directions (beta_k = z.q_k / d_k.q_k,
+// 0 for slot cur); then alpha = d.r / d.q (dq[cur] kept), x += alpha d, r -= alpha q,
+// F->est = ||r|| / ||b||, F->breakdown on d.q <= 0.
+hipError_t fcg_direction(int64_t n_pad, int nslots, int cur, double *z, const double *D, const double *Q,
+                         double *hcol, double *hpass, double *dq_beta_scratch, const double *dq, const Red &R,
+                         hipStream_t s);
+hipError_t fcg_step(int64_t n_pad, const double *d, const double *q, double *x, double *r, double *dq, int cur,
+                    double *alpha, FgmresScalars *F, const Red &R, hipStream_t s);
 
 }  // namespace krr

@@ -461,6 +461,51 @@ hipError_t zero_bytes(void *p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ flexible CG
+
+// beta_k = (z . q_k) / (d_k . q_k) for the stored directions; 0 for the slot the
+// new direction is about to replace.
+__global__ void k_fcg_beta(int nslots, int cur, const double *hcol, const double *dq, double *beta) {
+    for (int k = threadIdx.x; k < nslots; k += blockDim.x) beta[k] = (k == cur) ? 0.0 : hcol[k] / dq[k];
+}
+
+// dq[cur] = d . q, alpha = (d . r) / (d . q); breakdown when d . q <= 0.
+__global__ __launch_bounds__(BLOCK) void k_fcg_alpha(int64_t n_pad, const double *__restrict__ d,
+                                                     const double *__restrict__ q, const double *__restrict__ r,
+                                                     double *dq, int cur, double *alpha, FgmresScalars *F,
+                                                     double *partials, unsigned *counter) {
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, n_pad) {
+        acc[0] += d[i] * q[i];
+        acc[1] += d[i] * r[i];
+    }
+    if (grid_reduce(acc, partials, counter) && threadIdx.x == 0) {
+        dq[cur] = acc[0];
+        *alpha = acc[1] / acc[0];
+        if (!(acc[0] > 0.0) || !isfinite(acc[0]) || !isfinite(acc[1])) F->breakdown = 1;
+    }
+}
+
+// x += alpha d, r -= alpha q; est = ||r|| / ||b||.
+__global__ __launch_bounds__(BLOCK) void k_fcg_update(int64_t n_pad, double *x, double *r,
+                                                      const double *__restrict__ d, const double *__restrict__ q,
+                                                      const double *alpha, FgmresScalars *F, double *partials,
+                                                      unsigned *counter) {
+    if (F->breakdown) return;  // uniform: set by the previous kernel
+    const double a = *alpha;
+    double acc[1] = {0.0};
+    GRID_STRIDE(i, n_pad) {
+        x[i] += a * d[i];
+        const double ri = r[i] - a * q[i];
+        r[i] = ri;
+        acc[0] += ri * ri;
+    }
+    if (grid_reduce(acc, partials, counter) && threadIdx.x == 0) {
+        F->est = sqrt(acc[0]) / F->bnorm;
+        if (!isfinite(F->est)) F->nonfinite = 1;
+    }
+}
+
 hipError_t fg_orthogonalize(int gs, int64_t n_pad, int j, double *w, const double *V, double *hcol, double *hscratch,
                             FgmresScalars *F, const Red &R, hipStream_t s) {
     const int nb = vec_blocks(n_pad);
@@ -497,6 +542,26 @@ hipError_t fg_update_x(int64_t n_pad, int k, int m, const double *H, const doubl
                        double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_fg_backsolve, dim3(1), dim3(64), 0, s, k, m, H, g, y);
     LAUNCH(k_fg_update_x, vec_blocks(n_pad), n_pad, k, Z, y, x);
+    return hipGetLastError();
+}
+
+hipError_t fcg_direction(int64_t n_pad, int nslots, int cur, double *z, const double *D, const double *Q,
+                         double *hcol, double *hpass, double *dq_beta_scratch, const double *dq, const Red &R,
+                         hipStream_t s) {
+    // z <- z - D beta with beta_k = (z . q_k) / (d_k . q_k)
+    const int nb = vec_blocks(n_pad);
+    if (nslots <= 0) return hipSuccess;
+    LAUNCH(k_cgs_dots, nb, n_pad, z, Q, nslots - 1, hpass, hcol, 0, R.partials, R.counters + 10);
+    hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(BLOCK), 0, s, nslots, cur, hcol, dq, dq_beta_scratch);
+    LAUNCH(k_cgs_sub, nb, n_pad, z, D, nslots - 1, dq_beta_scratch, hcol, 0, R.partials, R.counters + 11);
+    return hipGetLastError();
+}
+
+hipError_t fcg_step(int64_t n_pad, const double *d, const double *q, double *x, double *r, double *dq, int cur,
+                    double *alpha, FgmresScalars *F, const Red &R, hipStream_t s) {
+    const int nb = vec_blocks(n_pad);
+    LAUNCH(k_fcg_alpha, nb, n_pad, d, q, r, dq, cur, alpha, F, R.partials, R.counters + 12);
+    LAUNCH(k_fcg_update, nb, n_pad, x, r, d, q, alpha, F, R.partials, R.counters + 13);
     return hipGetLastError();
 }
 

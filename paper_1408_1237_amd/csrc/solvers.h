@@ -52,6 +52,13 @@ SolverWork carve_solver(Carver &cv, const Prepared &P, const SolverOpts &o, bool
 
 int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpts &o, const SolverWork &W,
                   krr_info *info, hipStream_t s);
+// Flexible CG (the alternative to FGMRES the paper compares, sections 4.2 and
+// 5.4): restart_m direction slots, i.e. each new direction is K-orthogonalised
+// against up to restart_m - 1 previous ones; x0 = 0; confirmed on the true
+// residual (restart from it with an empty window otherwise).  Uses the FGMRES
+// workspace.
+int fcg_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,
+               hipStream_t s);
 int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,
                 hipStream_t s);
 // Tune the product plans a solve will use (no-op when already tuned).

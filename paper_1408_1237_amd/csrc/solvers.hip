@@ -233,6 +233,101 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
     return result;
 }
 
+// ---------------------------------------------------------------- flexible CG
+
+int fcg_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,
+               hipStream_t s) {
+    const int64_t np = P.n_pad;
+    const int m = o.restart_m;
+    FgmresScalars *F = &W.status->F;
+    double *r = W.V + static_cast<int64_t>(m) * np;  // slots 0..m-1 of V hold the directions d_k
+    double *z = W.w;
+    double *dq = W.H, *alpha = W.H + m;
+    StatusBlock st;
+    int64_t mvp64 = 0, mvp_in = 0;
+    int it = 0, since = 0, inner_total = 0, restarts = 0;
+    int result = KRR_NOT_CONVERGED;
+
+    KRR_HIP_STATUS(red_init(W.R, s));
+    KRR_HIP_STATUS(tune_products(P, W, o.inner != KRR_INNER_NONE, o.inner_prec, s));
+    KRR_HIP_STATUS(fill_d(W.x, np, 0.0, s));
+    KRR_HIP_STATUS(fg_residual(np, W.b, nullptr, r, F, W.g, W.R, s));
+    KRR_HIP_STATUS(read_status(W.status, st, s));
+    if (st.F.nonfinite) return KRR_ENONFINITE;
+    double est = st.F.bnorm == 0.0 ? 0.0 : st.F.est;
+    for (;;) {
+        if (est <= o.tol) {
+            if (st.F.bnorm == 0.0) {
+                result = KRR_OK;
+                break;
+            }
+            // confirm with the true residual b - K x; restart from it otherwise
+            KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.Ap64, W.ksc, nullptr, s));
+            ++mvp64;
+            KRR_HIP_STATUS(fg_residual(np, W.b, W.Ap64, r, F, W.g, W.R, s));
+            KRR_HIP_STATUS(read_status(W.status, st, s));
+            est = st.F.est;
+            if (est <= o.tol) {
+                result = KRR_OK;
+                break;
+            }
+            since = 0;
+            ++restarts;
+        }
+        if (it >= o.max_outer) break;
+        // z = M^-1 r (inner CG on K_hat + delta I), or z = r
+        if (o.inner == KRR_INNER_NONE) {
+            KRR_HIP_STATUS(copy_d(np, r, z, s));
+        } else {
+            KRR_HIP_STATUS(inner_solve(P, o.inner_prec, o.delta, r, z, o.inner_maxit, o.inner_tol, W, s));
+        }
+        const int cur = since % m;
+        const int nslots = since < m ? since : m;
+        KRR_HIP_STATUS(fcg_direction(np, nslots, cur, z, W.V, W.Z, W.hcol, W.y, W.hscr, dq, W.R, s));
+        double *dcur = W.V + static_cast<int64_t>(cur) * np;
+        double *qcur = W.Z + static_cast<int64_t>(cur) * np;
+        KRR_HIP_STATUS(copy_d(np, z, dcur, s));
+        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, dcur, qcur, W.ksc, nullptr, s));
+        ++mvp64;
+        KRR_HIP_STATUS(fcg_step(np, dcur, qcur, W.x, r, dq, cur, alpha, F, W.R, s));
+        KRR_HIP_STATUS(read_status(W.status, st, s));
+        ++it;
+        ++since;
+        if (o.inner != KRR_INNER_NONE) {
+            const int k = o.inner_prec == KRR_FP64 ? st.c64.iters : st.c32.iters;
+            inner_total += k;
+            mvp_in += k;
+        }
+        if (st.F.breakdown || st.F.nonfinite) {
+            result = KRR_BREAKDOWN;
+            break;
+        }
+        est = st.F.est;
+        if (progress_every() && it % progress_every() == 0)
+            std::fprintf(stderr, "krr fcg: iteration %d rel. residual (recursive) %.3e\n", it, est);
+    }
+    if (result == KRR_NOT_CONVERGED) {  // report the true residual of the last iterate
+        KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, W.x, W.Ap64, W.ksc, nullptr, s));
+        ++mvp64;
+        KRR_HIP_STATUS(fg_residual(np, W.b, W.Ap64, r, F, W.g, W.R, s));
+        KRR_HIP_STATUS(read_status(W.status, st, s));
+        est = st.F.est;
+    }
+    if (info) {
+        info->status = result;
+        info->outer_iters = it;
+        info->inner_iters = inner_total;
+        info->cycles = restarts + 1;
+        info->mvp64 = mvp64;
+        info->mvp32 = (o.inner != KRR_INNER_NONE && o.inner_prec == KRR_FP32) ? mvp_in : 0;
+        info->mvp16 = (o.inner != KRR_INNER_NONE && o.inner_prec == KRR_BF16) ? mvp_in : 0;
+        if (o.inner != KRR_INNER_NONE && o.inner_prec == KRR_FP64) info->mvp64 += mvp_in;
+        info->relres_true = est;
+        info->relres_est = est;
+    }
+    return result;
+}
+
 // ---------------------------------------------------------------- plain FP64 CG
 
 int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const SolverWork &W, krr_info *info,

@@ -21,7 +21,7 @@ KRR_INNER_CG, KRR_INNER_NONE = 0, 1
 KRR_GS_MGS, KRR_GS_CGS2 = 0, 1
 KRR_KERNEL_GAUSS, KRR_KERNEL_MATERN32 = 0, 1
 KERNEL = {"gauss": KRR_KERNEL_GAUSS, "matern32": KRR_KERNEL_MATERN32}
-KRR_MODE_FGMRES, KRR_MODE_CG64, KRR_MODE_GMRES = 0, 1, 2
+KRR_MODE_FGMRES, KRR_MODE_CG64, KRR_MODE_GMRES, KRR_MODE_FCG = 0, 1, 2, 3
 (KRR_WS_KMVP, KRR_WS_KMVP_MULTI, KRR_WS_KMVP_GRAD, KRR_WS_CG_INNER, KRR_WS_FGMRES, KRR_WS_SOLVE,
  KRR_WS_KMVP_CROSS) = range(7)
 KRR_MAX_DIM = 64
