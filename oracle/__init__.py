@@ -71,6 +71,8 @@ def _load():
             lib.or_fcg.restype = _int
             lib.or_fcg.argtypes = [_i64, _int, _dp, _dbl, _dbl, _dp, _dp, _int, _int, _dbl, _int, _dbl, _int,
                                    _dbl, _ip, _dp, _dp, _dp]
+            lib.or_predict.restype = _int
+            lib.or_predict.argtypes = [_i64, _i64, _int, _dp, _dp, _dbl, _dbl, _int, _dp, _dp, _dp]
             lib.or_matern.restype = _dbl
             lib.or_matern.argtypes = [_dp, _dp, _int, _dbl]
             lib.or_matern_matrix.argtypes = [_i64, _i64, _int, _dp, _dp, _dbl, _dp]
@@ -344,3 +346,19 @@ def matern_direct_solve(x, h: float, gamma: float, y) -> np.ndarray:
     K = matern_matrix(x, h)
     K[np.diag_indices_from(K)] += gamma
     return chol_solve(cholesky(K), y)
+
+
+def predict(x, xs, sigma: float, gamma: float, y, kernel: str = "gauss", want_var: bool = True):
+    """GPR posterior mean (eq. GPR_mean) and variance at the test points xs,
+    with the explicit matrix and Cholesky (see or_predict)."""
+    x, n, d = _pts(x)
+    xs, m, ds = _pts(xs)
+    assert ds == d
+    y = _f64(y)
+    mean = np.empty(m)
+    var = np.empty(m) if want_var else None
+    rc = _load().or_predict(n, m, d, _p(x), _p(xs), float(sigma), float(gamma), {"gauss": 0, "matern32": 1}[kernel],
+                            _p(y), _p(mean), _p(var) if want_var else None)
+    if rc != 0:
+        raise np.linalg.LinAlgError("kernel matrix not positive definite")
+    return (mean, var) if want_var else mean

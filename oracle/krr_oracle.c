@@ -541,6 +541,52 @@ done:
     return status;
 }
 
+/* GPR prediction (section 2.1): posterior mean (eq. GPR_mean) and variance
+ * (the equation after it) at m test points xs from n training points x,
+ *   mean_j = k_j^T (K_hat + gamma I)^{-1} y,
+ *   var_j  = k(xs_j, xs_j) - k_j^T (K_hat + gamma I)^{-1} k_j,
+ * k_j = [k(x_1, xs_j), ..., k(x_n, xs_j)]^T, with the explicit matrix and the
+ * textbook Cholesky solve.  kernel 0: Gaussian (sigma), 1: Matern-3/2 (length
+ * scale sigma).  var may be NULL.  Returns 0, or -1 if the matrix is not
+ * positive definite. */
+int or_predict(int64_t n, int64_t m, int d, const double *x, const double *xs, double sigma,
+               double gamma, int kernel, const double *y, double *mean, double *var)
+{
+    double *K = (double *)malloc((size_t)n * n * sizeof(double));
+    double *Ks = (double *)malloc((size_t)n * m * sizeof(double));   /* K_hat(x, xs), n x m */
+    double *a = (double *)malloc((size_t)n * sizeof(double));
+    double *col = (double *)malloc((size_t)n * sizeof(double));
+    double *sol = (double *)malloc((size_t)n * sizeof(double));
+    int rc = 0;
+    if (kernel == 1) {
+        or_matern_matrix(n, n, d, x, x, sigma, K);
+        or_matern_matrix(n, m, d, x, xs, sigma, Ks);
+    } else {
+        or_kernel_matrix(n, n, d, x, x, sigma, K);
+        or_kernel_matrix(n, m, d, x, xs, sigma, Ks);
+    }
+    for (int64_t i = 0; i < n; ++i) K[i * n + i] += gamma;
+    if (or_cholesky(n, K) != 0) { rc = -1; goto done; }
+    or_chol_solve(n, K, y, a);                       /* a = (K_hat + gamma I)^{-1} y */
+    for (int64_t j = 0; j < m; ++j) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += Ks[i * m + j] * a[i];
+        mean[j] = s;
+        if (var) {
+            for (int64_t i = 0; i < n; ++i) col[i] = Ks[i * m + j];
+            or_chol_solve(n, K, col, sol);
+            double kk = (kernel == 1) ? or_matern(xs + j * d, xs + j * d, d, sigma)
+                                      : or_gauss(xs + j * d, xs + j * d, d, sigma);
+            double t = 0.0;
+            for (int64_t i = 0; i < n; ++i) t += col[i] * sol[i];
+            var[j] = kk - t;
+        }
+    }
+done:
+    free(K); free(Ks); free(a); free(col); free(sol);
+    return rc;
+}
+
 /* Gradient of a scalar loss l(w), w = K^{-1} y, with respect to the points,
  * log sigma and log gamma (hyperparameters are set by maximum likelihood,
  * section 2.1 and section 6.1).  With lambda = K^{-1} (dl/dw), matrix calculus

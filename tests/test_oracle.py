@@ -466,3 +466,34 @@ def test_fcg_exact_inner_solve_converges_at_once():
     f = oracle.fcg(x, 0.2, 0.05, b, mmax=10, max_outer=10, tol=1e-8, delta=0.05, inner_maxit=2000,
                    inner_tol=1e-13)
     assert f["status"] == 0 and f["outer"] <= 2
+
+
+# ---------------------------------------------------------------- GPR prediction (section 2.1)
+
+def test_predict_closed_forms():
+    # one training point: mean = k y / (1 + gamma), var = 1 - k^2 / (1 + gamma)
+    x = np.array([[0.3, -0.2]])
+    xs = np.array([[0.3, -0.2], [1.0, 0.5], [50.0, 50.0]])
+    sigma, gamma, y = 0.7, 0.05, np.array([2.0])
+    k = np.array([oracle.gauss(x[0], t, sigma) for t in xs])
+    mean, var = oracle.predict(x, xs, sigma, gamma, y)
+    assert np.allclose(mean, k * 2.0 / (1 + gamma), rtol=1e-14)
+    assert np.allclose(var, 1 - k ** 2 / (1 + gamma), rtol=1e-13)
+    assert var[2] == pytest.approx(1.0) and mean[2] == pytest.approx(0.0, abs=1e-300)
+
+
+def test_predict_matches_scikit_learn_gpr():
+    # an independent implementation: GaussianProcessRegressor with a fixed RBF
+    # kernel, noise gamma as alpha, latent-function standard deviation
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import RBF, Matern
+    x = workloads.random_points(150, 120, 3, 1.0)
+    xs = workloads.random_points(151, 25, 3, 1.0)
+    y = workloads.random_vector(152, 120)
+    for kern, name in ((RBF(length_scale=0.4, length_scale_bounds="fixed"), "gauss"),
+                       (Matern(length_scale=0.4, nu=1.5, length_scale_bounds="fixed"), "matern32")):
+        gp = GaussianProcessRegressor(kernel=kern, alpha=0.01, optimizer=None, normalize_y=False).fit(x, y)
+        m_ref, s_ref = gp.predict(xs, return_std=True)
+        mean, var = oracle.predict(x, xs, 0.4, 0.01, y, kernel=name)
+        assert np.allclose(mean, m_ref, rtol=1e-8, atol=1e-10)
+        assert np.allclose(np.sqrt(np.maximum(var, 0.0)), s_ref, rtol=1e-6, atol=1e-8)
