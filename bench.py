@@ -88,12 +88,12 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the product kernels' source; the committed counter summary is used
-    only while it matches."""
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", "kmvp.hip"), "rb") as fh:
-        h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the matrix-core exponent kernel's source section (its traits and
+    kernel); the committed counter summary is used only while it matches."""
+    src = open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", "kmvp.hip")).read()
+    a = src.index("// ---------------------------------------------------------------- matrix-core exponent")
+    b = src.index("// qw_j = q_j * w_j", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def read_traffic(name: str):
@@ -366,6 +366,44 @@ def workload_matern(args, api, native, workloads, torch) -> dict:
             "speedup_fgmres_vs_cg64": tc / tf}
 
 
+def workload_sweep(args, api, native, workloads, torch) -> dict:
+    """The preconditioner's parameter study (section 5.3-5.4): 2000 points in the
+    unit cube, Gaussian kernel with three bandwidths (conditioning), flexible
+    GMRES and flexible CG over the inner shift delta and the inner tolerance
+    epsilon; outer and inner iteration counts and times per setting.  The
+    paper's figures for this study are not available: the table is reported,
+    not compared."""
+    import numpy as np
+
+    rng = np.random.default_rng(11)
+    n = 2000
+    xs = rng.random((n, 3))
+    y = rng.standard_normal(n)
+    x = torch.from_numpy(xs).cuda()
+    yt = torch.from_numpy(y).cuda()
+    gamma = 1e-6
+    rows = []
+    for sigma in (0.05, 0.1, 0.2):
+        for mode in ("fgmres", "fcg"):
+            for delta in (1e-4, 1e-3, 1e-2, 1e-1):
+                for eps in (1e-2, 1e-4, 1e-6):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    (w,), (info,) = api.krr_solve([x], [sigma], [gamma], [yt], mode=mode, delta=delta, inner_tol=eps,
+                                                  inner_maxit=500, restart_m=200, max_outer=200, inner_prec="fp32")
+                    torch.cuda.synchronize()
+                    rows.append({"sigma": sigma, "mode": mode, "delta": delta, "eps": eps, "status": info["status"],
+                                 "outer": info["outer_iters"], "inner": info["inner_iters"],
+                                 "relres": float(f"{info['relres_true']:.3e}"),
+                                 "time_ms": round(1e3 * (time.perf_counter() - t0), 2)})
+            log(f"sigma {sigma} done")
+    return {"metric": METRIC, "value": None, "unit": "table", "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
+            "higher_is_better": True, "vs_baseline": None,
+            "config": {"workload": "parameter study: N=2000 U[0,1]^3, gamma=1e-6, sigma in {0.05, 0.1, 0.2}; "
+                                   "delta in {1e-4..1e-1}, inner tolerance in {1e-2, 1e-4, 1e-6}, tol 1e-6"},
+            "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,7 +414,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
     ap.add_argument("--kernel-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision of the --kernel-only products")
-    ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern"),
+    ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "sweep"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
                     help="outer-step budget of the secondary workloads (clustered: default 8; others: "
@@ -399,7 +437,7 @@ def main() -> int:
         return 2
     native.load()
     others = {"clustered": workload_clustered, "batched": workload_batched, "gp": workload_gp,
-              "matern": workload_matern}
+              "matern": workload_matern, "sweep": workload_sweep}
     if args.workload in others:
         out = others[args.workload](args, api, native, workloads, torch)
         print(json.dumps(out), flush=True)

@@ -139,7 +139,8 @@ typedef enum {
     KRR_WS_CG_INNER = 3,
     KRR_WS_FGMRES = 4,
     KRR_WS_SOLVE = 5,
-    KRR_WS_KMVP_CROSS = 6
+    KRR_WS_KMVP_CROSS = 6,
+    KRR_WS_PREDICT = 7
 } krr_ws_call;
 
 void krr_default_opts(krr_fgmres_opts *opts /* host */);
@@ -147,7 +148,8 @@ const char *krr_status_string(int status);
 
 /* Bytes of workspace needed by call `which` for the given problem(s).
  * probs: host array of nprob point sets (only n and d are read); for
- * KRR_WS_KMVP_CROSS probs[0] are the targets and probs[1] the sources.  nrhs is
+ * KRR_WS_KMVP_CROSS probs[0] are the targets and probs[1] the sources, for
+ * KRR_WS_PREDICT probs[0] the training and probs[1] the test points.  nrhs is
  * the number of right-hand sides (multi products, krr_solve).  opts may be NULL
  * (defaults).  Returns 0 for invalid arguments. */
 size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob, int32_t nrhs,
@@ -237,6 +239,23 @@ int krr_solve(const krr_points *probs /* host */, int32_t nprob, const double *s
               int32_t mode, const krr_fgmres_opts *opts /* host, may be NULL */,
               krr_info *infos /* host, may be NULL */, void *ws, size_t ws_bytes,
               krr_stream_t stream);
+
+/* GPR prediction (section 2.1): at the m test points, the posterior mean
+ * (eq. GPR_mean; with w = (K_hat + gamma I)^{-1} y from a solve, mean = K_hat(test,
+ * train) w, also the kriging interpolant of eq. Kriging) and, when var is not
+ * NULL, the posterior variance
+ *   var_j = k(x*_j, x*_j) - k_j^T (K_hat + gamma I)^{-1} k_j,  k_j = K_hat(train, x*_j),
+ * by multi-right-hand-side solves of the training system (16 test points per
+ * batch; krr_solve with opts, mode FGMRES).  train, test: n x d and m x d
+ * row-major double (device); w: double[n]; mean, var: double[m] (device).
+ * opts->kernel selects the kernel (sigma: bandwidth or length scale).  infos
+ * (host, may be NULL): m entries, the solve of test point j.  Workspace:
+ * krr_workspace_size(KRR_WS_PREDICT, {train, test}, 2, 1, opts).  Returns the
+ * worst solve status (KRR_OK when var is NULL) or an error. */
+int krr_predict(const krr_points *train /* host */, const krr_points *test /* host */, double sigma,
+                double gamma, const double *w, double *mean, double *var,
+                const krr_fgmres_opts *opts /* host, may be NULL */, krr_info *infos /* host, may be NULL */,
+                void *ws, size_t ws_bytes, krr_stream_t stream);
 
 /* Launch timing of the kernel products (measurement support).  Between
  * krr_profile_begin() and krr_profile_end() every kernel-product launch made by

@@ -217,3 +217,24 @@ def probe_issue_rates(device="cuda") -> dict:
     N.check(lib.krr_probe_issue_rates(rates, ws.data_ptr(), ws.numel(), _stream()), "krr_probe_issue_rates")
     return {"fma_lane_ops_s": rates[0], "exp_fma_pairs_s": rates[1], "mfma_pairs_s": rates[2],
             "mg_mix_pairs_s": rates[3]}
+
+
+def krr_predict(x_train: torch.Tensor, x_test: torch.Tensor, sigma: float, gamma: float, w: torch.Tensor,
+                want_var: bool = True, ws: torch.Tensor | None = None, **opts):
+    """GPR posterior mean K_hat(test, train) w and (want_var) variance at the test
+    points.  Returns (mean, var or None, info dicts of the variance solves)."""
+    tr, te = _points(x_train), _points(x_test)
+    n, m = x_train.shape[0], x_test.shape[0]
+    w = _vec(w, n, torch.float64, "w")
+    mean = torch.empty(m, dtype=torch.float64, device=x_train.device)
+    var = torch.empty(m, dtype=torch.float64, device=x_train.device) if want_var else None
+    o = make_opts(**opts)
+    need = N.workspace_size(N.KRR_WS_PREDICT, [(n, x_train.shape[1]), (m, x_test.shape[1])], opts=o)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, x_train.device)
+    infos = (N.Info * m)()
+    rc = N.load().krr_predict(ctypes.byref(tr), ctypes.byref(te), float(sigma), float(gamma), w.data_ptr(),
+                              mean.data_ptr(), var.data_ptr() if want_var else None, ctypes.byref(o), infos,
+                              ws.data_ptr(), ws.numel(), _stream())
+    N.check(rc, "krr_predict")
+    return mean, var, ([i.as_dict() for i in infos] if want_var else [])

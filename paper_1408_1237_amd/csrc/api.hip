@@ -230,6 +230,17 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
                 if (probs[k].n < 1 || probs[k].d < 1 || probs[k].d > KRR_MAX_DIM) return 0;
             if (probs[0].d != probs[1].d) return 0;
             return carve_cross(nullptr, probs[0].n, probs[1].n, probs[0].d).total + 256;
+        case KRR_WS_PREDICT: {
+            if (nprob < 2) return 0;
+            for (int k = 0; k < 2; ++k)
+                if (probs[k].n < 1 || probs[k].d < 1 || probs[k].d > KRR_MAX_DIM) return 0;
+            if (probs[0].d != probs[1].d) return 0;
+            const size_t cross = carve_cross(nullptr, probs[1].n, probs[0].n, probs[0].d).total;
+            const size_t solve = krr_workspace_size(KRR_WS_SOLVE, probs, 1, 16, opts);
+            if (solve == 0) return 0;
+            const size_t var = predict_var_bytes(probs[0].n) + solve;
+            return (cross > var ? cross : var) + 512;
+        }
         case KRR_WS_SOLVE: {
             if (nrhs < 1) return 0;
             size_t mx = 0;
@@ -309,8 +320,8 @@ int kmvp_gauss_multi(const krr_points *pts, double sigma, double shift, int32_t 
     return KRR_OK;
 }
 
-int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, double sigma, int32_t prec,
-                     const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
+static int kmvp_cross_impl(const krr_points *targets, const krr_points *sources, int kernel, double sigma,
+                           int32_t prec, const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
     int rc;
     if ((rc = check_points(targets)) || (rc = check_points(sources)) || (rc = check_sigma(sigma)) ||
         (rc = check_prec(prec)))
@@ -322,8 +333,8 @@ int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, doubl
     if (L.total > ws_bytes) return KRR_EWORKSPACE;
     L = carve_cross(ws, targets->n, sources->n, targets->d);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    KRR_HIP_STATUS(prepare_points(L.T, targets->x, sigma, L.temp, L.temp_bytes, s));
-    KRR_HIP_STATUS(prepare_points(L.S, sources->x, sigma, L.temp, L.temp_bytes, s));
+    KRR_HIP_STATUS(prepare_points(L.T, targets->x, sigma, L.temp, L.temp_bytes, s, kernel));
+    KRR_HIP_STATUS(prepare_points(L.S, sources->x, sigma, L.temp, L.temp_bytes, s, kernel));
     if (prec == KRR_FP64) {
         KRR_HIP_STATUS((gather_sorted<double, double>(L.S, static_cast<const double *>(q), static_cast<double *>(L.q), s)));
         KRR_HIP_STATUS(kmvp_cross_sorted(L.T, L.S, prec, L.q, L.y, L.ksc, s));
@@ -340,6 +351,11 @@ int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, doubl
         KRR_HIP_STATUS((scatter_sorted<float, float>(L.T, static_cast<float *>(L.y), static_cast<float *>(y), s)));
     }
     return KRR_OK;
+}
+
+int kmvp_gauss_cross(const krr_points *targets, const krr_points *sources, double sigma, int32_t prec,
+                     const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
+    return kmvp_cross_impl(targets, sources, KRR_KERNEL_GAUSS, sigma, prec, q, y, ws, ws_bytes, stream);
 }
 
 int kmvp_grad(const krr_points *pts, double sigma, double gamma, int32_t prec, const double *lam, const double *w,
@@ -485,6 +501,51 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
                            W[k] + static_cast<size_t>(r) * ld, true, mode, o, inf, ws, ws_bytes, s);
             if (rc < 0) return rc;
             if (rc > worst) worst = rc;
+        }
+    }
+    return worst;
+}
+
+int krr_predict(const krr_points *train, const krr_points *test, double sigma, double gamma, const double *w,
+                double *mean, double *var, const krr_fgmres_opts *opts, krr_info *infos, void *ws, size_t ws_bytes,
+                krr_stream_t stream) {
+    int rc;
+    if ((rc = check_points(train)) || (rc = check_points(test)) || (rc = check_sigma(sigma))) return rc;
+    if (train->d != test->d || !is_fin(gamma) || gamma < 0.0 || w == nullptr || mean == nullptr) return KRR_EINVAL;
+    SolverOpts o;
+    if ((rc = resolve_opts(opts, gamma, o)) != KRR_OK) return rc;
+    const krr_points probs[2] = {*train, *test};
+    const size_t need = krr_workspace_size(KRR_WS_PREDICT, probs, 2, 1, opts);
+    if (ws == nullptr || need == 0 || ws_bytes < need) return KRR_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // mean = K_hat(test, train) w (FP64)
+    if ((rc = kmvp_cross_impl(test, train, o.kernel, sigma, KRR_FP64, w, mean, ws, ws_bytes, stream)) != KRR_OK)
+        return rc;
+    if (var == nullptr) return KRR_OK;
+    // variance: 16 test points per multi-right-hand-side solve
+    void *base = align_ws(ws, ws_bytes);
+    const int64_t n = train->n, m = test->n;
+    Carver cv(base);
+    double *B = cv.take<double>(static_cast<size_t>(n) * 16);
+    double *Wb = cv.take<double>(static_cast<size_t>(n) * 16);
+    void *sws = cv.take<char>(0);
+    const size_t sbytes = ws_bytes - cv.off;
+    krr_fgmres_opts oo;
+    if (opts) oo = *opts;
+    else krr_default_opts(&oo);
+    int worst = KRR_OK;
+    krr_info binfo[16];
+    for (int64_t j0 = 0; j0 < m; j0 += 16) {
+        KRR_HIP_STATUS(predict_kernel_block(train->x, n, train->d, test->x, m, j0, sigma, o.kernel, B, s));
+        const double *Yp[1] = {B};
+        double *Wp[1] = {Wb};
+        const int64_t ld[1] = {n};
+        rc = krr_solve(train, 1, &sigma, &gamma, 16, Yp, ld, Wp, KRR_MODE_FGMRES, &oo, binfo, sws, sbytes, stream);
+        if (rc < 0) return rc;
+        KRR_HIP_STATUS(predict_var_block(B, Wb, n, m, j0, var, s));
+        for (int c = 0; c < 16 && j0 + c < m; ++c) {
+            if (infos) infos[j0 + c] = binfo[c];
+            if (binfo[c].status > worst) worst = binfo[c].status;
         }
     }
     return worst;

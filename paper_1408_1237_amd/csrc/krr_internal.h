@@ -207,6 +207,14 @@ int profile_end(krr_profile_stats *out);
 size_t probe_workspace_bytes();
 hipError_t probe_issue_rates(double *rates, void *ws, hipStream_t s);
 
+// GPR prediction (predict.hip): the n x 16 block of kernel columns of test
+// points j0..j0+15 and the variance reduction 1 - k_j^T W_j.
+size_t predict_var_bytes(int64_t n);  // the block and its solution
+hipError_t predict_kernel_block(const double *x, int64_t n, int d, const double *xs, int64_t m, int64_t j0,
+                                double sigma, int kernel, double *B, hipStream_t s);
+hipError_t predict_var_block(const double *B, const double *W, int64_t n, int64_t m, int64_t j0, double *var,
+                             hipStream_t s);
+
 // Progress lines on stderr: KRR_PROGRESS=k prints one line every k outer steps
 // of a solve (0 or unset: silent).
 int progress_every();

@@ -23,12 +23,12 @@ KRR_KERNEL_GAUSS, KRR_KERNEL_MATERN32 = 0, 1
 KERNEL = {"gauss": KRR_KERNEL_GAUSS, "matern32": KRR_KERNEL_MATERN32}
 KRR_MODE_FGMRES, KRR_MODE_CG64, KRR_MODE_GMRES, KRR_MODE_FCG = 0, 1, 2, 3
 (KRR_WS_KMVP, KRR_WS_KMVP_MULTI, KRR_WS_KMVP_GRAD, KRR_WS_CG_INNER, KRR_WS_FGMRES, KRR_WS_SOLVE,
- KRR_WS_KMVP_CROSS) = range(7)
+ KRR_WS_KMVP_CROSS, KRR_WS_PREDICT) = range(8)
 KRR_MAX_DIM = 64
 
 EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss", "kmvp_matern",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
-            "krr_solve", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
+            "krr_solve", "krr_predict", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
             "krr_probe_issue_rates")
 
 
@@ -98,6 +98,9 @@ def load(path: str | None = None):
         lib.fgmres_solve.argtypes = [_P(Points), _dbl, _dbl, _vp, _vp, _P(Opts), _P(Info), _vp, _sz, _vp]
         lib.krr_solve.argtypes = [_P(Points), _i32, _P(_dbl), _P(_dbl), _i32, _P(_vp), _P(_i64), _P(_vp), _i32,
                                   _P(Opts), _P(Info), _vp, _sz, _vp]
+        lib.krr_predict.argtypes = [_P(Points), _P(Points), _dbl, _dbl, _vp, _vp, _vp, _P(Opts), _P(Info), _vp, _sz,
+                                    _vp]
+        lib.krr_predict.restype = ctypes.c_int
         lib.krr_profile_begin.argtypes = [_i32]
         lib.krr_profile_begin.restype = ctypes.c_int
         lib.krr_profile_end.argtypes = [_P(ProfileStats)]
