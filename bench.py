@@ -370,9 +370,11 @@ def workload_sweep(args, api, native, workloads, torch) -> dict:
     """The preconditioner's parameter study (section 5.3-5.4): 2000 points in the
     unit cube, Gaussian kernel with three bandwidths (conditioning), flexible
     GMRES and flexible CG over the inner shift delta and the inner tolerance
-    epsilon; outer and inner iteration counts and times per setting.  The
-    paper's figures for this study are not available: the table is reported,
-    not compared."""
+    epsilon; outer and inner iteration counts and times per setting.  Then the
+    plain FP64 CG over bandwidth and regulariser (section 3): iterations and
+    the condition number estimated from the CG's Lanczos coefficients.  The
+    paper's figures for these studies are not in its text: the tables are
+    reported, not compared."""
     import numpy as np
 
     rng = np.random.default_rng(11)
@@ -397,11 +399,28 @@ def workload_sweep(args, api, native, workloads, torch) -> dict:
                                  "relres": float(f"{info['relres_true']:.3e}"),
                                  "time_ms": round(1e3 * (time.perf_counter() - t0), 2)})
             log(f"sigma {sigma} done")
+    # condition number and plain CG iterations over bandwidth and regulariser
+    # (section 3): the condition number estimated from the CG's own Lanczos
+    # coefficients, the iteration count to the same tolerance
+    cond = []
+    for sigma in (0.025, 0.05, 0.1, 0.2, 0.4):
+        for gamma_c in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            (w,), (info,) = api.krr_solve([x], [sigma], [gamma_c], [yt], mode="cg64", max_outer=20000)
+            torch.cuda.synchronize()
+            lo, hi = info["lambda_min_est"], info["lambda_max_est"]
+            cond.append({"sigma": sigma, "gamma": gamma_c, "status": info["status"], "cg_iters": info["outer_iters"],
+                         "lambda_min_est": float(f"{lo:.4e}"), "lambda_max_est": float(f"{hi:.4e}"),
+                         "cond_est": float(f"{hi / lo:.3e}") if lo > 0 else None,
+                         "time_ms": round(1e3 * (time.perf_counter() - t0), 2)})
+        log(f"cg sigma {sigma} done")
     return {"metric": METRIC, "value": None, "unit": "table", "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
             "higher_is_better": True, "vs_baseline": None,
             "config": {"workload": "parameter study: N=2000 U[0,1]^3, gamma=1e-6, sigma in {0.05, 0.1, 0.2}; "
-                                   "delta in {1e-4..1e-1}, inner tolerance in {1e-2, 1e-4, 1e-6}, tol 1e-6"},
-            "rows": rows}
+                                   "delta in {1e-4..1e-1}, inner tolerance in {1e-2, 1e-4, 1e-6}, tol 1e-6; "
+                                   "FP64 CG over sigma in {0.025..0.4} x gamma in {1e-1..1e-6}"},
+            "rows": rows, "cg_condition": cond}
 
 
 def main() -> int:

@@ -120,6 +120,15 @@ typedef struct {
     double relres_true;    /* ||y - K w|| / ||y|| from an FP64 product at exit */
     double relres_est;     /* the solver's own last estimate */
     double t_total_ms;     /* host wall time of the call */
+    /* Plain CG (KRR_MODE_CG64) only, else 0: the smallest and largest eigenvalue
+     * of K_hat + gamma I estimated from the first CG run's coefficients (the
+     * extreme Ritz values of its Lanczos tridiagonal, krr_lanczos_extremes); their
+     * ratio estimates the condition number that sets CG's convergence (section 3,
+     * the need for preconditioning in section 5).  lambda_max_est converges in a
+     * few iterations; lambda_min_est approaches the true value from above as CG
+     * converges, so the ratio is a lower estimate of the condition number. */
+    double lambda_min_est;
+    double lambda_max_est;
 } krr_info;
 
 /* Solver modes of krr_solve. */
@@ -256,6 +265,19 @@ int krr_predict(const krr_points *train /* host */, const krr_points *test /* ho
                 double gamma, const double *w, double *mean, double *var,
                 const krr_fgmres_opts *opts /* host, may be NULL */, krr_info *infos /* host, may be NULL */,
                 void *ws, size_t ws_bytes, krr_stream_t stream);
+
+/* Extreme eigenvalues of the k x k Lanczos tridiagonal of a conjugate gradient
+ * run (section 3: CG on a symmetric positive definite matrix is the Lanczos
+ * process; the condition number bounds its convergence).  alpha[j] is the j-th
+ * step length and beta[j] = r_{j+1}.r_{j+1} / r_j.r_j (j = 0 .. k-1; beta[k-1] is
+ * not used).  The tridiagonal has diagonal 1/alpha_0 and
+ * 1/alpha_j + beta_{j-1}/alpha_{j-1} (j >= 1) and off-diagonal
+ * sqrt(beta_{j-1})/alpha_{j-1}; its extreme eigenvalues are found by Sturm-count
+ * bisection to about 1e-15 relative.  Host arrays; host computation only (no
+ * device call).  Returns KRR_OK, or KRR_EINVAL for null pointers, k < 1, or a
+ * non-finite or non-positive alpha or negative beta. */
+int krr_lanczos_extremes(const double *alpha /* host, k */, const double *beta /* host, k */, int32_t k,
+                         double *lambda_min /* host */, double *lambda_max /* host */);
 
 /* Launch timing of the kernel products (measurement support).  Between
  * krr_profile_begin() and krr_profile_end() every kernel-product launch made by

@@ -7,7 +7,8 @@ meet only in the seeded input generators of ``paper_1408_1237_amd.workloads``.
 
 The arithmetic lives in ``krr_oracle.c`` (plain FP64 loops, libm ``exp``).  This
 module compiles it with gcc on first use and wraps every routine with numpy
-argument marshalling; it adds no arithmetic of its own.
+argument marshalling; its own arithmetic is limited to library primitives named
+where they are used (norms, a symmetric eigenvalue routine).
 """
 from __future__ import annotations
 
@@ -292,6 +293,15 @@ def true_relres(x, sigma: float, gamma: float, y, w) -> float:
     """||y - (K_hat + gamma I) w|| / ||y|| with the on-the-fly FP64 product."""
     r = _f64(y) - mvp(x, sigma, _f64(w), gamma)
     return float(np.linalg.norm(r) / np.linalg.norm(y))
+
+
+def eig_extremes(x, sigma: float, gamma: float) -> tuple[float, float]:
+    """Smallest and largest eigenvalue of the explicit K_hat + gamma I (eq.
+    kernelMatrix); their ratio is the condition number that section 3 ties to
+    CG's iteration count.  numpy's symmetric eigenvalue routine is the step."""
+    x, n, d = _pts(x)
+    ev = np.linalg.eigvalsh(kernel_matrix(x, sigma) + gamma * np.eye(n))
+    return float(ev[0]), float(ev[-1])
 
 
 # ---------------------------------------------------------------- Matern-3/2 (section 6)

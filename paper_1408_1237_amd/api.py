@@ -219,6 +219,22 @@ def probe_issue_rates(device="cuda") -> dict:
             "mg_mix_pairs_s": rates[3]}
 
 
+def lanczos_extremes(alpha, beta) -> tuple[float, float]:
+    """Extreme eigenvalues of a CG run's Lanczos tridiagonal from its step
+    lengths alpha_j and residual ratios beta_j (host computation in the
+    library; see krr_lanczos_extremes)."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if a.ndim != 1 or b.shape != a.shape:
+        raise ValueError("alpha and beta must be 1-D arrays of the same length")
+    lo, hi = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    N.check(N.load().krr_lanczos_extremes(a.ctypes.data_as(dp), b.ctypes.data_as(dp), int(a.size),
+                                          ctypes.byref(lo), ctypes.byref(hi)), "krr_lanczos_extremes")
+    return lo.value, hi.value
+
+
 def krr_predict(x_train: torch.Tensor, x_test: torch.Tensor, sigma: float, gamma: float, w: torch.Tensor,
                 want_var: bool = True, ws: torch.Tensor | None = None, **opts):
     """GPR posterior mean K_hat(test, train) w and (want_var) variance at the test

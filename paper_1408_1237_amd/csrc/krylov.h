@@ -22,6 +22,8 @@ struct CgVecs {
     T *x = nullptr, *r = nullptr, *p = nullptr, *Ap = nullptr;
     uint16_t *p16 = nullptr;  // only for the bf16 product
     CgScalars<T> *S = nullptr;
+    double *hist = nullptr;   // optional (alpha_k, beta_k) history, hist_cap pairs
+    int hist_cap = 0;
 };
 
 int vec_blocks(int64_t n_pad);

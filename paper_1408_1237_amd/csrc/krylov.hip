@@ -111,11 +111,13 @@ __global__ __launch_bounds__(BLOCK) void k_cg_alpha(int64_t n_pad, const T *__re
     }
 }
 
-// x += alpha p, r -= alpha Ap, rr' = r.r, beta = rr'/rr; stop tests.
+// x += alpha p, r -= alpha Ap, rr' = r.r, beta = rr'/rr; stop tests.  With a
+// history array, iteration k stores (alpha_k, beta_k) at hist[2k], hist[2k+1]
+// while k < hist_cap (the coefficients of the Lanczos tridiagonal).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cg_update(int64_t n_pad, T *x, T *r, const T *__restrict__ p,
                                                      const T *__restrict__ Ap, CgScalars<T> *S, T *partials,
-                                                     unsigned *counter) {
+                                                     unsigned *counter, double *hist, int hist_cap) {
     if (S->active == 0) return;
     const T a = S->alpha;
     T acc[1] = {T(0)};
@@ -129,6 +131,10 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(int64_t n_pad, T *x, T *r, 
         const T rr = acc[0];
         S->beta = rr / S->rr;
         S->rr = rr;
+        if (hist != nullptr && S->iters < hist_cap) {
+            hist[2 * S->iters] = static_cast<double>(S->alpha);
+            hist[2 * S->iters + 1] = static_cast<double>(S->beta);
+        }
         S->iters += 1;
         if (!isfinite(static_cast<double>(rr))) {
             S->status = KRR_BREAKDOWN;
@@ -405,7 +411,7 @@ hipError_t cg_step(const Prepared &P, int prec, double shift, const CgVecs<T> &c
     const int nb = vec_blocks(c.n_pad);
     T *part = reinterpret_cast<T *>(R.partials);
     LAUNCH(k_cg_alpha<T>, nb, c.n_pad, c.p, c.Ap, c.S, part, R.counters + 1);
-    LAUNCH(k_cg_update<T>, nb, c.n_pad, c.x, c.r, c.p, c.Ap, c.S, part, R.counters + 2);
+    LAUNCH(k_cg_update<T>, nb, c.n_pad, c.x, c.r, c.p, c.Ap, c.S, part, R.counters + 2, c.hist, c.hist_cap);
     LAUNCH(k_cg_pupdate<T>, nb, c.n_pad, c.r, c.p, c.p16, c.S);
     return hipGetLastError();
 }

@@ -38,6 +38,7 @@ struct SolverWork {
     uint16_t *p16 = nullptr;
     KmvpScratch ksc;
     StatusBlock *status = nullptr;
+    double *cghist = nullptr;  // plain CG: (alpha_k, beta_k) for k < max_outer
     Red R;
 };
 

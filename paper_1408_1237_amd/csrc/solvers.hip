@@ -7,11 +7,13 @@
 //    truncated inner CG on its own.
 // The drivers only enqueue kernels; they read a small status block back once per
 // outer step (FGMRES) or per group of iterations (plain CG).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
 #include <cstdio>
 
+#include <vector>
 #include "solvers.h"
 
 namespace krr {
@@ -47,6 +49,8 @@ SolverWork carve_solver(Carver &cv, const Prepared &P, const SolverOpts &o, bool
         W.Ap32 = cv.take<float>(np);
         W.p16 = cv.take<uint16_t>(np);
         W.z64 = cv.take<double>(np);
+    } else {
+        W.cghist = cv.take<double>(2 * static_cast<size_t>(o.max_outer > 0 ? o.max_outer : 1));
     }
     W.ksc = carve_kmvp_scratch(cv, P);
     W.status = cv.take<StatusBlock>(1);
@@ -340,8 +344,11 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
     c.p = W.p64;
     c.Ap = W.Ap64;
     c.S = &W.status->c64;
+    c.hist = W.cghist;
+    c.hist_cap = o.max_outer;
     StatusBlock st;
     int64_t mvp64 = 0;
+    int lanczos_k = -1;  // iterations of the first CG run (before any restart)
     int cycles = 1;
     int result = KRR_NOT_CONVERGED;
     double relres = 1.0;
@@ -371,6 +378,7 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
         }
         if (st.c64.candidate || st.c64.active == 0) {
             // confirm with the true residual b - K x; restart from it if needed
+            if (lanczos_k < 0) lanczos_k = st.c64.iters;
             KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, c.x, W.Ap64, W.ksc, nullptr, s));
             ++mvp64;
             KRR_HIP_STATUS(cg_restart<double>(c, W.b, W.Ap64, W.R, s));
@@ -393,6 +401,23 @@ int cg64_sorted(const Prepared &P, double gamma, const SolverOpts &o, const Solv
         info->mvp32 = info->mvp16 = 0;
         info->relres_true = relres;
         info->relres_est = std::sqrt(st.c64.rr / st.c64.rr0);
+        info->lambda_min_est = info->lambda_max_est = 0.0;
+        const int k = std::min(lanczos_k < 0 ? st.c64.iters : lanczos_k, o.max_outer);
+        if (k > 0) {
+            std::vector<double> h(2 * static_cast<size_t>(k));
+            KRR_HIP_STATUS(hipMemcpyAsync(h.data(), W.cghist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            KRR_HIP_STATUS(hipStreamSynchronize(s));
+            std::vector<double> a(k), b(k);
+            for (int j = 0; j < k; ++j) {
+                a[j] = h[2 * j];
+                b[j] = h[2 * j + 1];
+            }
+            double lo = 0.0, hi = 0.0;
+            if (krr_lanczos_extremes(a.data(), b.data(), k, &lo, &hi) == KRR_OK) {
+                info->lambda_min_est = lo;
+                info->lambda_max_est = hi;
+            }
+        }
     }
     return result;
 }

@@ -29,7 +29,7 @@ KRR_MAX_DIM = 64
 EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss", "kmvp_matern",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
             "krr_solve", "krr_predict", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
-            "krr_probe_issue_rates")
+            "krr_probe_issue_rates", "krr_lanczos_extremes")
 
 
 class Points(ctypes.Structure):
@@ -56,7 +56,8 @@ class Info(ctypes.Structure):
                 ("inner_iters", ctypes.c_int32), ("cycles", ctypes.c_int32),
                 ("mvp64", ctypes.c_int64), ("mvp32", ctypes.c_int64), ("mvp16", ctypes.c_int64),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("lambda_min_est", ctypes.c_double),
+                ("lambda_max_est", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +109,8 @@ def load(path: str | None = None):
         lib.krr_probe_workspace_size.argtypes = []
         lib.krr_probe_issue_rates.restype = ctypes.c_int
         lib.krr_probe_issue_rates.argtypes = [_P(_dbl), _vp, _sz, _vp]
+        lib.krr_lanczos_extremes.restype = ctypes.c_int
+        lib.krr_lanczos_extremes.argtypes = [_P(_dbl), _P(_dbl), _i32, _P(_dbl), _P(_dbl)]
         lib.krr_profile_end.restype = ctypes.c_int
         for name in ("kmvp_gauss", "kmvp_matern", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
                      "fgmres_solve", "krr_solve"):

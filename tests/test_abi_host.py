@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1408_1237_amd import native as N
@@ -99,3 +100,58 @@ def test_probe_rejects_bad_arguments_on_the_host():
     rates = (ctypes.c_double * 4)()
     assert lib.krr_probe_issue_rates(rates, None, 0, None) == N.KRR_EWORKSPACE
     assert lib.krr_probe_issue_rates(None, None, 0, None) == N.KRR_EINVAL
+
+
+def _textbook_cg_coefficients(A, b, k):
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    alpha, beta = [], []
+    for _ in range(k):
+        Ap = A @ p
+        a = rr / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        rr_new = r @ r
+        alpha.append(a)
+        beta.append(rr_new / rr)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return np.array(alpha), np.array(beta)
+
+
+def test_lanczos_extremes_recover_the_spectrum():
+    # host-only computation: after n steps of CG on an n x n SPD matrix the
+    # Lanczos tridiagonal has the matrix's eigenvalues; after one step its only
+    # Ritz value is the Rayleigh quotient of the right-hand side
+    from paper_1408_1237_amd import api
+    rng = np.random.default_rng(4)
+    n = 24
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.linspace(0.5, 20.0, n)
+    A = (Q * ev) @ Q.T
+    b = rng.standard_normal(n)
+    al, be = _textbook_cg_coefficients(A, b, n)
+    lo, hi = api.lanczos_extremes(al, be)
+    assert lo == pytest.approx(0.5, rel=1e-8) and hi == pytest.approx(20.0, rel=1e-8)
+    al1, be1 = _textbook_cg_coefficients(A, b, 1)
+    lo1, hi1 = api.lanczos_extremes(al1, be1)
+    assert lo1 == pytest.approx(b @ A @ b / (b @ b), rel=1e-14) and hi1 == lo1
+    # a partial run: Ritz values lie inside the spectrum, the largest close to it
+    alp, bep = _textbook_cg_coefficients(A, b, 12)
+    lop, hip = api.lanczos_extremes(alp, bep)
+    assert 0.5 * (1 - 1e-12) <= lop <= hip <= 20.0 * (1 + 1e-12)
+
+
+def test_lanczos_extremes_rejects_bad_input():
+    lib = N.load()
+    d = ctypes.c_double
+    a = (d * 2)(1.0, -1.0)
+    b = (d * 2)(0.5, 0.5)
+    lo, hi = d(0.0), d(0.0)
+    assert lib.krr_lanczos_extremes(a, b, 2, ctypes.byref(lo), ctypes.byref(hi)) == N.KRR_EINVAL
+    assert lib.krr_lanczos_extremes(a, b, 0, ctypes.byref(lo), ctypes.byref(hi)) == N.KRR_EINVAL
+    assert lib.krr_lanczos_extremes(None, b, 1, ctypes.byref(lo), ctypes.byref(hi)) == N.KRR_EINVAL
+    assert lib.krr_lanczos_extremes(a, b, 1, ctypes.byref(lo), ctypes.byref(hi)) == N.KRR_OK
+    assert lo.value == pytest.approx(1.0) and hi.value == pytest.approx(1.0)

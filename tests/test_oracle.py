@@ -497,3 +497,35 @@ def test_predict_matches_scikit_learn_gpr():
         mean, var = oracle.predict(x, xs, 0.4, 0.01, y, kernel=name)
         assert np.allclose(mean, m_ref, rtol=1e-8, atol=1e-10)
         assert np.allclose(np.sqrt(np.maximum(var, 0.0)), s_ref, rtol=1e-6, atol=1e-8)
+
+
+def test_eig_extremes_closed_forms():
+    # spectrum of K_hat + gamma I for point sets whose kernel matrix is known
+    # exactly: n coincident points give 1 1^T (eigenvalues n and 0), far points
+    # give I, two points give [[1, k], [k, 1]] (eigenvalues 1 -+ k)
+    g = 1e-3
+    lo, hi = oracle.eig_extremes(np.zeros((7, 3)), 0.5, g)
+    assert lo == pytest.approx(g, abs=1e-12) and hi == pytest.approx(7 + g, rel=1e-14)
+    far = np.arange(6, dtype=np.float64)[:, None] * 100.0
+    lo, hi = oracle.eig_extremes(far, 1.0, g)
+    assert lo == pytest.approx(1 + g, rel=1e-14) and hi == pytest.approx(1 + g, rel=1e-14)
+    a, b = np.array([0.0, 0.0]), np.array([0.3, 0.4])
+    k = np.exp(-0.25 / (2 * 0.5 ** 2))
+    lo, hi = oracle.eig_extremes(np.stack([a, b]), 0.5, g)
+    assert lo == pytest.approx(1 - k + g, rel=1e-13) and hi == pytest.approx(1 + k + g, rel=1e-13)
+
+
+def test_condition_grows_with_bandwidth_and_falls_with_regulariser():
+    # section 3 (the need for preconditioning): on uniform points in the unit cube
+    # a larger bandwidth or a smaller regulariser gives a worse-conditioned matrix
+    x = np.random.default_rng(0).random((300, 3))
+    kap = {}
+    for s in (0.05, 0.1, 0.2):
+        for g in (1e-2, 1e-4):
+            lo, hi = oracle.eig_extremes(x, s, g)
+            assert lo >= g * (1 - 1e-9) and hi <= 300 + g
+            kap[s, g] = hi / lo
+    assert kap[0.05, 1e-2] < kap[0.1, 1e-2] < kap[0.2, 1e-2]
+    assert kap[0.05, 1e-4] < kap[0.1, 1e-4] < kap[0.2, 1e-4]
+    for s in (0.05, 0.1, 0.2):
+        assert kap[s, 1e-2] < kap[s, 1e-4]
