@@ -44,27 +44,43 @@ METRIC = "kernel-MVP pairs/s + time to 1e-6 residual, mixed-prec FGMRES vs FP64 
 SIMD_CYCLES_S = 256 * 4 * 2.4e9
 VALU_LANE_OPS = SIMD_CYCLES_S * 16          # FMA lane-ops/s
 C_FMA, C_EXP, C_MFMA32, C_MFMA64 = 4, 8, 32, 64
+C_MFMA_H32 = 32                              # v_mfma_f32_32x32x16_f16 (1024 outputs x 16 slots)
+DIMS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64)
+
+
+def dpad(d: int) -> int:
+    """The compiled dimension the library runs d at."""
+    return next(p for p in DIMS if p >= d)
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     """Peak pairs/s of the product kernel that runs for dimension d and precision.
 
-    d <= 16 (matrix-core exponent kernel), per 1024 pairs (one wave, one 16-column
-    step): 4 ceil((d+1)/4) 16x16x4 matrix-core operations plus, per lane, 16
-    exponentials and 16 FMAs.  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs
-    and one exponential per lane.
+    d <= 16, per 1024 pairs (one wave-step) plus, per lane, 16 exponentials and
+    16 FMAs: FP32 / BF16 (split-f16 kernel) ceil((3D + 2) / 16) 32x32x16 f16
+    matrix-core operations; FP64 4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the
+    compiled dimension).  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs and
+    one exponential per lane.  Matrix-core and VALU issue counted one after the
+    other (measured by the issue probe).
     """
     tag = {"fp64": "FP64", "bf16": "BF16"}.get(prec, "FP32")
     if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
-        dk = (d + 4) // 4
+        D = dpad(d)
+        if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":
+            kc = (3 * D + 2 + 15) // 16
+            cyc = kc * C_MFMA_H32 + 16 * (C_EXP + C_FMA)
+            rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core op(s) + 16 x (exp2 + FMA) "
+                    f"per lane, serial issue; 1024 SIMDs x 2.4 GHz")
+            return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, {tag}>"
+        dk = (D + 4) // 4
         if prec == "fp64":
             cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64 + C_FMA)
         else:
             cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
                 f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
-        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mg<{d}, {tag}>"
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mg<{D}, {tag}>"
     if prec == "fp64":
         cyc = (d + 1) * C_FMA + C_EXP2_F64
     else:
@@ -88,10 +104,10 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the matrix-core exponent kernel's source section (its traits and
-    kernel); the committed counter summary is used only while it matches."""
+    """Hash of the split-f16 product kernel's source section; the committed
+    counter summary is used only while it matches."""
     src = open(os.path.join(ROOT, "paper_1408_1237_amd", "csrc", "kmvp.hip")).read()
-    a = src.index("// ---------------------------------------------------------------- matrix-core exponent")
+    a = src.index("// ---------------------------------------------------------------- split-f16 matrix-core exponent")
     b = src.index("// qw_j = q_j * w_j", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 

@@ -209,14 +209,14 @@ def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | N
 
 def probe_issue_rates(device="cuda") -> dict:
     """Measured issue rates of the device (see krr_probe_issue_rates): FMA
-    lane-ops/s, exp2+FMA pairs/s, matrix-core pairs/s, matrix-core exponent mix
-    pairs/s."""
+    lane-ops/s, exp2+FMA pairs/s, matrix-core pairs/s, the FP32 and split-f16
+    matrix-core exponent mixes' pairs/s."""
     lib = N.load()
     ws = workspace(int(lib.krr_probe_workspace_size()), torch.device(device))
-    rates = (ctypes.c_double * 4)()
+    rates = (ctypes.c_double * 5)()
     N.check(lib.krr_probe_issue_rates(rates, ws.data_ptr(), ws.numel(), _stream()), "krr_probe_issue_rates")
     return {"fma_lane_ops_s": rates[0], "exp_fma_pairs_s": rates[1], "mfma_pairs_s": rates[2],
-            "mg_mix_pairs_s": rates[3]}
+            "mg_mix_pairs_s": rates[3], "mh_mix_pairs_s": rates[4]}
 
 
 def lanczos_extremes(alpha, beta) -> tuple[float, float]:

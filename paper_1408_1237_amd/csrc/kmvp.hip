@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "krr_internal.h"
+#include "split16.h"
 
 namespace krr {
 
@@ -87,6 +88,8 @@ struct KArgs {
     const double *anchor;
     const double *tile_r2;
     const double *tile_nj;
+    const float *tile_far;       // split-f16 kernel: per-tile far threshold on |t|^2
+    const void *slots;           // split-f16 kernel: source slot octets of the product's precision
     const void *off;
     const void *q;
     const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
@@ -511,6 +514,239 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- split-f16 matrix-core exponent
+//
+// FP32 and BF16 products with the folded exponent formed by the f16 matrix
+// cores.  Every FP32 operand v is split as v = hi + lo, hi = f16(v),
+// lo = f16(v - hi): |v - hi - lo| <= 2^-24 |v| (f16 subnormals are kept), the
+// accuracy of the FP32 operand itself.  The exponent of the form above becomes
+// an inner product over 3d + 2 slots,
+//   arg_ij = sum_k ( o_hi 2t_hi + o_hi 2t_lo + o_lo 2t_hi )_jk,ik + c_hi + c_lo,
+// dropping only the lo * lo terms (below 2^-24 of each product); the products
+// are exact and accumulate in FP32 as in the FP32 matrix-core form.  One
+// v_mfma_f32_32x32x16_f16 covers 32 sources x 32 targets x 16 slots.  Its lane
+// layout: A (sources x slots) lane l holds source l % 32 and slots
+// 8 (l / 32) .. + 7; B (slots x targets) lane l holds target l % 32 and the same
+// slots; accumulator element v of lane l is source 8 (v / 4) + 4 (l / 32) + v % 4
+// against target l % 32.  A wave owns 2 groups of 32 targets (64 rows).
+//
+// A target whose every pair with the tile has arg <= -200 (so that exp2 is 0 in
+// FP32 either way) gets the exponent -2000 for the whole tile; the others have
+// |c| < 640 and |2t| < 50 on tiles with R^2 <= 64, inside the f16 range.  Wide
+// tiles (R^2 > 64, offsets possibly beyond the f16 range) are staged as plain
+// FP32 offsets in the same LDS words and take the direct form.
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using Off = typename P::Off;
+    using Q = typename P::Q;
+    constexpr int NS = 3 * D + 2;       // slots of the split inner product
+    constexpr int KC = (NS + 15) / 16;  // 16-slot chunks
+    constexpr int RG = 2;               // groups of 32 targets per wave
+    static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
+    // sources of the current column tile, double-buffered: their slot vectors
+    // ([buffer][chunk * 2 + half][source], 8 slots each) and q w (or q on wide tiles)
+    __shared__ __align__(16) half8_t s_a[2][2 * KC][TILE];
+    __shared__ __align__(16) float s_q[2][TILE];
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const float *__restrict__ qw = static_cast<const float *>(a.qw);
+    const int64_t n_pad = a.n_pad;
+
+    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE;
+    const int r32 = lane % 32, h = lane / 32;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (tid / WAVE) * 64;
+
+    double aI[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
+    float oi[RG][D];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+        for (int k = 0; k < D; ++k) oi[rg][k] = P::off(row_off[k * a.n_pad_rows + row0 + rg * 32 + r32]);
+    float acc[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.f;
+    float *__restrict__ out = static_cast<float *>(a.out);
+
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    // staging registers: this thread's source of the next tile, its slot octets
+    // (prepared with the points) or, on wide tiles, its plain FP32 offsets
+    // (coordinate k in word k % 4 of octet k / 4)
+    const half8_t *__restrict__ slots = static_cast<const half8_t *>(a.slots);
+    half8_t st_a[2 * KC];
+    float st_q;
+    auto stage_load = [&](int J) {
+        const int64_t j = static_cast<int64_t>(J) * TILE + tid;
+        if (a.tile_r2[J] > P::wide) {
+#pragma unroll
+            for (int c = 0; c < 2 * KC; ++c) {
+                uintx4_t u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float o = (4 * c + e < D) ? P::off(off[(4 * c + e) * n_pad + j]) : 0.f;
+                    u[e] = __builtin_bit_cast(unsigned, o);
+                }
+                st_a[c] = __builtin_bit_cast(half8_t, u);
+            }
+            st_q = P::q(q[j]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2 * KC; ++c) st_a[c] = slots[c * n_pad + j];
+            st_q = qw[j];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < 2 * KC; ++c) s_a[buf][c][tid] = st_a[c];
+        s_q[buf][tid] = st_q;
+    };
+    if (J0 < J1) {
+        stage_load(J0);
+        stage_store(0);
+    }
+    __syncthreads();
+    for (int J = J0; J < J1; ++J) {
+        const int buf = (J - J0) & 1;
+        if (J + 1 < J1) stage_load(J + 1);
+        const double r2 = a.tile_r2[J];
+        const float njf = static_cast<float>(a.tile_nj[J]);  // a small integer
+        const float far_t2 = a.tile_far[J];
+        half8_t bval[RG][KC];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            float t[D];
+            double tt = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double td = (aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rg][k]);
+                t[k] = static_cast<float>(td);
+                tt = __builtin_fma(td, td, tt);
+            }
+            const bool far = static_cast<float>(tt) > far_t2;
+            HiLo v[D], c;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+            // c = -|t|^2 - N_J formed in FP32 (two roundings, 2^-23 relative)
+            c = far ? HiLo{static_cast<_Float16>(-2000.f), static_cast<_Float16>(0.f)}
+                    : split_f16(-static_cast<float>(tt) - njf);
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c);
+                const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c);
+                bval[rg][kc] = h ? hi8 : lo8;
+            }
+        }
+        if (r2 <= P::wide) {
+            // Software pipeline over the 8 column steps of 32 sources: the matrix
+            // cores form step st (own accumulators) while the VALU exponentiates
+            // and accumulates step st - 1; the source slots are read one step ahead.
+            auto load_a = [&](int cb, half8_t (&av)[KC]) {
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) av[kc] = s_a[buf][2 * kc + h][cb + r32];
+            };
+            auto load_q = [&](int cb, floatx4_t (&qv)[4]) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) qv[m] = *reinterpret_cast<const floatx4_t *>(&s_q[buf][cb + 8 * m + 4 * h]);
+            };
+            auto exponents = [&](const half8_t (&av)[KC], floatx16_t (&G)[RG]) {
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) G[rg][v] = 0.f;
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc)
+                        G[rg] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[kc], bval[rg][kc], G[rg], 0, 0, 0);
+                }
+            };
+            auto accumulate = [&](const floatx16_t (&G)[RG], const floatx4_t (&qv)[4]) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg)
+                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+            };
+            half8_t av[2][KC];
+            floatx4_t qv[4];
+            floatx16_t G[2][RG];
+            load_a(0, av[0]);
+            exponents(av[0], G[0]);
+            load_a(32, av[1]);
+#pragma unroll
+            for (int st = 1; st < TILE / 32; ++st) {
+                exponents(av[st & 1], G[st & 1]);
+                if (st + 1 < TILE / 32) load_a((st + 1) * 32, av[(st + 1) & 1]);
+                load_q((st - 1) * 32, qv);
+                accumulate(G[(st - 1) & 1], qv);
+            }
+            load_q((TILE / 32 - 1) * 32, qv);
+            accumulate(G[(TILE / 32 - 1) & 1], qv);
+        } else {
+            // wide tile: the direct form sum_k (t_k - o_k)^2 on the VALU, the two
+            // halves of the wave taking alternate sources (FP32 offsets staged)
+            float t[RG][D];
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    t[rg][k] = static_cast<float>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
+                                                  static_cast<double>(oi[rg][k]));
+            for (int cs = 0; cs < TILE; cs += 2) {
+                const int cj = cs + h;
+                float oc[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    // the word goes through a scalar: a bit cast whose operand is a
+                    // vector element reads the vector's first element in this compiler
+                    const unsigned w = __builtin_bit_cast(uintx4_t, s_a[buf][k / 4][cj])[k % 4];
+                    oc[k] = __builtin_bit_cast(float, w);
+                }
+                const float qj = s_q[buf][cj];
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) {
+                    float ss = 0.f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const float dd = t[rg][k] - oc[k];
+                        ss = __builtin_fmaf(dd, dd, ss);
+                    }
+                    acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), qj, acc[rg]);
+                }
+            }
+        }
+        // close a partial-sum group (fixed tile ranges: the result does not
+        // depend on how groups are dealt to blocks)
+        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                float sum = acc[rg];
+                sum += __shfl_xor(sum, 32, WAVE);
+                acc[rg] = 0.f;
+                const int64_t i = row0 + rg * 32 + r32;
+                if (h == 0) {
+                    if (a.ngroups == 1) {
+                        if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
+                        out[i] = (i < a.n_rows) ? sum : 0.f;
+                    } else {
+                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
+                    }
+                }
+            }
+        }
+        if (J + 1 < J1) stage_store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 // qw_j = q_j * w_j (the per-source factor of the folded form), once per product.
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_prescale(int64_t n_pad, const void *q_, const void *w_, void *qw_,
@@ -643,10 +879,16 @@ KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
     return k;
 }
 
-// Products up to d = 16 take the matrix-core exponent kernel, larger d the VALU
-// kernel.  KRR_KMVP_VALU=1 forces the VALU kernel (used to cross-check the two).
+// Products up to d = 16 take a matrix-core exponent kernel (split-f16 for FP32
+// and BF16, FP64 matrix cores for FP64), larger d the VALU kernel.
+// KRR_KMVP_VALU=1 forces the VALU kernel and KRR_KMVP_MG32=1 the FP32
+// matrix-core form for FP32 / BF16 (both used to cross-check the kernels).
 static bool use_valu_kernel() {
     const char *v = std::getenv("KRR_KMVP_VALU");
+    return v && v[0] == '1';
+}
+static bool use_fp32_matrix_kernel() {
+    const char *v = std::getenv("KRR_KMVP_MG32");
     return v && v[0] == '1';
 }
 
@@ -661,6 +903,12 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     }
     if constexpr (D <= 16) {
         if (!use_valu_kernel()) {
+            if constexpr (PREC != KRR_FP64) {
+                if (!use_fp32_matrix_kernel()) {
+                    hipLaunchKernelGGL((k_kmvp_mh<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+                    return hipGetLastError();
+                }
+            }
             hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
@@ -710,6 +958,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.anchor = C.anchor;
     a.tile_r2 = C.tile_r2;
     a.tile_nj = C.tile_nj;
+    a.tile_far = C.tile_far;
+    a.slots = prec == KRR_FP32 ? C.slot32 : prec == KRR_BF16 ? C.slot16 : nullptr;
     a.q = q;
     a.qw = sc.qw;
     a.shift = square ? shift : 0.0;

@@ -94,6 +94,7 @@ struct Prepared {
     double *anchor = nullptr; // ntiles * dpad
     double *tile_r2 = nullptr;
     double *tile_nj = nullptr;
+    float *tile_far = nullptr; // |t|^2 beyond which every exponent against the tile is <= -200
     double *off64 = nullptr;  // dpad * n_pad
     float *off32 = nullptr;
     uint16_t *off16 = nullptr;
@@ -101,6 +102,10 @@ struct Prepared {
     float *w32 = nullptr;
     float *w16 = nullptr;
     double *sq64 = nullptr;   // n_pad: ||o_j||^2 (FP64 offsets)
+    // split-f16 source slot vectors of the FP32 and BF16 offsets (split16.h):
+    // 2 split_chunks(dpad) octets per point, octet-major ([octet][n_pad]), for dpad <= 16
+    void *slot32 = nullptr;
+    void *slot16 = nullptr;
     int *flags = nullptr;     // [0]: non-finite input seen
     int kernel = KRR_KERNEL_GAUSS;  // krr_kernel of the products on this set
 };

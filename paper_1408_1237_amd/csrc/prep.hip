@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "krr_internal.h"
+#include "split16.h"
 
 namespace krr {
 
@@ -29,6 +30,7 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     P.anchor = cv.take<double>(static_cast<size_t>(P.ntiles) * P.dpad);
     P.tile_r2 = cv.take<double>(P.ntiles);
     P.tile_nj = cv.take<double>(P.ntiles);
+    P.tile_far = cv.take<float>(P.ntiles);
     P.off64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.off32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.off16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
@@ -36,6 +38,11 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     P.w32 = cv.take<float>(P.n_pad);
     P.w16 = cv.take<float>(P.n_pad);
     P.sq64 = cv.take<double>(P.n_pad);
+    const int oct = 2 * split_chunks(P.dpad);
+    if (oct > 0) {
+        P.slot32 = cv.take<half8_t>(static_cast<size_t>(oct) * P.n_pad);
+        P.slot16 = cv.take<half8_t>(static_cast<size_t>(oct) * P.n_pad);
+    }
     P.flags = cv.take<int>(4);
     return P;
 }
@@ -172,11 +179,55 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
     if (threadIdx.x == 0) {
         P.tile_r2[J] = r2;
         P.tile_nj[J] = nj;
+        // a target at |t| from the anchor has exponent <= -(|t| - R)^2 + R^2 - N_J
+        // against every source of the tile: <= -200 beyond this |t|^2 (1e-4 margin)
+        const double u = sqrt(r2) + sqrt(200.0 + r2 - nj);
+        P.tile_far[J] = static_cast<float>(1.0001 * u * u);
     }
     P.sq64[j] = sq64;
     P.w64[j] = (real && r2 <= WIDE_R2_FP64) ? exp2(nj - sq64) : 0.0;
     P.w32[j] = (real && r2 <= WIDE_R2_FP32) ? static_cast<float>(exp2(nj - sq32)) : 0.0f;
     P.w16[j] = (real && r2 <= WIDE_R2_FP32) ? static_cast<float>(exp2(nj - sq16)) : 0.0f;
+}
+
+// Source slot vectors (split16.h) of the FP32 or BF16 offsets, once per set.
+template <int D, bool BF>
+__global__ __launch_bounds__(BLOCK) void k_slots(Prepared P) {
+    const int64_t j = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
+    if (j >= P.n_pad) return;
+    constexpr int KC = split_chunks(D);
+    HiLo v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float o = BF ? bf16_to_f32(P.off16[k * P.n_pad + j]) : P.off32[k * P.n_pad + j];
+        v[k] = split_f16(o);
+    }
+    const HiLo one{static_cast<_Float16>(1.f), static_cast<_Float16>(1.f)};
+    half8_t *out = static_cast<half8_t *>(BF ? P.slot16 : P.slot32);
+#pragma unroll
+    for (int w = 0; w < 2 * KC; ++w) out[w * P.n_pad + j] = slot_octet<D, true>(w, v, one);
+}
+
+template <int D>
+static hipError_t launch_slots(const Prepared &P, hipStream_t s) {
+    const dim3 g((P.n_pad + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL((k_slots<D, false>), g, dim3(BLOCK), 0, s, P);
+    hipLaunchKernelGGL((k_slots<D, true>), g, dim3(BLOCK), 0, s, P);
+    return hipGetLastError();
+}
+
+static hipError_t build_slots(const Prepared &P, hipStream_t s) {
+    switch (P.dpad) {
+        case 1: return launch_slots<1>(P, s);
+        case 2: return launch_slots<2>(P, s);
+        case 3: return launch_slots<3>(P, s);
+        case 4: return launch_slots<4>(P, s);
+        case 6: return launch_slots<6>(P, s);
+        case 8: return launch_slots<8>(P, s);
+        case 12: return launch_slots<12>(P, s);
+        case 16: return launch_slots<16>(P, s);
+        default: return hipSuccess;  // larger dimensions take the VALU kernel
+    }
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -223,7 +274,8 @@ hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp
                                       static_cast<unsigned>(dm * bits), s));
     hipLaunchKernelGGL(k_tiles, dim3(P.ntiles), dim3(TILE), 0, s, x, n, d, P.dpad, P.scale,
                        static_cast<const int32_t *>(vals.current()), P);
-    return hipGetLastError();
+    KRR_HIP(hipGetLastError());
+    return build_slots(P, s);
 }
 
 // ---------------------------------------------------------------- gather / scatter

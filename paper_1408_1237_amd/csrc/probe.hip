@@ -1,6 +1,6 @@
 // Issue-rate probe (measurement support for the product rooflines).
 //
-// Four register-only kernels, each timed with HIP events on the caller's
+// Five register-only kernels, each timed with HIP events on the caller's
 // stream, measure on the device at hand:
 //   rates[0]  FP32 FMA lane-operations per second (8 independent chains);
 //   rates[1]  exp2 + dependent FMA pairs per second (the VALU kernels' inner
@@ -9,7 +9,9 @@
 //   rates[3]  pairs per second of the matrix-core exponent kernel's mix: per
 //             1024 pairs four v_mfma_f32_16x16x4f32, 16 v_exp_f32 and 16 FMAs
 //             per lane, the matrix-core results of one step feeding the next
-//             step's exponentials.
+//             step's exponentials;
+//   rates[4]  the same for the split-f16 kernel's mix: per 1024 pairs one
+//             v_mfma_f32_32x32x16_f16, 16 v_exp_f32 and 16 FMAs per lane.
 // Comparing rates[3] with rates[1] and rates[2] shows whether the matrix-core
 // and VALU work of one SIMD overlap.  The kernels write one float per thread
 // into the workspace (so nothing is dead code); no memory is allocated.
@@ -22,6 +24,8 @@ namespace krr {
 namespace {
 
 typedef float pf4 __attribute__((ext_vector_type(4)));
+typedef float pf16 __attribute__((ext_vector_type(16)));
+typedef _Float16 ph8 __attribute__((ext_vector_type(8)));
 constexpr int PSTEPS = 256;
 constexpr int PBLOCKS = 256 * 16;  // 4096 blocks of 256 threads
 
@@ -96,6 +100,30 @@ __global__ __launch_bounds__(BLOCK) void kp_mix(float *out, float c) {
     out[gid] = acc[0] + acc[1] + acc[2] + acc[3];
 }
 
+__global__ __launch_bounds__(BLOCK) void kp_mix_h(float *out, float c) {
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    ph8 a, b;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = static_cast<_Float16>(-0.01f * (threadIdx.x % 16) - 0.001f * i);
+        b[i] = static_cast<_Float16>(0.02f + gid * 1e-9f);
+    }
+    pf16 G[2];
+    G[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, pf16{}, 0, 0, 0);
+    for (int i = 0; i < PSTEPS; i += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            a[0] = static_cast<_Float16>(static_cast<float>(a[0]) * c + h);
+            G[h ^ 1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, pf16{}, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                acc[v % 4] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[h][v]), 0.5f + v, acc[v % 4]);
+        }
+    }
+    out[gid] = acc[0] + acc[1] + acc[2] + acc[3];
+}
+
 }  // namespace
 
 size_t probe_workspace_bytes() { return static_cast<size_t>(PBLOCKS) * BLOCK * sizeof(float); }
@@ -107,17 +135,18 @@ hipError_t probe_issue_rates(double *rates, void *ws, hipStream_t s) {
     KRR_HIP(hipEventCreate(&e1));
     const double threads = static_cast<double>(PBLOCKS) * BLOCK;
     const double waves = threads / WAVE;
-    // work per launch: FMA lane-ops, exp2+FMA pairs, matrix-core pairs, mix pairs
-    const double work[4] = {threads * PSTEPS * 8, threads * PSTEPS * 16, waves * PSTEPS * 4 * 256,
-                            waves * PSTEPS * 1024};
+    // work per launch: FMA lane-ops, exp2+FMA pairs, matrix-core pairs, the two mixes' pairs
+    const double work[5] = {threads * PSTEPS * 8, threads * PSTEPS * 16, waves * PSTEPS * 4 * 256,
+                            waves * PSTEPS * 1024, waves * PSTEPS * 1024};
     hipError_t err = hipSuccess;
-    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+    for (int k = 0; k < 5 && err == hipSuccess; ++k) {
         auto launch = [&]() {
             switch (k) {
                 case 0: hipLaunchKernelGGL(kp_fma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 0.9999f); break;
                 case 1: hipLaunchKernelGGL(kp_expfma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
                 case 2: hipLaunchKernelGGL(kp_mfma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
-                default: hipLaunchKernelGGL(kp_mix, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
+                case 3: hipLaunchKernelGGL(kp_mix, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
+                default: hipLaunchKernelGGL(kp_mix_h, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
             }
             return hipGetLastError();
         };

@@ -195,3 +195,55 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     assert _relerr(outs[0], oracle.mvp(x, sigma, q, shift=0.01)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 12, 16])
+def test_split_f16_kernel_matches_fp32_matrix_kernel(monkeypatch, prec, d):
+    # FP32 / BF16 products run the split-f16 matrix-core kernel; KRR_KMVP_MG32=1
+    # selects the FP32 matrix-core form; both meet the oracle bar and agree to
+    # FP32 rounding (the split keeps the FP32 operands to 2^-24)
+    n = 2100
+    x = workloads.random_points(90 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(91 + d, n)
+    sigma = 0.7 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_MG32", "0")
+    a = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.setenv("KRR_KMVP_MG32", "1")
+    b = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.delenv("KRR_KMVP_MG32")
+    want = oracle.mvp(x, sigma, q, shift=0.02)
+    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    assert _relerr(a, b) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_split_f16_kernel_far_and_wide_tiles(monkeypatch, prec):
+    # three clusters: two tight ones 6 and 40 bandwidths apart (targets of one
+    # against tiles of the other: every pair's exponent near or below -200, the
+    # clamped case) and a sparse one whose tiles are wide (direct VALU form,
+    # offsets beyond the f16 range).  FP32 meets the oracle bar; BF16 inputs on
+    # these dense clusters lose more than 1e-2 to input rounding alone, so the
+    # split-f16 kernel is held to the FP32 matrix-core kernel on the same
+    # rounded inputs, and the sparse rows to (1 + s) times the rounded q.
+    rng = np.random.default_rng(17)
+    a = rng.normal(0.0, 1.0, size=(1200, 3))
+    b = rng.normal(0.0, 1.0, size=(1100, 3)) + np.array([6.0, 0.0, 0.0])
+    c = rng.normal(0.0, 1.0, size=(900, 3)) + np.array([0.0, 40.0, 0.0])
+    s = rng.uniform(-300.0, 300.0, size=(700, 3)) + np.array([0.0, 0.0, 400.0])
+    x = np.ascontiguousarray(np.concatenate([a, b, c, s]))
+    q = workloads.random_vector(18, x.shape[0])
+    monkeypatch.setenv("KRR_KMVP_MG32", "0")
+    y = _gpu_mvp(x, 1.0, q, 0.01, prec)
+    monkeypatch.setenv("KRR_KMVP_MG32", "1")
+    y_mg = _gpu_mvp(x, 1.0, q, 0.01, prec)
+    monkeypatch.delenv("KRR_KMVP_MG32")
+    assert _relerr(y, y_mg) <= 1e-5
+    rows = np.arange(3200, 3900)
+    if prec == "fp32":
+        want = oracle.mvp(x, 1.0, q, shift=0.01)
+        assert _relerr(y, want) <= TOL[prec]
+        assert _relerr(y[rows], want[rows]) <= TOL[prec]
+    else:
+        qb = torch.from_numpy(q).float().to(torch.bfloat16).double().numpy()
+        assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6

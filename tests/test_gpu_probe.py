@@ -15,3 +15,7 @@ def test_probe_rates_within_unit_count_bounds():
     assert r["mfma_pairs_s"] <= 1.05 * SIMD_CYCLES_S * 256 / 32
     assert r["exp_fma_pairs_s"] <= 1.05 * SIMD_CYCLES_S * 16
     assert r["mg_mix_pairs_s"] <= 1.05 * min(r["exp_fma_pairs_s"], r["mfma_pairs_s"])
+    # the split-f16 mix: one 32x32x16 f16 operation per 1024 pairs, which also
+    # need 16 exp2 (8 cycles) and 16 FMAs (4 cycles) per lane on the VALU
+    assert r["mh_mix_pairs_s"] <= 1.05 * SIMD_CYCLES_S * 1024 / (16 * (8 + 4))
+    assert r["mh_mix_pairs_s"] > r["mg_mix_pairs_s"]
