@@ -227,6 +227,33 @@ def test_fgmres_identity_preconditioner_is_gmres():
     assert np.linalg.norm(r["w"] - ws) / np.linalg.norm(ws) <= kappa * 2e-8
 
 
+def test_fgmres_exact_inner_solve_is_gmres_on_right_preconditioned_operator():
+    # right preconditioning by M = K_hat + delta I (section 5): with the inner
+    # system solved exactly, FGMRES minimises ||b - K M^{-1} u|| over the Krylov
+    # space of K M^{-1}, i.e. it is GMRES on that operator; K M^{-1} has
+    # eigenvalues (lambda + gamma) / (lambda + delta) in [gamma / delta, 1], so
+    # the residual falls at least like 2 ((sqrt(k) - 1) / (sqrt(k) + 1))^j with
+    # k = delta / gamma (Chebyshev bound for a normal operator)
+    p = workloads.plain_small(n=150)
+    delta = 10 * p.gamma
+    Kh = oracle.kernel_matrix(p.x, p.sigma)
+    K = Kh + p.gamma * np.eye(150)
+    A = K @ np.linalg.inv(Kh + delta * np.eye(150))
+    r = oracle.fgmres(p.x, p.sigma, p.gamma, p.y, m=40, max_outer=6, tol=1e-14, inner="cg", delta=delta,
+                      inner_maxit=5000, inner_tol=1e-14)
+    for k in range(1, 7):
+        assert r["est_hist"][k - 1] == pytest.approx(_krylov_min_residual(A, p.y, k), rel=1e-6)
+    r = oracle.fgmres(p.x, p.sigma, p.gamma, p.y, m=80, max_outer=80, tol=1e-10, inner="cg", delta=delta,
+                      inner_maxit=5000, inner_tol=1e-14)
+    assert r["status"] == 0 and r["cycles"] == 1
+    rho = (np.sqrt(10.0) - 1) / (np.sqrt(10.0) + 1)
+    for j, e in enumerate(r["est_hist"], start=1):
+        assert e <= 2 * rho ** j * (1 + 1e-9)
+    # without the preconditioner the same accuracy takes more steps
+    g = oracle.fgmres(p.x, p.sigma, p.gamma, p.y, m=200, max_outer=200, tol=1e-10, inner="none")
+    assert g["status"] == 0 and g["outer"] > r["outer"]
+
+
 def test_fgmres_flexible_arnoldi_relation_and_least_squares():
     p = workloads.plain_small(n=120)
     r = oracle.fgmres(p.x, p.sigma, p.gamma, p.y, m=30, max_outer=30, tol=1e-9, inner="cg",
