@@ -45,6 +45,7 @@ SIMD_CYCLES_S = 256 * 4 * 2.4e9
 VALU_LANE_OPS = SIMD_CYCLES_S * 16          # FMA lane-ops/s
 C_FMA, C_EXP, C_MFMA32, C_MFMA64 = 4, 8, 32, 64
 C_MFMA_H32 = 32                              # v_mfma_f32_32x32x16_f16 (1024 outputs x 16 slots)
+C_SQRT = 8                                   # v_sqrt_f32, like v_exp_f32
 DIMS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64)
 
 
@@ -87,6 +88,24 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         cyc = (d + 1) * C_FMA + C_EXP
     rule = f"64 pairs per {cyc} SIMD cycles: (d + 1) FMAs + exp2 per lane; 1024 SIMDs x 2.4 GHz"
     return SIMD_CYCLES_S * 64 / cyc, rule, f"k_kmvp<{d}, {tag}>"
+
+
+def matern_peak(d: int) -> tuple[float, str, str]:
+    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 16 (split-f16 kernel),
+    per 1024 pairs: ceil((3D + 4) / 16) 32x32x16 f16 matrix-core operations and,
+    per lane, 16 x (sqrt + exp2 + 2 FMAs), serial issue (v_sqrt_f32 costs 8
+    cycles, as v_exp_f32).  Otherwise (VALU kernel) per 64 pairs: 2d + 3
+    FMA-class operations, sqrt and exp2 per lane."""
+    if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
+        D = dpad(d)
+        kc = (3 * D + 4 + 15) // 16
+        cyc = kc * C_MFMA_H32 + 16 * (C_SQRT + C_EXP + 2 * C_FMA)
+        rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core op(s) + 16 x (sqrt + exp2 + "
+                f"2 FMA) per lane, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, FP32, matern>"
+    cyc = (2 * d + 3) * C_FMA + C_SQRT + C_EXP
+    rule = f"64 pairs per {cyc} SIMD cycles: 2d + 3 FMA-class ops + sqrt + exp2 per lane"
+    return SIMD_CYCLES_S * 64 / cyc, rule, f"k_kmvp_matern<{d}, FP32>"
 
 
 def multi_peak(d: int) -> tuple[float, str, str]:
@@ -365,16 +384,14 @@ def workload_matern(args, api, native, workloads, torch) -> dict:
     tc = time.perf_counter() - t0
     log(f"matern cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
     d = p.d
-    cyc = (2 * d + 3) * C_FMA + 2 * C_EXP  # d differences + d FMAs, sqrt, exp2, scale, two FMAs per lane
-    peak = SIMD_CYCLES_S * 64 / cyc
+    peak, rule, kname = matern_peak(d)
     ach = rates["fp32"]["gpair_s"]
     return {"metric": METRIC, "value": ach * 1e9, "unit": "pairs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
             "higher_is_better": True, "vs_baseline": None,
             "config": {"workload": "matern32 classification N=1e5 d=8 h=sqrt(8) gamma=1e-2; FGMRES with the paper's "
                                    "inner rule vs FP64 CG", "n": p.n, "d": d},
             "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
-                         "frac": round(ach * 1e9 / peak, 4), "traffic": None, "kernel": f"k_kmvp_matern<{d}, FP32>",
-                         "peak_rule": f"64 pairs per {cyc} SIMD cycles: 2d + 3 FMA-class ops + sqrt + exp2 per lane"},
+                         "frac": round(ach * 1e9 / peak, 4), "traffic": None, "kernel": kname, "peak_rule": rule},
             "products": rates,
             "fgmres": {"time_s": tf, "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
                        "relres_true": info["relres_true"]},

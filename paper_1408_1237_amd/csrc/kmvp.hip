@@ -535,9 +535,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 // |c| < 640 and |2t| < 50 on tiles with R^2 <= 64, inside the f16 range.  Wide
 // tiles (R^2 > 64, offsets possibly beyond the f16 range) are staged as plain
 // FP32 offsets in the same LDS words and take the direct form.
+//
+// MAT: the Matern-3/2 product.  With t' = log2(e) t and o' = log2(e) o the
+// same operation forms G = |t'|^2 + |o'|^2 - 2 t'.o' = (log2(e) s)^2 (the
+// source constant |o'|^2 is prepared with the slots); per pair the VALU takes
+// u = sqrt(|G|), e = exp2(-u) and accumulates e (q + u ln2 q) = (1 + s) e^-s q
+// (ln2 q staged beside q).  A target at scaled distance >= 111 from every source
+// of a tile (exp2 is 0 in FP32) gets G = 60000 for the tile; the others have
+// |t'|^2 < 30000 and |2t'| < 350, inside the f16 range.
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 
-template <int D, int PREC>
+template <int D, int PREC, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
@@ -548,9 +556,11 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     constexpr int RG = 2;               // groups of 32 targets per wave
     static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
     // sources of the current column tile, double-buffered: their slot vectors
-    // ([buffer][chunk * 2 + half][source], 8 slots each) and q w (or q on wide tiles)
+    // ([buffer][chunk * 2 + half][source], 8 slots each) and q w (or q on wide
+    // tiles; Matern: q, and ln2 q in s_q2)
     __shared__ __align__(16) half8_t s_a[2][2 * KC][TILE];
     __shared__ __align__(16) float s_q[2][TILE];
+    __shared__ __align__(16) float s_q2[MAT ? 2 : 1][MAT ? TILE : 4];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -602,13 +612,14 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
         } else {
 #pragma unroll
             for (int c = 0; c < 2 * KC; ++c) st_a[c] = slots[c * n_pad + j];
-            st_q = qw[j];
+            st_q = MAT ? P::q(q[j]) : qw[j];
         }
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < 2 * KC; ++c) s_a[buf][c][tid] = st_a[c];
         s_q[buf][tid] = st_q;
+        if constexpr (MAT) s_q2[buf][tid] = LN2_F * st_q;
     };
     if (J0 < J1) {
         stage_load(J0);
@@ -633,16 +644,26 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                 tt = __builtin_fma(td, td, tt);
             }
             const bool far = static_cast<float>(tt) > far_t2;
-            HiLo v[D], c;
+            const _Float16 z16 = static_cast<_Float16>(0.f), one16 = static_cast<_Float16>(1.f);
+            HiLo v[D], c, c2;
+            if constexpr (MAT) {
+                // -2 t', |t'|^2 (t' = log2(e) t) and the source constant's (1, 1)
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
-            // c = -|t|^2 - N_J formed in FP32 (two roundings, 2^-23 relative)
-            c = far ? HiLo{static_cast<_Float16>(-2000.f), static_cast<_Float16>(0.f)}
-                    : split_f16(-static_cast<float>(tt) - njf);
+                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : -2.f * LOG2E_F * t[k]);
+                c = far ? HiLo{static_cast<_Float16>(60000.f), z16}
+                        : split_f16(LOG2E_F * LOG2E_F * static_cast<float>(tt));
+                c2 = HiLo{one16, one16};
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                // c = -|t|^2 - N_J formed in FP32 (two roundings, 2^-23 relative)
+                c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
+                c2 = HiLo{z16, z16};
+            }
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c);
-                const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c);
+                const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c, c2);
+                const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c, c2);
                 bval[rg][kc] = h ? hi8 : lo8;
             }
         }
@@ -654,9 +675,14 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
 #pragma unroll
                 for (int kc = 0; kc < KC; ++kc) av[kc] = s_a[buf][2 * kc + h][cb + r32];
             };
-            auto load_q = [&](int cb, floatx4_t (&qv)[4]) {
+            auto load_q = [&](int cb, floatx4_t (&qv)[4], floatx4_t (&qv2)[MAT ? 4 : 1]) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) qv[m] = *reinterpret_cast<const floatx4_t *>(&s_q[buf][cb + 8 * m + 4 * h]);
+                if constexpr (MAT) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        qv2[m] = *reinterpret_cast<const floatx4_t *>(&s_q2[buf][cb + 8 * m + 4 * h]);
+                }
             };
             auto exponents = [&](const half8_t (&av)[KC], floatx16_t (&G)[RG]) {
 #pragma unroll
@@ -668,15 +694,23 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                         G[rg] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[kc], bval[rg][kc], G[rg], 0, 0, 0);
                 }
             };
-            auto accumulate = [&](const floatx16_t (&G)[RG], const floatx4_t (&qv)[4]) {
+            auto accumulate = [&](const floatx16_t (&G)[RG], const floatx4_t (&qv)[4],
+                                  const floatx4_t (&qv2)[MAT ? 4 : 1]) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v)
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg)
-                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                    for (int rg = 0; rg < RG; ++rg) {
+                        if constexpr (MAT) {
+                            const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[rg][v]));
+                            const float w = __builtin_fmaf(u, qv2[v / 4][v % 4], qv[v / 4][v % 4]);
+                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-u), w, acc[rg]);
+                        } else {
+                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                        }
+                    }
             };
             half8_t av[2][KC];
-            floatx4_t qv[4];
+            floatx4_t qv[4], qv2[MAT ? 4 : 1];
             floatx16_t G[2][RG];
             load_a(0, av[0]);
             exponents(av[0], G[0]);
@@ -685,11 +719,11 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
             for (int st = 1; st < TILE / 32; ++st) {
                 exponents(av[st & 1], G[st & 1]);
                 if (st + 1 < TILE / 32) load_a((st + 1) * 32, av[(st + 1) & 1]);
-                load_q((st - 1) * 32, qv);
-                accumulate(G[(st - 1) & 1], qv);
+                load_q((st - 1) * 32, qv, qv2);
+                accumulate(G[(st - 1) & 1], qv, qv2);
             }
-            load_q((TILE / 32 - 1) * 32, qv);
-            accumulate(G[(TILE / 32 - 1) & 1], qv);
+            load_q((TILE / 32 - 1) * 32, qv, qv2);
+            accumulate(G[(TILE / 32 - 1) & 1], qv, qv2);
         } else {
             // wide tile: the direct form sum_k (t_k - o_k)^2 on the VALU, the two
             // halves of the wave taking alternate sources (FP32 offsets staged)
@@ -719,7 +753,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                         const float dd = t[rg][k] - oc[k];
                         ss = __builtin_fmaf(dd, dd, ss);
                     }
-                    acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), qj, acc[rg]);
+                    if constexpr (MAT) {
+                        const float sd = __builtin_sqrtf(ss);
+                        const float e = __builtin_amdgcn_exp2f(-LOG2E_F * sd);
+                        acc[rg] = __builtin_fmaf(__builtin_fmaf(sd, e, e), qj, acc[rg]);
+                    } else {
+                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), qj, acc[rg]);
+                    }
                 }
             }
         }
@@ -880,7 +920,8 @@ KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
 }
 
 // Products up to d = 16 take a matrix-core exponent kernel (split-f16 for FP32
-// and BF16, FP64 matrix cores for FP64), larger d the VALU kernel.
+// and BF16, FP64 matrix cores for FP64; Matern: split-f16 for FP32 and BF16),
+// the rest the VALU kernels.
 // KRR_KMVP_VALU=1 forces the VALU kernel and KRR_KMVP_MG32=1 the FP32
 // matrix-core form for FP32 / BF16 (both used to cross-check the kernels).
 static bool use_valu_kernel() {
@@ -896,6 +937,12 @@ template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     using P = Prec<PREC>;
     if (kernel == KRR_KERNEL_MATERN32) {
+        if constexpr (D <= 16 && PREC != KRR_FP64) {
+            if (!use_valu_kernel()) {
+                hipLaunchKernelGGL((k_kmvp_mh<D, PREC, true>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_kmvp_matern<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
                            static_cast<const typename P::Off *>(a.off), static_cast<const typename P::Q *>(a.q),
                            a.anchor, static_cast<typename P::T *>(a.out));
@@ -905,7 +952,8 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
         if (!use_valu_kernel()) {
             if constexpr (PREC != KRR_FP64) {
                 if (!use_fp32_matrix_kernel()) {
-                    hipLaunchKernelGGL((k_kmvp_mh<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+                    hipLaunchKernelGGL((k_kmvp_mh<D, PREC, false>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s,
+                                       a);
                     return hipGetLastError();
                 }
             }

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(BLOCK) void k_morton(const double *__restrict__ x, 
 // One block per tile: anchor, offsets, radius, normaliser and weights.
 __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, int64_t n, int d, int dpad,
                                                 double scale, const int32_t *__restrict__ sorted_idx,
-                                                Prepared P) {
+                                                Prepared P, int matern) {
     __shared__ double lds[TILE / WAVE];
     const int J = blockIdx.x;
     const int64_t j = static_cast<int64_t>(J) * TILE + threadIdx.x;
@@ -179,9 +179,11 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
     if (threadIdx.x == 0) {
         P.tile_r2[J] = r2;
         P.tile_nj[J] = nj;
-        // a target at |t| from the anchor has exponent <= -(|t| - R)^2 + R^2 - N_J
-        // against every source of the tile: <= -200 beyond this |t|^2 (1e-4 margin)
-        const double u = sqrt(r2) + sqrt(200.0 + r2 - nj);
+        // Gaussian: a target at |t| from the anchor has exponent
+        // <= -(|t| - R)^2 + R^2 - N_J against every source of the tile, <= -200
+        // beyond this |t|^2; Matern: scaled distance >= 111 (exp2 of -log2(e) s
+        // is 0 in FP32) beyond (R + 111)^2; 1e-4 margin
+        const double u = matern ? sqrt(r2) + 111.0 : sqrt(r2) + sqrt(200.0 + r2 - nj);
         P.tile_far[J] = static_cast<float>(1.0001 * u * u);
     }
     P.sq64[j] = sq64;
@@ -191,28 +193,42 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
 }
 
 // Source slot vectors (split16.h) of the FP32 or BF16 offsets, once per set.
-template <int D, bool BF>
+// Gaussian: the offsets o and no source constant.  Matern: o' = log2(e) o and
+// the constant |o'|^2, so that the product forms (log2(e) r)^2.
+template <int D, bool BF, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_slots(Prepared P) {
     const int64_t j = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
     if (j >= P.n_pad) return;
     constexpr int KC = split_chunks(D);
     HiLo v[D];
+    double so = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const float o = BF ? bf16_to_f32(P.off16[k * P.n_pad + j]) : P.off32[k * P.n_pad + j];
+        float o = BF ? bf16_to_f32(P.off16[k * P.n_pad + j]) : P.off32[k * P.n_pad + j];
+        if (MAT) {
+            o *= LOG2E_F;
+            so = __builtin_fma(static_cast<double>(o), static_cast<double>(o), so);
+        }
         v[k] = split_f16(o);
     }
     const HiLo one{static_cast<_Float16>(1.f), static_cast<_Float16>(1.f)};
+    const HiLo zero{static_cast<_Float16>(0.f), static_cast<_Float16>(0.f)};
+    const HiLo e = MAT ? split_f16(static_cast<float>(so)) : zero;
     half8_t *out = static_cast<half8_t *>(BF ? P.slot16 : P.slot32);
 #pragma unroll
-    for (int w = 0; w < 2 * KC; ++w) out[w * P.n_pad + j] = slot_octet<D, true>(w, v, one);
+    for (int w = 0; w < 2 * KC; ++w) out[w * P.n_pad + j] = slot_octet<D, true>(w, v, one, e);
 }
 
 template <int D>
 static hipError_t launch_slots(const Prepared &P, hipStream_t s) {
     const dim3 g((P.n_pad + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL((k_slots<D, false>), g, dim3(BLOCK), 0, s, P);
-    hipLaunchKernelGGL((k_slots<D, true>), g, dim3(BLOCK), 0, s, P);
+    if (P.kernel == KRR_KERNEL_MATERN32) {
+        hipLaunchKernelGGL((k_slots<D, false, true>), g, dim3(BLOCK), 0, s, P);
+        hipLaunchKernelGGL((k_slots<D, true, true>), g, dim3(BLOCK), 0, s, P);
+    } else {
+        hipLaunchKernelGGL((k_slots<D, false, false>), g, dim3(BLOCK), 0, s, P);
+        hipLaunchKernelGGL((k_slots<D, true, false>), g, dim3(BLOCK), 0, s, P);
+    }
     return hipGetLastError();
 }
 
@@ -273,7 +289,7 @@ hipError_t prepare_points(Prepared &P, const double *x, double sigma, void *temp
     KRR_HIP(rocprim::radix_sort_pairs(sort_tmp, need, keys, vals, static_cast<size_t>(n), 0u,
                                       static_cast<unsigned>(dm * bits), s));
     hipLaunchKernelGGL(k_tiles, dim3(P.ntiles), dim3(TILE), 0, s, x, n, d, P.dpad, P.scale,
-                       static_cast<const int32_t *>(vals.current()), P);
+                       static_cast<const int32_t *>(vals.current()), P, kernel == KRR_KERNEL_MATERN32 ? 1 : 0);
     KRR_HIP(hipGetLastError());
     return build_slots(P, s);
 }

@@ -104,3 +104,51 @@ def test_matern_unknown_kernel_rejected():
     p = workloads.matern_classification(n=200, d=2)
     with pytest.raises(native.KrrError):
         api.fgmres_solve(_t(p.x), p.sigma, p.gamma, _t(p.y), kernel=7)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 12, 16])
+def test_matern_matrix_core_kernel_matches_valu_kernel(monkeypatch, prec, d):
+    # FP32 / BF16 Matern products at d <= 16 form the squared distance on the
+    # matrix cores (split-f16); KRR_KMVP_VALU=1 selects the VALU kernel.  The
+    # two agree to FP32 rounding on the same rounded inputs; FP32 meets the
+    # oracle bar, BF16 inputs do up to d = 8 (at d = 12, 16 the BF16 rounding of
+    # the offsets alone reaches about 1e-2, the same for both kernels)
+    n = 1900
+    x = workloads.random_points(120 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(121 + d, n)
+    h = 0.8 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.matern_mvp(x, h, q, shift=0.03)
+    assert _rel(a, b) <= 1e-5
+    bar = TOL[prec] if (prec == "fp32" or d <= 8) else 2e-2
+    assert _rel(a, want) <= bar and _rel(b, want) <= bar
+
+
+def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch):
+    # two tight clusters 150 length scales apart (targets of one are beyond the
+    # clamp distance from every tile of the other) and a sparse cluster with wide
+    # tiles.  On the dense clusters the FP32 rounding of q and of the points alone
+    # costs about 5e-5 against the FP64 oracle, for the VALU kernel as for the
+    # matrix-core one, so the matrix-core kernel is held to the VALU kernel there
+    # and the sparse rows to the oracle.
+    rng = np.random.default_rng(23)
+    a = rng.normal(0.0, 1.0, size=(1000, 2))
+    b = rng.normal(0.0, 1.0, size=(900, 2)) + np.array([150.0, 0.0])
+    s = rng.uniform(-3000.0, 3000.0, size=(500, 2)) + np.array([0.0, 5000.0])
+    x = np.ascontiguousarray(np.concatenate([a, b, s]))
+    q = workloads.random_vector(24, x.shape[0])
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    y = _mvp(x, 1.0, q, 0.01, "fp32")
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    yv = _mvp(x, 1.0, q, 0.01, "fp32")
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.matern_mvp(x, 1.0, q, shift=0.01)
+    assert _rel(y, yv) <= 1e-5
+    assert _rel(y, want) <= 1e-4
+    rows = np.arange(1900, 2400)
+    assert _rel(y[rows], want[rows]) <= 1e-6

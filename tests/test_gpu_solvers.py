@@ -208,6 +208,24 @@ def test_batched_matches_single_solves_and_zero_column():
             assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], a) <= 1e-6
 
 
+def test_batched_independent_of_system_order():
+    # every (system, column) pair is its own FGMRES instance: permuting the
+    # systems of a batch permutes the results and changes nothing else
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=500, nmax=1500, nrhs=2)
+    order = [2, 0, 1]
+    args = lambda ps: ([_t(p.x) for p in ps], [p.sigma for p in ps], [p.gamma for p in ps],
+                       [_fcol(p.y) for p in ps])
+    Wa, ia = api.krr_solve(*args(probs), mode="fgmres")
+    Wb, ib = api.krr_solve(*args([probs[k] for k in order]), mode="fgmres")
+    assert all(i["status"] == 0 for i in ia + ib)
+    for pos, k in enumerate(order):
+        a, b = Wa[k].cpu().numpy(), Wb[pos].cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+        for r in range(2):
+            assert ia[2 * k + r]["outer_iters"] == ib[2 * pos + r]["outer_iters"]
+
+
 def test_batched_gmres_mode():
     api = _api()
     probs = workloads.batched(nsys=3, nmin=300, nmax=800, nrhs=2)
