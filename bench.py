@@ -109,9 +109,18 @@ def matern_peak(d: int) -> tuple[float, str, str]:
 
 
 def multi_peak(d: int) -> tuple[float, str, str]:
-    """Peak pair x RHS products/s of the FP32 16-RHS product: per 4 columns x 64
-    rows (one wave step) 4 matrix-core operations (16 x 4 x 16 MACs each) and,
-    per lane, d FMAs and one exponential, serial issue."""
+    """Peak pair x RHS products/s of the FP32 16-RHS product, per 16 sources x 16
+    targets x 16 RHS (one wave step), serial issue.  d <= 16 (split-f16 exponent):
+    ceil(2 ceil((3D + 4) / 16) / 4) 16x16x32 f16 operations (16 cycles each),
+    4 exp2 per lane and four 16x16x4 FP32 operations.  Otherwise: four FP32
+    operations and, per lane, 4 x (d FMAs + exp2)."""
+    if d <= 16 and os.environ.get("KRR_KMVP_MULTI_VALU", "0") != "1":
+        D = dpad(d)
+        kc = (2 * ((3 * D + 4 + 15) // 16) + 3) // 4
+        cyc = kc * 16 + 4 * C_EXP + 4 * C_MFMA32
+        rule = (f"4096 pair-RHS per {cyc} SIMD cycles: {kc} 16x16x32 f16 op(s) for the exponents, 4 exp2 per lane, "
+                f"four 16x16x4 FP32 ops for 16 RHS, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 4096 / cyc, rule, f"k_kmvp_multi<{D}, FP32, split-f16>"
     cyc = 4 * C_MFMA32 + 4 * (d * C_FMA + C_EXP)
     rule = (f"4096 pair x RHS per {cyc} SIMD cycles: 4 16x16x4 matrix-core ops + 4 x (d FMAs + exp2) per lane, "
             "serial issue; 1024 SIMDs x 2.4 GHz")
@@ -262,6 +271,8 @@ def workload_batched(args, api, native, workloads, torch) -> dict:
     batched FGMRES solve; the multi-RHS kernel rate on the largest system."""
     import numpy as np
 
+    # the library prints a progress line every 50 outer steps (a long solve is one call)
+    os.environ.setdefault("KRR_PROGRESS", "50")
     probs = workloads.batched()
     xs = [torch.from_numpy(q.x).cuda() for q in probs]
     Ys = [torch.from_numpy(np.asfortranarray(q.y)).cuda() for q in probs]

@@ -12,6 +12,8 @@ struct MArgs {
     const double *anchor;
     const double *tile_r2;
     const double *tile_nj;
+    const float *tile_far;  // split-f16 exponent (FP32 / BF16): per-tile far threshold on |t|^2
+    const void *slots;      // split-f16 exponent: source slot octets of the product's precision
     const void *off;
     const void *qwt;  // Q' as [nrb][n_pad][16]
     void *parts;      // [splits][nrb][n_pad][16]

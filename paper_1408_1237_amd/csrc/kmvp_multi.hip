@@ -11,7 +11,10 @@
 // A wave owns 64 rows (four 16-row blocks, four accumulators) and sweeps the
 // columns of its split 4 at a time; a block of 4 waves owns one 256-row tile.
 // Partial sums per split are added in fixed order by the finish kernel.
+#include <cstdlib>
+
 #include "krr_internal.h"
+#include "split16.h"
 
 namespace krr {
 
@@ -243,12 +246,248 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
     }
 }
 
+// ---------------------------------------------------------------- split-f16 exponent
+//
+// FP32 / BF16 at d <= 16: the kernel values come from the matrix cores too.
+// One v_mfma_f32_16x16x32_f16 per 32 slots of the split exponent (split16.h:
+// sources as A, the lane's target as B) forms the exponents of 16 sources x 16
+// targets; its accumulator gives lane l target l % 16 against sources
+// 4 (l / 16) + v (v < 4), which after exp2 is exactly the A operand of the
+// 16 x 4 x 16 FP32 product with Q' when its v-th operation takes sources
+// v, 4 + v, 8 + v, 12 + v of the step (B reads the Q' rows in that order), so
+// no value moves between lanes.  Per 16 sources x 16 targets: one f16 operation
+// per 32 slots, 4 exp2 per lane and 4 FP32 operations for 16 right-hand sides.
+// Targets far from a tile get the exponent -2000 (as in the single product);
+// wide tiles stage plain FP32 offsets in the octet words and take the direct
+// form for the kernel values.
+template <int D>
+constexpr int multi_chunk_h() {
+    constexpr int bytes = 2 * split_chunks(D) * 16 + 64;
+    constexpr int fit = 20480 / bytes;
+    return fit >= 256 ? 256 : fit >= 128 ? 128 : fit >= 64 ? 64 : 32;
+}
+
 template <int D, int PREC>
+__device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int rbk) {
+    using P = MP<PREC>;
+    using Off = typename P::Off;
+    constexpr int NOCT = 2 * split_chunks(D);  // prepared octets per source
+    constexpr int KC = (NOCT + 3) / 4;         // 32-slot chunks
+    constexpr int RB = D <= 8 ? 4 : 2;         // 16-row blocks per pass (register budget)
+    constexpr int SC = multi_chunk_h<D>();
+    constexpr int CPT = TILE / SC;
+    __shared__ __align__(16) half8_t s_a[2][NOCT][SC];
+    __shared__ __align__(16) float s_b[2][SC][16];
+    const auto off = gp<Off>(a.off);
+    const auto slots = gp<half8_t>(a.slots);
+    const auto qb = gp<float>(a.qwt) + static_cast<int64_t>(rbk) * a.n_pad * 16;
+    const auto anchor = gp<double>(a.anchor);
+    const auto tile_r2 = gp<double>(a.tile_r2);
+    const auto tile_nj = gp<double>(a.tile_nj);
+    const auto tile_far = gp<float>(a.tile_far);
+    const int64_t n_pad = a.n_pad;
+    const int tid = threadIdx.x;
+    const int wave = tid / WAVE;
+    const int lane = tid % WAVE;
+    const int r16 = lane % 16, g = lane / 16;
+    float *parts = static_cast<float *>(a.parts) + (static_cast<int64_t>(by) * a.nrb + rbk) * n_pad * 16;
+    const int C0 = by * a.tps * CPT;
+    const int C1 = min(a.ntiles, (by + 1) * a.tps) * CPT;
+    const half8_t zero8 = __builtin_bit_cast(half8_t, uintx4_t{0u, 0u, 0u, 0u});
+
+    double aI[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) aI[k] = anchor[static_cast<int64_t>(bx) * D + k];
+
+    // staging: entry e = w * SC + col (octet w of source col), then the 16 Q'
+    // values of each source; on wide tiles octet w holds FP32 offsets 4w .. 4w + 3
+    constexpr int NA = (SC * NOCT + BLOCK - 1) / BLOCK;
+    constexpr int NB = (SC * 16 + BLOCK - 1) / BLOCK;
+    half8_t st_a[NA];
+    float st_b[NB];
+    auto stage_load = [&](int cidx) {
+        const int64_t j0 = static_cast<int64_t>(cidx) * SC;
+        const bool wide = tile_r2[cidx / CPT] > P::wide;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            const int w = e / SC, col = e % SC;
+            if (e >= SC * NOCT) {
+                st_a[u] = zero8;
+            } else if (wide) {
+                uintx4_t v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float o = (4 * w + i < D) ? P::off(off[(4 * w + i) * n_pad + j0 + col]) : 0.f;
+                    v[i] = __builtin_bit_cast(unsigned, o);
+                }
+                st_a[u] = __builtin_bit_cast(half8_t, v);
+            } else {
+                st_a[u] = slots[w * n_pad + j0 + col];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) st_b[u] = qb[j0 * 16 + u * BLOCK + tid];
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            if (e < SC * NOCT) s_a[buf][e / SC][e % SC] = st_a[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = u * BLOCK + tid;
+            s_b[buf][e / 16][e % 16] = st_b[u];
+        }
+    };
+
+    for (int pass = 0; pass < 4 / RB; ++pass) {
+        const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + wave * 64 + pass * RB * 16;
+        float oi[RB][D];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int k = 0; k < D; ++k) oi[rb][k] = P::off(off[k * n_pad + row0 + rb * 16 + r16]);
+        floatx4 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        if (C0 < C1) {
+            stage_load(C0);
+            stage_store(0);
+        }
+        __syncthreads();
+        for (int ci = C0; ci < C1; ++ci) {
+            const int buf = (ci - C0) & 1;
+            if (ci + 1 < C1) stage_load(ci + 1);
+            const int J = ci / CPT;
+            const double r2 = tile_r2[J];
+            if (r2 <= P::wide) {
+                const float njf = static_cast<float>(tile_nj[J]);
+                const float far_t2 = tile_far[J];
+                half8_t bval[RB][KC];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    float t[D];
+                    double tt = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double td =
+                            (aI[k] - anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rb][k]);
+                        t[k] = static_cast<float>(td);
+                        tt = __builtin_fma(td, td, tt);
+                    }
+                    const bool far = static_cast<float>(tt) > far_t2;
+                    const _Float16 z16 = static_cast<_Float16>(0.f);
+                    HiLo v[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                    const HiLo c = far ? HiLo{static_cast<_Float16>(-2000.f), z16}
+                                       : split_f16(-static_cast<float>(tt) - njf);
+                    const HiLo c2{z16, z16};
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) {
+                        // octet 4 kc + g of the target vector (lane group g)
+                        const half8_t o0 = slot_octet<D, false>(4 * kc + 0, v, c, c2);
+                        const half8_t o1 = slot_octet<D, false>(4 * kc + 1, v, c, c2);
+                        const half8_t o2 = slot_octet<D, false>(4 * kc + 2, v, c, c2);
+                        const half8_t o3 = slot_octet<D, false>(4 * kc + 3, v, c, c2);
+                        bval[rb][kc] = g == 0 ? o0 : g == 1 ? o1 : g == 2 ? o2 : o3;
+                    }
+                }
+#pragma unroll 2
+                for (int st = 0; st < SC; st += 16) {
+                    half8_t av[KC];
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) {
+                        const int w = 4 * kc + g;
+                        av[kc] = (w < NOCT) ? s_a[buf][w < NOCT ? w : 0][st + r16] : zero8;
+                    }
+                    float bq[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) bq[v] = s_b[buf][st + 4 * g + v][r16];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        floatx4 G = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int kc = 0; kc < KC; ++kc)
+                            G = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[kc], bval[rb][kc], G, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_amdgcn_exp2f(G[v]), bq[v],
+                                                                          acc[rb], 0, 0, 0);
+                    }
+                }
+            } else {
+                float t[RB][D];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        t[rb][k] = static_cast<float>((aI[k] - anchor[static_cast<int64_t>(J) * D + k]) +
+                                                      static_cast<double>(oi[rb][k]));
+#pragma unroll 1
+                for (int st = 0; st < SC; st += 16) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int cj = st + 4 * g + v;
+                        float oc[D];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            // through a scalar: a bit cast whose operand is a vector
+                            // element reads the vector's first element in this compiler
+                            const unsigned wv = __builtin_bit_cast(uintx4_t, s_a[buf][k / 4][cj])[k % 4];
+                            oc[k] = __builtin_bit_cast(float, wv);
+                        }
+                        const float b = s_b[buf][cj][r16];
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) {
+                            float ss = 0.f;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                const float dd = t[rb][k] - oc[k];
+                                ss = __builtin_fmaf(dd, dd, ss);
+                            }
+                            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_amdgcn_exp2f(-ss), b, acc[rb],
+                                                                          0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (ci + 1 < C1) stage_store(buf ^ 1);
+            __syncthreads();
+        }
+        // accumulator: lane l holds right-hand side l % 16 of rows 4 (l / 16) + v
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) parts[(row0 + rb * 16 + 4 * g + v) * 16 + r16] = acc[rb][v];
+    }
+}
+
+// H: the split-f16 exponent body (FP32 / BF16, d <= 16), else the VALU one.
+template <int D, int PREC, bool H>
+__device__ __forceinline__ void multi_select(const MArgs &a, int bx, int by, int rbk) {
+    if constexpr (H && PREC != KRR_FP64 && D <= 16)
+        multi_body_h<D, PREC>(a, bx, by, rbk);
+    else
+        multi_body<D, PREC>(a, bx, by, rbk);
+}
+
+// Which body a launch takes: the split-f16 exponent for FP32 / BF16 up to
+// d = 16 unless KRR_KMVP_MULTI_VALU=1 (used to cross-check the two).
+static bool multi_use_h(int dpad, int prec) {
+    const char *v = std::getenv("KRR_KMVP_MULTI_VALU");
+    return prec != KRR_FP64 && dpad <= 16 && !(v && v[0] == '1');
+}
+
+template <int D, int PREC, bool H>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_multi(MArgs a) {
     const int lb = xcd_remap_m(blockIdx.x, a.nrowblocks * a.splits * a.nrb);
     const int bx = lb % a.nrowblocks;
     const int rest = lb / a.nrowblocks;
-    multi_body<D, PREC>(a, bx, rest % a.splits, rest / a.splits);
+    multi_select<D, PREC, H>(a, bx, rest % a.splits, rest / a.splits);
 }
 
 
@@ -258,7 +497,7 @@ __device__ __forceinline__ bool gate_live(const ColGate &g, int c) {
     return (g.a == nullptr || g.a[c] != 0) && (g.b == nullptr || g.b[c] != 0);
 }
 
-template <int D, int PREC>
+template <int D, int PREC, bool H>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_multi_batched(const MSysB *__restrict__ sys,
                                                               const MItem *__restrict__ items, ColGate gate) {
     const MItem it = items[blockIdx.x];
@@ -267,7 +506,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_multi_batched(const MSysB *__res
         const int live = threadIdx.x < 16 ? gate_live(gate, m.col0 + it.rbk * 16 + threadIdx.x) : 0;
         if (!__syncthreads_or(live)) return;  // block-uniform
     }
-    multi_body<D, PREC>(m.a, it.bx, it.by, it.rbk);
+    multi_select<D, PREC, H>(m.a, it.bx, it.by, it.rbk);
 }
 
 // Q'[rbk][j][r % 16] = Q[p_j + r ldq] * weff_j for r < nrhs (0 beyond), where
@@ -405,6 +644,8 @@ void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, i
     a.anchor = P.anchor;
     a.tile_r2 = P.tile_r2;
     a.tile_nj = P.tile_nj;
+    a.tile_far = P.tile_far;
+    a.slots = prec == KRR_FP32 ? P.slot32 : prec == KRR_BF16 ? P.slot16 : nullptr;
     a.parts = cv.take<double>(static_cast<size_t>(a.splits) * nrb * P.n_pad * 16);
     a.qwt = cv.take<double>(static_cast<size_t>(nrb) * P.n_pad * 16);
     a.off = prec == KRR_FP64 ? static_cast<const void *>(P.off64)
@@ -421,7 +662,10 @@ void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, i
 
 template <int D, int PREC>
 static hipError_t launch_multi_b(const MSysB *S, const MItem *items, int nitems, ColGate gate, hipStream_t s) {
-    hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC>), dim3(nitems), dim3(BLOCK), 0, s, S, items, gate);
+    if (multi_use_h(D, PREC))
+        hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC, true>), dim3(nitems), dim3(BLOCK), 0, s, S, items, gate);
+    else
+        hipLaunchKernelGGL((k_kmvp_multi_batched<D, PREC, false>), dim3(nitems), dim3(BLOCK), 0, s, S, items, gate);
     return hipGetLastError();
 }
 
@@ -492,7 +736,11 @@ size_t kmvp_multi_scratch_bytes(const Prepared &P, int nrhs) {
 
 template <int D, int PREC>
 static hipError_t launch_multi(const MArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_kmvp_multi<D, PREC>), dim3(a.nrowblocks * a.splits * a.nrb), dim3(BLOCK), 0, s, a);
+    const dim3 grid(a.nrowblocks * a.splits * a.nrb);
+    if (multi_use_h(D, PREC))
+        hipLaunchKernelGGL((k_kmvp_multi<D, PREC, true>), grid, dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_kmvp_multi<D, PREC, false>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -531,6 +779,8 @@ static hipError_t multi_run(const Prepared &P, int nrhs, double shift, const int
     a.anchor = P.anchor;
     a.tile_r2 = P.tile_r2;
     a.tile_nj = P.tile_nj;
+    a.tile_far = P.tile_far;
+    a.slots = PREC == KRR_FP32 ? P.slot32 : PREC == KRR_BF16 ? P.slot16 : nullptr;
     Carver cv(scratch);
     const int mx = P.ntiles / 2 > 1 ? (P.ntiles / 2 < 16 ? P.ntiles / 2 : 16) : 1;
     a.parts = cv.take<double>(static_cast<size_t>(mx) * nrb * P.n_pad * 16);

@@ -105,3 +105,51 @@ def test_multi_gp_regression_shape_sampled_rows():
     for r in (0, 15):
         want = oracle.mvp_rows(p.x, p.sigma, np.ascontiguousarray(Q[:, r]), rows)
         assert np.linalg.norm(Y[rows, r] - want) / np.linalg.norm(want) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 12, 16])
+def test_multi_split_exponent_matches_valu_exponent(monkeypatch, prec, d):
+    # FP32 / BF16 multi-RHS products at d <= 16 form the kernel values on the
+    # matrix cores (split-f16 exponent); KRR_KMVP_MULTI_VALU=1 forms them on the
+    # VALU; both meet the oracle bar and agree to FP32 rounding
+    n = 1300
+    x = workloads.random_points(130 + d, n, d, 1.0, kind="normal")
+    Q = workloads.random_vector(131 + d, n, 16)
+    sigma = 0.7 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_MULTI_VALU", "0")
+    A = _gpu_multi(x, sigma, Q, 0.02, prec)
+    monkeypatch.setenv("KRR_KMVP_MULTI_VALU", "1")
+    B = _gpu_multi(x, sigma, Q, 0.02, prec)
+    monkeypatch.delenv("KRR_KMVP_MULTI_VALU")
+    W = _ref(x, sigma, Q, 0.02, prec)
+    assert _colerr(A, W) <= TOL[prec] and _colerr(B, W) <= TOL[prec]
+    assert _colerr(A, B) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_multi_split_exponent_far_and_wide_tiles(monkeypatch, prec):
+    # tight clusters far apart (clamped targets) and a sparse cluster (wide
+    # tiles).  BF16 offsets on these dense clusters alone move the product by
+    # more than 1e-2, so BF16 is held to the VALU-exponent body on the same
+    # rounded inputs, FP32 to the oracle as well
+    rng = np.random.default_rng(31)
+    a = rng.normal(0.0, 1.0, size=(900, 3))
+    b = rng.normal(0.0, 1.0, size=(800, 3)) + np.array([40.0, 0.0, 0.0])
+    s = rng.uniform(-300.0, 300.0, size=(500, 3)) + np.array([0.0, 0.0, 400.0])
+    x = np.ascontiguousarray(np.concatenate([a, b, s]))
+    Q = workloads.random_vector(32, x.shape[0], 16)
+    monkeypatch.setenv("KRR_KMVP_MULTI_VALU", "0")
+    Y = _gpu_multi(x, 2.0, Q, 0.01, prec)
+    monkeypatch.setenv("KRR_KMVP_MULTI_VALU", "1")
+    B = _gpu_multi(x, 2.0, Q, 0.01, prec)
+    monkeypatch.delenv("KRR_KMVP_MULTI_VALU")
+    W = _ref(x, 2.0, Q, 0.01, prec)
+    assert _colerr(Y, B) <= 1e-5
+    if prec == "fp32":
+        assert _colerr(Y, W) <= TOL[prec]
+    # the sparse rows see only their own point (BF16: the reference rounds Q
+    # from FP64 directly, the library through FP32, which can differ by one
+    # BF16 unit on a tie)
+    rows = np.arange(1700, 2200)
+    assert _colerr(Y[rows], W[rows]) <= (1e-6 if prec == "fp32" else 1e-3)
