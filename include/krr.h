@@ -302,19 +302,21 @@ typedef struct {
 int krr_profile_begin(int32_t max_launches);
 int krr_profile_end(krr_profile_stats *out /* host */);
 
-/* Issue-rate probe (measurement support, not part of the method): times five
+/* Issue-rate probe (measurement support, not part of the method): times six
  * register-only kernels on `stream` and writes rates[0] = FP32 FMA lane-ops/s,
  * rates[1] = exp2 + dependent FMA pairs/s, rates[2] = 16x16x4 FP32 matrix-core
  * pairs/s (4 multiply-adds per pair), rates[3] = pairs/s of the FP32
  * matrix-core exponent product's instruction mix (per 1024 pairs: four 16x16x4
  * FP32 matrix-core operations, 16 exp2 and 16 FMAs per lane), rates[4] = pairs/s
  * of the split-f16 product's mix (per 1024 pairs: one 32x32x16 f16 matrix-core
- * operation, 16 exp2 and 16 FMAs per lane).  rates: host array of 5 doubles.
+ * operation, 16 exp2 and 16 FMAs per lane), rates[5] = FP64 exp2 + dependent
+ * FP64 FMA pairs/s (the FP64 products' per-pair VALU work).  rates: host array
+ * of 6 doubles.
  * ws: device workspace of at least krr_probe_workspace_size() bytes (scratch,
  * overwritten).  Synchronises the stream.  Returns KRR_OK, KRR_EINVAL,
  * KRR_EWORKSPACE or KRR_EHIP. */
 size_t krr_probe_workspace_size(void);
-int krr_probe_issue_rates(double *rates /* host, 5 */, void *ws, size_t ws_bytes, krr_stream_t stream);
+int krr_probe_issue_rates(double *rates /* host, 6 */, void *ws, size_t ws_bytes, krr_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -213,10 +213,10 @@ def probe_issue_rates(device="cuda") -> dict:
     matrix-core exponent mixes' pairs/s."""
     lib = N.load()
     ws = workspace(int(lib.krr_probe_workspace_size()), torch.device(device))
-    rates = (ctypes.c_double * 5)()
+    rates = (ctypes.c_double * 6)()
     N.check(lib.krr_probe_issue_rates(rates, ws.data_ptr(), ws.numel(), _stream()), "krr_probe_issue_rates")
     return {"fma_lane_ops_s": rates[0], "exp_fma_pairs_s": rates[1], "mfma_pairs_s": rates[2],
-            "mg_mix_pairs_s": rates[3], "mh_mix_pairs_s": rates[4]}
+            "mg_mix_pairs_s": rates[3], "mh_mix_pairs_s": rates[4], "exp64_fma_pairs_s": rates[5]}
 
 
 def lanczos_extremes(alpha, beta) -> tuple[float, float]:

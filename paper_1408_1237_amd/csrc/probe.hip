@@ -1,6 +1,6 @@
 // Issue-rate probe (measurement support for the product rooflines).
 //
-// Five register-only kernels, each timed with HIP events on the caller's
+// Six register-only kernels, each timed with HIP events on the caller's
 // stream, measure on the device at hand:
 //   rates[0]  FP32 FMA lane-operations per second (8 independent chains);
 //   rates[1]  exp2 + dependent FMA pairs per second (the VALU kernels' inner
@@ -11,7 +11,10 @@
 //             per lane, the matrix-core results of one step feeding the next
 //             step's exponentials;
 //   rates[4]  the same for the split-f16 kernel's mix: per 1024 pairs one
-//             v_mfma_f32_32x32x16_f16, 16 v_exp_f32 and 16 FMAs per lane.
+//             v_mfma_f32_32x32x16_f16, 16 v_exp_f32 and 16 FMAs per lane;
+//   rates[5]  FP64 exp2 (the library's exp2_f64) + dependent FP64 FMA pairs
+//             per second (the FP64 products' per-pair VALU work), with one
+//             FP64 add per pair that varies the argument.
 // Comparing rates[3] with rates[1] and rates[2] shows whether the matrix-core
 // and VALU work of one SIMD overlap.  The kernels write one float per thread
 // into the workspace (so nothing is dead code); no memory is allocated.
@@ -124,6 +127,21 @@ __global__ __launch_bounds__(BLOCK) void kp_mix_h(float *out, float c) {
     out[gid] = acc[0] + acc[1] + acc[2] + acc[3];
 }
 
+__global__ __launch_bounds__(BLOCK) void kp_exp64(float *out, float c) {
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    double a[8], acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = -0.37 * k - gid * 1e-9;
+    const double cd = c;
+    for (int i = 0; i < PSTEPS; ++i) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k % 2] = __builtin_fma(exp2_f64(a[k]), cd, acc[k % 2]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = a[k] - cd * 1e-6;
+    }
+    out[gid] = static_cast<float>(acc[0] + acc[1]);
+}
+
 }  // namespace
 
 size_t probe_workspace_bytes() { return static_cast<size_t>(PBLOCKS) * BLOCK * sizeof(float); }
@@ -135,18 +153,20 @@ hipError_t probe_issue_rates(double *rates, void *ws, hipStream_t s) {
     KRR_HIP(hipEventCreate(&e1));
     const double threads = static_cast<double>(PBLOCKS) * BLOCK;
     const double waves = threads / WAVE;
-    // work per launch: FMA lane-ops, exp2+FMA pairs, matrix-core pairs, the two mixes' pairs
-    const double work[5] = {threads * PSTEPS * 8, threads * PSTEPS * 16, waves * PSTEPS * 4 * 256,
-                            waves * PSTEPS * 1024, waves * PSTEPS * 1024};
+    // work per launch: FMA lane-ops, exp2+FMA pairs, matrix-core pairs, the two
+    // mixes' pairs, FP64 exp2+FMA pairs
+    const double work[6] = {threads * PSTEPS * 8, threads * PSTEPS * 16, waves * PSTEPS * 4 * 256,
+                            waves * PSTEPS * 1024, waves * PSTEPS * 1024, threads * PSTEPS * 8};
     hipError_t err = hipSuccess;
-    for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+    for (int k = 0; k < 6 && err == hipSuccess; ++k) {
         auto launch = [&]() {
             switch (k) {
                 case 0: hipLaunchKernelGGL(kp_fma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 0.9999f); break;
                 case 1: hipLaunchKernelGGL(kp_expfma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
                 case 2: hipLaunchKernelGGL(kp_mfma, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
                 case 3: hipLaunchKernelGGL(kp_mix, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
-                default: hipLaunchKernelGGL(kp_mix_h, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
+                case 4: hipLaunchKernelGGL(kp_mix_h, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
+                default: hipLaunchKernelGGL(kp_exp64, dim3(PBLOCKS), dim3(BLOCK), 0, s, out, 1.0001f); break;
             }
             return hipGetLastError();
         };

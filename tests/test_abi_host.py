@@ -97,7 +97,7 @@ def test_invalid_arguments_rejected_before_any_launch():
 def test_probe_rejects_bad_arguments_on_the_host():
     lib = N.load()
     assert lib.krr_probe_workspace_size() > 0
-    rates = (ctypes.c_double * 5)()
+    rates = (ctypes.c_double * 6)()
     assert lib.krr_probe_issue_rates(rates, None, 0, None) == N.KRR_EWORKSPACE
     assert lib.krr_probe_issue_rates(None, None, 0, None) == N.KRR_EINVAL
 

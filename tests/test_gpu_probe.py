@@ -19,3 +19,5 @@ def test_probe_rates_within_unit_count_bounds():
     # need 16 exp2 (8 cycles) and 16 FMAs (4 cycles) per lane on the VALU
     assert r["mh_mix_pairs_s"] <= 1.05 * SIMD_CYCLES_S * 1024 / (16 * (8 + 4))
     assert r["mh_mix_pairs_s"] > r["mg_mix_pairs_s"]
+    # FP64 exp2 takes at least 13 FP64 VALU instructions (4 cycles each) per pair
+    assert r["exp64_fma_pairs_s"] <= 1.05 * SIMD_CYCLES_S * 64 / (13 * 4)
