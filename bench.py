@@ -53,6 +53,7 @@ def dpad(d: int) -> int:
     """The compiled dimension the library runs d at."""
     return next(p for p in DIMS if p >= d)
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
+C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, index, shift, table product, ldexp
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
@@ -61,8 +62,9 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     d <= 16, per 1024 pairs (one wave-step) plus, per lane, 16 exponentials and
     16 FMAs: FP32 / BF16 (split-f16 kernel) ceil((3D + 2) / 16) 32x32x16 f16
     matrix-core operations; FP64 4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the
-    compiled dimension).  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs and
-    one exponential per lane.  Matrix-core and VALU issue counted one after the
+    compiled dimension; FP64 exponentials from the 256-entry table, 11
+    instructions).  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs and one
+    exponential per lane.  Matrix-core and VALU issue counted one after the
     other (measured by the issue probe).
     """
     tag = {"fp64": "FP64", "bf16": "BF16"}.get(prec, "FP32")
@@ -76,7 +78,7 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
             return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, {tag}>"
         dk = (D + 4) // 4
         if prec == "fp64":
-            cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64 + C_FMA)
+            cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64_TAB + C_FMA)
         else:
             cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "krr_internal.h"
+#include "exp2_table.h"
 #include "split16.h"
 
 namespace krr {
@@ -89,6 +90,7 @@ struct KArgs {
     const double *tile_r2;
     const double *tile_nj;
     const float *tile_far;       // split-f16 kernel: per-tile far threshold on |t|^2
+    const float *tile_far64;     // FP64 matrix-core kernel: the same for exponents <= -1100
     const void *slots;           // split-f16 kernel: source slot octets of the product's precision
     const void *off;
     const void *q;
@@ -322,6 +324,24 @@ struct MG<KRR_FP32> {
 template <>
 struct MG<KRR_BF16> : MG<KRR_FP32> {};
 
+// 2^(x / 256) for the FP64 product, x = 256 arg from the matrix cores: with
+// n = rint(x), j = n mod 256, f = x - n (exact, |f| <= 1/2),
+// 2^(x/256) = 2^((n - j)/256) 2^(j/256) 2^(f/256), the middle factor from the
+// correctly rounded table in LDS, the last a degree-4 polynomial (relative
+// error 2e-18; exp2_table.py).  x must lie in int range (the caller clamps far
+// targets); 12 instructions against 15 for exp2_f64.
+__device__ __forceinline__ double exp2_x256(double x, const double *__restrict__ tab) {
+    const double n = __builtin_rint(x);
+    const double f = x - n;
+    const int i = static_cast<int>(n);
+    double p = EXP2_POLY256[0];
+    p = __builtin_fma(p, f, EXP2_POLY256[1]);
+    p = __builtin_fma(p, f, EXP2_POLY256[2]);
+    p = __builtin_fma(p, f, EXP2_POLY256[3]);
+    p = __builtin_fma(p, f, EXP2_POLY256[4]);
+    return __builtin_amdgcn_ldexp(p * tab[i & 255], i >> 8);
+}
+
 template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -340,6 +360,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     // J + 1 from memory while it computes tile J.
     __shared__ T s_off[2][DR][LDO];
     __shared__ __align__(16) T s_q[2][TILE];
+    // FP64: the table of 2^(j/256) (exp2_x256)
+    constexpr bool TAB = PREC == KRR_FP64;
+    __shared__ double s_exp2[TAB ? 256 : 1];
+    if constexpr (TAB) s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -420,14 +444,24 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 const double tk = static_cast<double>(t[rg][k]);
                 tt = __builtin_fma(tk, tk, tt);
             }
-            const T c = static_cast<T>(-tt - nj);
+            T c = static_cast<T>(-tt - nj);
+            // FP64: the operand is scaled by 256 (exactly) for exp2_x256, and a
+            // target whose every exponent against the tile is <= -1100 (exp2 is
+            // 0 in FP64 either way) gets -2000 for the whole tile, which keeps
+            // the scaled exponents in int range
+            const T sc = TAB ? T(256) : T(1);
+            bool far = false;
+            if constexpr (TAB) {
+                far = tt > static_cast<double>(a.tile_far64[J]);
+                c = far ? T(-2000.0 * 256.0) : c * sc;
+            }
             // coordinate 4 kc + g of [2t, c, 0...] for this lane's chunk slots
 #pragma unroll
             for (int kc = 0; kc < DK; ++kc) {
                 const int dim = 4 * kc + g;
                 T v = (dim == D) ? c : T(0);
 #pragma unroll
-                for (int k = 0; k < D; ++k) v = (dim == k) ? T(2) * t[rg][k] : v;
+                for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2) * sc * t[rg][k]) : v;
                 bval[rg][kc] = v;
             }
         }
@@ -452,7 +486,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg) acc[rg] = M::fma(P::ex2(G[rg][v]), qv[v], acc[rg]);
+                    for (int rg = 0; rg < RG; ++rg) {
+                        if constexpr (TAB)
+                            acc[rg] = M::fma(exp2_x256(G[rg][v], s_exp2), qv[v], acc[rg]);
+                        else
+                            acc[rg] = M::fma(P::ex2(G[rg][v]), qv[v], acc[rg]);
+                    }
             };
             // 16 column steps, fully unrolled with two register sets so the
             // pipeline needs no copies
@@ -1007,6 +1046,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.tile_r2 = C.tile_r2;
     a.tile_nj = C.tile_nj;
     a.tile_far = C.tile_far;
+    a.tile_far64 = C.tile_far64;
     a.slots = prec == KRR_FP32 ? C.slot32 : prec == KRR_BF16 ? C.slot16 : nullptr;
     a.q = q;
     a.qw = sc.qw;

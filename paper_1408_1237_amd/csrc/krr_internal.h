@@ -95,6 +95,7 @@ struct Prepared {
     double *tile_r2 = nullptr;
     double *tile_nj = nullptr;
     float *tile_far = nullptr; // |t|^2 beyond which every exponent against the tile is <= -200
+    float *tile_far64 = nullptr; // the same for exponents <= -1100 (FP64 Gaussian product)
     double *off64 = nullptr;  // dpad * n_pad
     float *off32 = nullptr;
     uint16_t *off16 = nullptr;

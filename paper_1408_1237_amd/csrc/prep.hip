@@ -31,6 +31,7 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     P.tile_r2 = cv.take<double>(P.ntiles);
     P.tile_nj = cv.take<double>(P.ntiles);
     P.tile_far = cv.take<float>(P.ntiles);
+    P.tile_far64 = cv.take<float>(P.ntiles);
     P.off64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.off32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.off16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
@@ -185,6 +186,9 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
         // is 0 in FP32) beyond (R + 111)^2; 1e-4 margin
         const double u = matern ? sqrt(r2) + 111.0 : sqrt(r2) + sqrt(200.0 + r2 - nj);
         P.tile_far[J] = static_cast<float>(1.0001 * u * u);
+        // FP64 Gaussian product: exponents <= -1100 (exp2 is 0 in FP64)
+        const double u64 = sqrt(r2) + sqrt(1100.0 + r2 - nj);
+        P.tile_far64[J] = static_cast<float>(1.0001 * u64 * u64);
     }
     P.sq64[j] = sq64;
     P.w64[j] = (real && r2 <= WIDE_R2_FP64) ? exp2(nj - sq64) : 0.0;

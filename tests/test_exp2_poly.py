@@ -45,3 +45,54 @@ def test_exp2_poly_float64_horner():
         p = p * f + v
     rel = np.abs(p / np.exp2(f) - 1)
     assert rel.max() < 1e-15
+
+
+TAB_HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1408_1237_amd", "csrc", "exp2_table.h")
+
+
+def _table_header():
+    src = open(TAB_HDR).read()
+    poly = src[src.index("EXP2_POLY256[5] = {"):]
+    poly = [float(v) for v in re.findall(r"[-0-9.e+]+", poly[poly.index("{") + 1: poly.index("}")])]
+    tab = src[src.index("EXP2_TABLE256[256] = {"):]
+    tab = [float(v) for v in re.findall(r"[-0-9.e+]+", tab[tab.index("{") + 1: tab.index("}")])]
+    return poly, tab
+
+
+def test_exp2_table_correctly_rounded():
+    # the FP64 product's table holds 2^(j/256) rounded to nearest double
+    import mpmath as mp
+    mp.mp.dps = 50
+    poly, tab = _table_header()
+    assert len(poly) == 5 and poly[-1] == 1.0 and len(tab) == 256
+    for j, v in enumerate(tab):
+        assert v == float(mp.power(2, mp.mpf(j) / 256))
+
+
+def test_exp2_x256_scheme_float64():
+    # 2^(x/256) = 2^((n - j)/256) 2^(j/256) p(x - n), n = rint(x), j = n mod 256,
+    # evaluated in float64 as the kernel does (with separate multiply and add in
+    # place of the fused operations), against mpmath over the argument range the
+    # kernel feeds it, including the clamp value -2000 * 256 (result 0)
+    import mpmath as mp
+    mp.mp.dps = 40
+    poly, tab = _table_header()
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([rng.uniform(-1100 * 256, 256 * 256, 3000), rng.uniform(-512, 512, 1000),
+                         np.arange(-300, 300) + 0.5, [0.0, -0.5, 0.5, 255.5, -256.5]])
+    worst = 0.0
+    for x in xs:
+        n = np.rint(x)
+        f = x - n
+        i = int(n)
+        p = poly[0]
+        for c in poly[1:]:
+            p = p * f + c
+        got = np.ldexp(p * tab[i & 255], i >> 8)
+        want = mp.power(2, mp.mpf(float(x)) / 256)
+        if want < mp.mpf(2) ** -1000:
+            continue
+        worst = max(worst, float(abs(mp.mpf(float(got)) / want - 1)))
+    assert worst < 5e-16
+    i = -2000 * 256
+    assert np.ldexp(1.0 * tab[i & 255], i >> 8) == 0.0
