@@ -590,8 +590,8 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     using P = Prec<PREC>;
     using Off = typename P::Off;
     using Q = typename P::Q;
-    constexpr int NS = 3 * D + 2;       // slots of the split inner product
-    constexpr int KC = (NS + 15) / 16;  // 16-slot chunks
+    constexpr int KC = split_chunks(D);  // 16-slot chunks (3D + 4 slots: Gaussian and Matern forms)
+    static_assert(KC >= 1 && 16 * KC >= 3 * D + 4, "slot chunks cover the split inner product");
     constexpr int RG = 2;               // groups of 32 targets per wave
     static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
     // sources of the current column tile, double-buffered: their slot vectors
