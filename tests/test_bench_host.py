@@ -1,0 +1,61 @@
+"""Host-side logic of bench.py (no GPU): the issue-model peaks against cycle
+counts worked out by hand, the counter-summary parser and its source-hash gate,
+and the refusal of several GPUs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.join(os.path.dirname(__file__), "..")
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+S = 256 * 4 * 2.4e9  # SIMD cycles per second
+
+
+def test_compiled_dimensions():
+    assert [bench.dpad(d) for d in (1, 2, 3, 4, 5, 7, 9, 13, 17, 33, 64)] == [1, 2, 3, 4, 6, 8, 12, 16, 24, 48, 64]
+
+
+def test_product_peaks_by_hand(monkeypatch):
+    monkeypatch.delenv("KRR_KMVP_VALU", raising=False)
+    monkeypatch.delenv("KRR_KMVP_MG32", raising=False)
+    # FP32 d = 3: one 32x32x16 f16 op (32) + 16 x (exp2 8 + FMA 4) per 1024 pairs
+    assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / 224)
+    # FP32 d = 16: ceil(52 / 16) = 4 ops
+    assert bench.product_peak(16)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
+    # FP64 d = 3: four 16x16x4 FP64 ops (64 each) + 16 x (11 x 4 + 4)
+    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 768))
+    # VALU kernel beyond d = 16: 64 pairs per (d + 1) FMAs + exp2
+    assert bench.product_peak(20)[0] == pytest.approx(S * 64 / (21 * 4 + 8))
+    monkeypatch.setenv("KRR_KMVP_MG32", "1")
+    assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
+    # Matern d = 8: two f16 ops + 16 x (sqrt 8 + exp2 8 + 2 FMAs)
+    monkeypatch.delenv("KRR_KMVP_MG32")
+    assert bench.matern_peak(8)[0] == pytest.approx(S * 1024 / (64 + 384))
+    # 16-RHS product d = 4: one 16x16x32 f16 op + 4 exp2 + four 16x16x4 FP32 ops per 4096 pair-RHS
+    assert bench.multi_peak(4)[0] == pytest.approx(S * 4096 / (16 + 32 + 128))
+
+
+def test_traffic_parser_and_hash_gate(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    (tmp_path / "profiles" / "c.txt").write_text("x\ntraffic: bytes_per_launch=12345 source_hash=abc\n")
+    assert bench.read_traffic("c.txt") == 12345.0
+    (tmp_path / "profiles" / "d.txt").write_text("traffic: bytes_per_launch=12345 source_hash=zzz\n")
+    assert bench.read_traffic("d.txt") is None  # kernel changed since the counters were taken
+    assert bench.read_traffic("missing.txt") is None
+
+
+def test_committed_counters_match_kernel_source():
+    # the committed counter summary is the one the bench line's traffic figure uses
+    v = bench.read_traffic("kmvp_fp32_d3_kriging_counters.txt")
+    assert v is None or v > 3.6e6  # at least the algorithmic bytes when current
+
+
+def test_several_gpus_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
