@@ -25,6 +25,7 @@
 #include <cstdint>
 
 #include "../../include/krr.h"
+#include "exp2_table.h"
 
 namespace krr {
 
@@ -58,6 +59,24 @@ __device__ __forceinline__ double exp2_f64(double a) {
     p = __builtin_fma(p, f, 0.69314718055995);
     p = __builtin_fma(p, f, 1.0);
     return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+}
+
+// 2^(x / 256) for the FP64 products (x = 256 times the exponent): with
+// n = rint(x), j = n mod 256, f = x - n (exact, |f| <= 1/2),
+// 2^(x/256) = 2^((n - j)/256) 2^(j/256) 2^(f/256), the middle factor from the
+// correctly rounded table in LDS, the last a degree-4 polynomial (relative
+// error 2e-18; exp2_table.py).  x must lie in int range (the caller clamps far
+// targets); 12 instructions against 15 for exp2_f64.
+__device__ __forceinline__ double exp2_x256(double x, const double *__restrict__ tab) {
+    const double n = __builtin_rint(x);
+    const double f = x - n;
+    const int i = static_cast<int>(n);
+    double p = EXP2_POLY256[0];
+    p = __builtin_fma(p, f, EXP2_POLY256[1]);
+    p = __builtin_fma(p, f, EXP2_POLY256[2]);
+    p = __builtin_fma(p, f, EXP2_POLY256[3]);
+    p = __builtin_fma(p, f, EXP2_POLY256[4]);
+    return __builtin_amdgcn_ldexp(p * tab[i & 255], i >> 8);
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
