@@ -59,16 +59,24 @@ C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, i
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     """Peak pairs/s of the product kernel that runs for dimension d and precision.
 
-    d <= 16, per 1024 pairs (one wave-step) plus, per lane, 16 exponentials and
-    16 FMAs: FP32 / BF16 (split-f16 kernel) ceil((3D + 2) / 16) 32x32x16 f16
-    matrix-core operations; FP64 4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the
-    compiled dimension; FP64 exponentials from the 256-entry table, 11
-    instructions).  Otherwise (VALU kernel) per 64 pairs: d + 1 FMAs and one
-    exponential per lane.  Matrix-core and VALU issue counted one after the
-    other (measured by the issue probe).
+    Matrix-core kernels, per 1024 pairs (one wave-step) plus, per lane, 16
+    exponentials and 16 FMAs: FP32 / BF16 for d <= 48 (split-f16 kernels)
+    ceil((3D + 2) / 16) 32x32x16 f16 matrix-core operations; FP64 for d <= 16
+    4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the compiled dimension; FP64
+    exponentials from the 256-entry table, 11 instructions).  Otherwise (VALU
+    kernel) per 64 pairs: d + 1 FMAs and one exponential per lane.  Matrix-core
+    and VALU issue counted one after the other (measured by the issue probe).
     """
     tag = {"fp64": "FP64", "bf16": "BF16"}.get(prec, "FP32")
-    if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
+    valu = os.environ.get("KRR_KMVP_VALU", "0") == "1"
+    if 16 < d <= 48 and prec != "fp64" and not valu:
+        D = dpad(d)
+        kc = (3 * D + 2 + 15) // 16
+        cyc = kc * C_MFMA_H32 + 16 * (C_EXP + C_FMA)
+        rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core ops + 16 x (exp2 + FMA) "
+                f"per lane, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mhw<{D}, {tag}>"
+    if d <= 16 and not valu:
         D = dpad(d)
         if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":
             kc = (3 * D + 2 + 15) // 16

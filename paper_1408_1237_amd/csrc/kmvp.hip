@@ -844,6 +844,236 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad,
     y[i] = square ? s + static_cast<T>(shift) * P::q(q[i]) : s;
 }
 
+// ---------------------------------------------------------------- split-f16, d = 24 .. 48
+//
+// The split-f16 Gaussian product (FP32 / BF16) for the compiled dimensions 24,
+// 32 and 48: the slots, operations and clamps of k_kmvp_mh, with 3D + 4 slots in
+// KC = ceil((3D + 4) / 16) chunks.  Its operands do not fit the d <= 16 layout,
+// so the sources of a column tile are staged in LDS 64 at a time (double
+// buffered; a thread carries at most ceil(KC / 2) octets), the target operand
+// is rebuilt once per column tile from the anchors and target offsets read
+// from memory, and within a 64-source stage the matrix cores form the second
+// 32-source step while the VALU exponentiates the first.  Wide tiles take the
+// direct form on staged FP32 offsets, one target group at a time.
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using Off = typename P::Off;
+    using Q = typename P::Q;
+    constexpr int KC = split_chunks(D);
+    constexpr int NOCT = 2 * KC;
+    constexpr int RG = 2;                                  // groups of 32 targets per wave
+    constexpr int CH = 64;                                 // sources per LDS stage
+    constexpr int NCH = TILE / CH;                         // stages per column tile
+    constexpr int NA = (NOCT * CH + BLOCK - 1) / BLOCK;    // octets staged per thread
+    static_assert(KC >= 1 && 16 * KC >= 3 * D + 4 && TILE % CH == 0 && CH % 32 == 0, "stage layout");
+    static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
+    __shared__ __align__(16) half8_t s_a[2][NOCT][CH];
+    __shared__ __align__(16) float s_q[2][CH];
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const float *__restrict__ qw = static_cast<const float *>(a.qw);
+    const half8_t *__restrict__ slots = static_cast<const half8_t *>(a.slots);
+    const int64_t n_pad = a.n_pad;
+
+    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE;
+    const int r32 = lane % 32, h = lane / 32;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (tid / WAVE) * 64;
+    float acc[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.f;
+    float *__restrict__ out = static_cast<float *>(a.out);
+    const half8_t zero8 = __builtin_bit_cast(half8_t, uintx4_t{0u, 0u, 0u, 0u});
+
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    const int C0 = J0 * NCH, C1 = J1 * NCH;
+    // staging: entry e = c * CH + col is octet c of source col of the stage; on
+    // wide tiles octet c holds the FP32 offsets 4c .. 4c + 3
+    half8_t st_a[NA];
+    float st_q = 0.f;
+    auto stage_load = [&](int ci) {
+        const int J = ci / NCH;
+        const int64_t j0 = static_cast<int64_t>(J) * TILE + (ci % NCH) * CH;
+        const bool wide = a.tile_r2[J] > P::wide;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            const int c = e / CH, col = e % CH;
+            if (e >= NOCT * CH) {
+                st_a[u] = zero8;
+            } else if (wide) {
+                uintx4_t v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float o = (4 * c + i < D) ? P::off(off[(4 * c + i) * n_pad + j0 + col]) : 0.f;
+                    v[i] = __builtin_bit_cast(unsigned, o);
+                }
+                st_a[u] = __builtin_bit_cast(half8_t, v);
+            } else {
+                st_a[u] = slots[c * n_pad + j0 + col];
+            }
+        }
+        if (tid < CH) st_q = wide ? P::q(q[j0 + tid]) : qw[j0 + tid];
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            if (e < NOCT * CH) s_a[buf][e / CH][e % CH] = st_a[u];
+        }
+        if (tid < CH) s_q[buf][tid] = st_q;
+    };
+    // the anchor difference a_B - a_J of the row block and tile J, coordinate
+    // k in lane k (uniform values kept in vector registers: as scalars they
+    // would not fit)
+    auto anchor_diff = [&](int J) -> double {
+        return lane < D ? a.row_anchor[static_cast<int64_t>(bx) * D + lane] - a.anchor[static_cast<int64_t>(J) * D + lane] : 0.0;
+    };
+    // the target's t = x - a_J for coordinates k = 0 .. D - 1 in turn: rp points
+    // at coordinate k of the target's offsets and advances one coordinate per
+    // call.  The empty statement keeps the pointer an opaque vector value, so
+    // that the D coordinate addresses are not all formed up front in scalar
+    // registers (which would not fit).
+    auto target_t = [&](double dA, const Off *&rp, int k) -> double {
+        const uint64_t bits = __builtin_bit_cast(uint64_t, dA);
+        const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(bits), k);
+        const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(bits >> 32), k);
+        const double dk = __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+        const double td = dk + static_cast<double>(P::off(*rp));
+        rp += a.n_pad_rows;
+        asm volatile("" : "+v"(rp));
+        return td;
+    };
+
+    if (C0 < C1) {
+        stage_load(C0);
+        stage_store(0);
+    }
+    __syncthreads();
+    half8_t bval[RG][KC];
+    for (int ci = C0; ci < C1; ++ci) {
+        const int buf = (ci - C0) & 1;
+        if (ci + 1 < C1) stage_load(ci + 1);
+        const int J = ci / NCH;
+        const bool wide = a.tile_r2[J] > P::wide;
+        if (!wide && ci % NCH == 0) {
+            // the target operand of tile J: 2t and c = -|t|^2 - N_J split as in k_kmvp_mh
+            const float njf = static_cast<float>(a.tile_nj[J]);
+            const float far_t2 = a.tile_far[J];
+            const double dA = anchor_diff(J);
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                float t[D];
+                double tt = 0.0;
+                const Off *rp = row_off + (row0 + rg * 32 + r32);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double td = target_t(dA, rp, k);
+                    t[k] = static_cast<float>(td);
+                    tt = __builtin_fma(td, td, tt);
+                }
+                const bool far = static_cast<float>(tt) > far_t2;
+                const _Float16 z16 = static_cast<_Float16>(0.f);
+                HiLo v[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                const HiLo c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
+                const HiLo c2{z16, z16};
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c, c2);
+                    const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c, c2);
+                    bval[rg][kc] = h ? hi8 : lo8;
+                }
+                // one target group at a time: the splits of both groups live at
+                // once would not fit the register file
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (!wide) {
+            // two 32-source steps, each one exponent block per target group on
+            // the matrix cores followed by exp2 and the accumulation
+#pragma unroll
+            for (int st = 0; st < CH / 32; ++st) {
+                floatx16_t G[RG];
+                {
+                    half8_t av[KC];
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) av[kc] = s_a[buf][2 * kc + h][st * 32 + r32];
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) G[rg][v] = 0.f;
+#pragma unroll
+                        for (int kc = 0; kc < KC; ++kc)
+                            G[rg] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[kc], bval[rg][kc], G[rg], 0, 0, 0);
+                    }
+                }
+                floatx4_t qv[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    qv[m] = *reinterpret_cast<const floatx4_t *>(&s_q[buf][st * 32 + 8 * m + 4 * h]);
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg)
+                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+            }
+        } else {
+            // wide tile: the direct form on the staged FP32 offsets, the two halves
+            // of the wave taking alternate sources
+            const double dA = anchor_diff(J);
+#pragma unroll 1
+            for (int rg = 0; rg < RG; ++rg) {
+                float t[D];
+                const Off *rp = row_off + (row0 + rg * 32 + r32);
+#pragma unroll
+                for (int k = 0; k < D; ++k) t[k] = static_cast<float>(target_t(dA, rp, k));
+#pragma unroll 1
+                for (int cs = 0; cs < CH; cs += 2) {
+                    const int cj = cs + h;
+                    float ss = 0.f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        // through a scalar: a bit cast whose operand is a vector
+                        // element reads the vector's first element in this compiler
+                        const unsigned wv = __builtin_bit_cast(uintx4_t, s_a[buf][k / 4][cj])[k % 4];
+                        const float dd = t[k] - __builtin_bit_cast(float, wv);
+                        ss = __builtin_fmaf(dd, dd, ss);
+                    }
+                    acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), s_q[buf][cj], acc[rg]);
+                }
+            }
+        }
+        // close a partial-sum group after the last stage of a tile
+        if (ci % NCH == NCH - 1 && ((J + 1) % a.gtiles == 0 || J + 1 == J1)) {
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                float sum = acc[rg];
+                sum += __shfl_xor(sum, 32, WAVE);
+                acc[rg] = 0.f;
+                const int64_t i = row0 + rg * 32 + r32;
+                if (h == 0) {
+                    if (a.ngroups == 1) {
+                        if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
+                        out[i] = (i < a.n_rows) ? sum : 0.f;
+                    } else {
+                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
+                    }
+                }
+            }
+        }
+        if (ci + 1 < C1) stage_store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- plans and tuning
 
 // Partial-sum groups: the sources are cut into groups of gtiles consecutive
@@ -968,6 +1198,12 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
                            static_cast<const typename P::Off *>(a.off), static_cast<const typename P::Q *>(a.q),
                            a.anchor, static_cast<typename P::T *>(a.out));
         return hipGetLastError();
+    }
+    if constexpr (D > 16 && D <= 48 && PREC != KRR_FP64) {
+        if (!use_valu_kernel()) {
+            hipLaunchKernelGGL((k_kmvp_mhw<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
     }
     if constexpr (D <= 16) {
         if (!use_valu_kernel()) {

@@ -123,7 +123,7 @@ struct Prepared {
     float *w16 = nullptr;
     double *sq64 = nullptr;   // n_pad: ||o_j||^2 (FP64 offsets)
     // split-f16 source slot vectors of the FP32 and BF16 offsets (split16.h):
-    // 2 split_chunks(dpad) octets per point, octet-major ([octet][n_pad]), for dpad <= 16
+    // 2 split_chunks(dpad) octets per point, octet-major ([octet][n_pad]), for dpad <= 48
     void *slot32 = nullptr;
     void *slot16 = nullptr;
     int *flags = nullptr;     // [0]: non-finite input seen

@@ -246,7 +246,10 @@ static hipError_t build_slots(const Prepared &P, hipStream_t s) {
         case 8: return launch_slots<8>(P, s);
         case 12: return launch_slots<12>(P, s);
         case 16: return launch_slots<16>(P, s);
-        default: return hipSuccess;  // larger dimensions take the VALU kernel
+        case 24: return launch_slots<24>(P, s);
+        case 32: return launch_slots<32>(P, s);
+        case 48: return launch_slots<48>(P, s);
+        default: return hipSuccess;  // d = 64 takes the VALU kernel
     }
 }
 

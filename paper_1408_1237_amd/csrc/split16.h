@@ -19,8 +19,8 @@ namespace krr {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef unsigned uintx4_t __attribute__((ext_vector_type(4)));
 
-// 16-slot chunks of dimension D (compiled dimensions up to 16), 0 above.
-constexpr int split_chunks(int D) { return D <= 16 ? (3 * D + 4 + 15) / 16 : 0; }
+// 16-slot chunks of dimension D (compiled dimensions up to 48), 0 above.
+constexpr int split_chunks(int D) { return D <= 48 ? (3 * D + 4 + 15) / 16 : 0; }
 
 struct HiLo {
     _Float16 hi, lo;

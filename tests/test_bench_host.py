@@ -27,8 +27,15 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(16)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
     # FP64 d = 3: four 16x16x4 FP64 ops (64 each) + 16 x (11 x 4 + 4)
     assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 768))
-    # VALU kernel beyond d = 16: 64 pairs per (d + 1) FMAs + exp2
+    # FP32 d = 20 runs at D = 24: ceil(74 / 16) = 5 ops; d = 41 at D = 48: 10 ops
+    assert bench.product_peak(20)[0] == pytest.approx(S * 1024 / (5 * 32 + 192))
+    assert bench.product_peak(41, "bf16")[0] == pytest.approx(S * 1024 / (10 * 32 + 192))
+    # VALU kernel: FP64 beyond d = 16, every precision beyond d = 48, and on request;
+    # 64 pairs per (d + 1) FMAs + exp2
+    assert bench.product_peak(60)[0] == pytest.approx(S * 64 / (61 * 4 + 8))
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
     assert bench.product_peak(20)[0] == pytest.approx(S * 64 / (21 * 4 + 8))
+    monkeypatch.delenv("KRR_KMVP_VALU")
     monkeypatch.setenv("KRR_KMVP_MG32", "1")
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
     # Matern d = 8: two f16 ops + 16 x (sqrt 8 + exp2 8 + 2 FMAs)

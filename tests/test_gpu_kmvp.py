@@ -247,3 +247,68 @@ def test_split_f16_kernel_far_and_wide_tiles(monkeypatch, prec):
     else:
         qb = torch.from_numpy(q).float().to(torch.bfloat16).double().numpy()
         assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [17, 24, 29, 32, 41, 48])
+def test_split_f16_large_d_matches_valu_kernel(monkeypatch, prec, d):
+    # 16 < d <= 48 (compiled at 24, 32, 48): the staged split-f16 kernel meets
+    # the oracle bar and agrees with the VALU kernel (KRR_KMVP_VALU=1) to FP32
+    # rounding; N = 1300 spans five full column tiles and a ragged one
+    n = 1300
+    x = workloads.random_points(120 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(121 + d, n)
+    sigma = 0.6 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _gpu_mvp(x, sigma, q, 0.03, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _gpu_mvp(x, sigma, q, 0.03, prec)
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.mvp(x, sigma, q, shift=0.03)
+    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    assert _relerr(a, b) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [24, 48])
+def test_split_f16_large_d_far_and_wide_tiles(monkeypatch, prec, d):
+    # d-dimensional version of the three-cluster case: two tight clusters 6 and
+    # 40 bandwidths apart along different axes (the second pair clamped as far)
+    # and a sparse cluster of wide tiles (direct form on FP32 offsets)
+    rng = np.random.default_rng(31 + d)
+    a = rng.normal(0.0, 0.3, size=(900, d))
+    b = rng.normal(0.0, 0.3, size=(800, d))
+    b[:, 0] += 6.0
+    c = rng.normal(0.0, 0.3, size=(700, d))
+    c[:, 1] += 40.0
+    s = rng.uniform(-300.0, 300.0, size=(600, d))
+    s[:, 2] += 400.0
+    x = np.ascontiguousarray(np.concatenate([a, b, c, s]))
+    q = workloads.random_vector(32 + d, x.shape[0])
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    y = _gpu_mvp(x, 1.0, q, 0.01, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    y_valu = _gpu_mvp(x, 1.0, q, 0.01, prec)
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    assert _relerr(y, y_valu) <= 1e-5
+    rows = np.arange(2400, 3000)
+    if prec == "fp32":
+        want = oracle.mvp(x, 1.0, q, shift=0.01)
+        assert _relerr(y, want) <= TOL[prec]
+        assert _relerr(y[rows], want[rows]) <= TOL[prec]
+    else:
+        qb = torch.from_numpy(q).float().to(torch.bfloat16).double().numpy()
+        assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [20, 40])
+def test_kmvp_cross_large_d(prec, d):
+    # prediction at new points through the staged split-f16 kernel
+    xs = workloads.random_points(800 + d, 1100, d, 1.0, kind="normal")
+    xt = workloads.random_points(900 + d, 700, d, 1.0, kind="normal")
+    q = workloads.random_vector(1000 + d, 1100)
+    sigma = 0.6 * np.sqrt(d)
+    y = _gpu_cross(xt, xs, sigma, q, prec)
+    want = oracle.mvp(xt, sigma, q, xs=xs)
+    assert _relerr(y, want) <= TOL[prec]
