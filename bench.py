@@ -97,7 +97,8 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     else:
         cyc = (d + 1) * C_FMA + C_EXP
     rule = f"64 pairs per {cyc} SIMD cycles: (d + 1) FMAs + exp2 per lane; 1024 SIMDs x 2.4 GHz"
-    return SIMD_CYCLES_S * 64 / cyc, rule, f"k_kmvp<{d}, {tag}>"
+    kname = f"k_kmvp_hd<{dpad(d)}, {tag}, gauss>" if d > 16 else f"k_kmvp<{dpad(d)}, {tag}>"
+    return SIMD_CYCLES_S * 64 / cyc, rule, kname
 
 
 def matern_peak(d: int) -> tuple[float, str, str]:
@@ -115,7 +116,8 @@ def matern_peak(d: int) -> tuple[float, str, str]:
         return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, FP32, matern>"
     cyc = (2 * d + 3) * C_FMA + C_SQRT + C_EXP
     rule = f"64 pairs per {cyc} SIMD cycles: 2d + 3 FMA-class ops + sqrt + exp2 per lane"
-    return SIMD_CYCLES_S * 64 / cyc, rule, f"k_kmvp_matern<{d}, FP32>"
+    kname = f"k_kmvp_hd<{dpad(d)}, FP32, matern>" if d > 16 else f"k_kmvp_matern<{dpad(d)}, FP32>"
+    return SIMD_CYCLES_S * 64 / cyc, rule, kname
 
 
 def multi_peak(d: int) -> tuple[float, str, str]:

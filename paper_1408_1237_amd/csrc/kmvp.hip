@@ -34,6 +34,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Lane k's value of v (k a wave-uniform index), as a scalar.
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const uint64_t bits = __builtin_bit_cast(uint64_t, v);
+    const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(bits), k);
+    const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(bits >> 32), k);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 template <int PREC>
 struct Prec;
 template <>
@@ -92,6 +100,7 @@ struct KArgs {
     const float *tile_far64;     // FP64 matrix-core kernel: the same for exponents <= -1100
     const void *slots;           // split-f16 kernel: source slot octets of the product's precision
     const void *off;
+    const void *pm;  // point-major offsets (dpad > 16)
     const void *q;
     const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
     void *out;
@@ -278,6 +287,173 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_matern(KArgs a, const typename P
     }
 }
 
+// ---------------------------------------------------------------- VALU form, d = 24 .. 64
+//
+// The VALU products of k_kmvp (Gaussian) and k_kmvp_matern for the large
+// compiled dimensions, with the same arithmetic in the same order per pair (the
+// results are bitwise those of the small-d kernels' loops).  The small-d
+// kernels keep the d coordinates of a group of columns in scalar registers,
+// reached through d coordinate addresses, with the row anchors beside them; at
+// d >= 24 that overflows the scalar register file.  Here the sources come from
+// the point-major copy pm ([n_pad][D]): a group of UC columns is one contiguous
+// run read by scalar loads at immediate offsets from a single base, two
+// columns at a time; the anchor differences of a tile sit one coordinate per
+// lane (read out with readlane) and the target offsets are re-read per tile
+// through a pointer that advances one coordinate per load behind an empty
+// statement (otherwise the compiler forms all d addresses up front in scalar
+// registers).
+template <int D, int PREC, bool MAT>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_hd(KArgs a, const typename Prec<PREC>::Off *__restrict__ pm,
+                                                   const typename Prec<PREC>::T *__restrict__ qw,
+                                                   const double *__restrict__ anchor,
+                                                   typename Prec<PREC>::T *__restrict__ out) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using T = typename P::T;
+    using Q = typename P::Q;
+    using Off = typename P::Off;
+    constexpr int UC = 16;  // columns per group
+    // a group is read in chunks of KCH coordinates of a column pair (32 scalar
+    // registers), software-pipelined one chunk ahead
+    constexpr int KCH = (PREC == KRR_FP64 || D % 16 != 0) ? 8 : 16;
+    constexpr int NKC = D / KCH;          // chunks per column pair
+    constexpr int NCK = (UC / 2) * NKC;   // chunks per group
+    // the FP64 Matern product (direct form only) measured faster with the
+    // column pairs left to the compiler's scheduling
+    constexpr bool PIPE = !(MAT && PREC == KRR_FP64);
+    static_assert(D % KCH == 0, "whole chunks per column");
+    auto load_chunk = [&](const typename Prec<PREC>::Off *b, int ck, typename Prec<PREC>::Off *dst) {
+        const int u = 2 * (ck / NKC), k0 = (ck % NKC) * KCH;
+#pragma unroll
+        for (int e = 0; e < KCH; ++e) {
+            dst[e] = b[u * D + k0 + e];
+            dst[KCH + e] = b[(u + 1) * D + k0 + e];
+        }
+    };
+    static_assert(D <= WAVE && TILE % UC == 0, "one anchor coordinate per lane; whole groups per tile");
+    constexpr double LOG2E = 1.4426950408889634074;
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
+    const int lane = threadIdx.x % WAVE;
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const double aB = lane < D ? a.row_anchor[static_cast<int64_t>(bx) * D + lane] : 0.0;
+
+    T acc = T(0);
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    for (int J = J0; J < J1; ++J) {
+        const double dA = lane < D ? aB - anchor[static_cast<int64_t>(J) * D + lane] : 0.0;
+        // t_k = x_k - a_Jk of this lane's target, kept as 2 t_k
+        T Tk[D];
+        double tt = 0.0;
+        {
+            const Off *rp = row_off + i;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const T tk = static_cast<T>(lane_value(dA, k) + static_cast<double>(P::off(*rp)));
+                rp += a.n_pad_rows;
+                asm volatile("" : "+v"(rp));
+                Tk[k] = tk + tk;
+                tt = __builtin_fma(static_cast<double>(tk), static_cast<double>(tk), tt);
+            }
+        }
+        const int64_t j0 = static_cast<int64_t>(J) * TILE;
+        const bool folded = !MAT && a.tile_r2[J] <= P::wide;
+        const T init = folded ? static_cast<T>(-tt - a.tile_nj[J]) : T(0);
+        for (int jb = 0; jb < TILE; jb += UC) {
+            // per column: folded, the exponent c + sum_k 2 t_k o_k; direct, the
+            // squared distance sum_k (t_k - o_k)^2
+            const Off *cb = pm + (j0 + jb) * D;
+            T arg[UC];
+            if constexpr (PIPE) {
+                T a0 = init, a1 = init, dep = init;
+                Off cur[2 * KCH];
+                load_chunk(cb, 0, cur);
+#pragma unroll
+                for (int ck = 0; ck < NCK; ++ck) {
+                    const int u = 2 * (ck / NKC), k0 = (ck % NKC) * KCH;
+                    Off nxt[2 * KCH];
+                    if (ck + 1 < NCK) {
+                        // the next chunk's loads wait for the previous chunk's
+                        // arithmetic (through dep): two chunks in flight at most
+                        // (a zero index that the compiler cannot see through: the
+                        // address stays based on pm, whose reads may then use the
+                        // scalar unit, and readfirstlane marks it uniform again)
+                        int z = 0;
+                        asm volatile("" : "+s"(z) : "v"(dep));
+                        load_chunk(cb + __builtin_amdgcn_readfirstlane(z), ck + 1, nxt);
+                    }
+                    if (k0 == 0) a0 = a1 = init;
+#pragma unroll
+                    for (int e = 0; e < KCH; ++e) {
+                        const T tk2 = Tk[k0 + e];
+                        if (folded) {
+                            a0 = fma_t(tk2, P::off(cur[e]), a0);
+                            a1 = fma_t(tk2, P::off(cur[KCH + e]), a1);
+                        } else {
+                            const T tk = tk2 * T(0.5);
+                            const T d0 = tk - P::off(cur[e]);
+                            const T d1 = tk - P::off(cur[KCH + e]);
+                            a0 = fma_t(d0, d0, a0);
+                            a1 = fma_t(d1, d1, a1);
+                        }
+                    }
+                    if (k0 + KCH == D) {
+                        arg[u] = a0;
+                        arg[u + 1] = a1;
+                    }
+                    dep = a0;
+#pragma unroll
+                    for (int e = 0; e < 2 * KCH; ++e) cur[e] = nxt[e];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < UC; u += 2) {
+                    T a0 = init, a1 = init;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const T tk = Tk[k] * T(0.5);
+                        const T d0 = tk - P::off(cb[u * D + k]);
+                        const T d1 = tk - P::off(cb[(u + 1) * D + k]);
+                        a0 = fma_t(d0, d0, a0);
+                        a1 = fma_t(d1, d1, a1);
+                    }
+                    arg[u] = a0;
+                    arg[u + 1] = a1;
+                }
+            }
+            if (folded) {
+#pragma unroll
+                for (int u = 0; u < UC; ++u) acc = fma_t(P::ex2(arg[u]), qw[j0 + jb + u], acc);
+            } else {
+#pragma unroll
+                for (int u = 0; u < UC; ++u) {
+                    const int64_t j = j0 + jb + u;
+                    if (MAT) {
+                        const T sd = sqrt(arg[u]);
+                        const T e = P::ex2(-sd * static_cast<T>(LOG2E));
+                        acc = fma_t(fma_t(sd, e, e), P::q(q[j]), acc);
+                    } else {
+                        acc = fma_t(P::ex2(-arg[u]), P::q(q[j]), acc);
+                    }
+                }
+            }
+        }
+        // close a partial-sum group
+        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
+            if (a.ngroups == 1) {
+                if (i < a.n_rows && a.square) acc += static_cast<T>(a.shift) * P::q(q[i]);
+                out[i] = (i < a.n_rows) ? acc : T(0);
+            } else {
+                out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = acc;
+            }
+            acc = T(0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- matrix-core exponent
 //
 // Products with the exponent on the matrix cores.  The folded exponent of a
@@ -409,11 +585,9 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
         if (J + 1 < J1) stage_load(J + 1);
         const double r2 = a.tile_r2[J];
         const double nj = a.tile_nj[J];
-        T t[RG][D];
-        T bval[RG][DK];
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-            double tt = 0.0;
+        // t = x - a_J of target group rg's lane (below d = 16 not kept over the
+        // folded path: the wide path forms it again)
+        auto target_t = [&](int rg, T (&t)[D]) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 T o;
@@ -421,10 +595,39 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                     o = oi[rg][k];
                 else
                     o = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
-                t[rg][k] = static_cast<T>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
-                                          static_cast<double>(o));
-                const double tk = static_cast<double>(t[rg][k]);
-                tt = __builtin_fma(tk, tk, tt);
+                t[k] = static_cast<T>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(o));
+            }
+        };
+        // at d = 16 keeping t for the wide path (formed in the same loop as |t|^2)
+        // measured faster than forming it again
+        constexpr bool KEEP_T = D >= 16;
+        T t_keep[KEEP_T ? RG : 1][KEEP_T ? D : 1];
+        T bval[RG][DK];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            T t[D];
+            double tt = 0.0;
+            if constexpr (KEEP_T) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    T o;
+                    if constexpr (KEEP)
+                        o = oi[rg][k];
+                    else
+                        o = P::off(row_off[k * a.n_pad_rows + row0 + rg * 16 + r16]);
+                    t_keep[rg][k] = static_cast<T>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
+                                                   static_cast<double>(o));
+                    const double tk = static_cast<double>(t_keep[rg][k]);
+                    tt = __builtin_fma(tk, tk, tt);
+                    t[k] = t_keep[rg][k];
+                }
+            } else {
+                target_t(rg, t);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double tk = static_cast<double>(t[k]);
+                    tt = __builtin_fma(tk, tk, tt);
+                }
             }
             T c = static_cast<T>(-tt - nj);
             // FP64: the operand is scaled by 256 (exactly) for exp2_x256, and a
@@ -443,7 +646,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 const int dim = 4 * kc + g;
                 T v = (dim == D) ? c : T(0);
 #pragma unroll
-                for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2) * sc * t[rg][k]) : v;
+                for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2) * sc * t[k]) : v;
                 bval[rg][kc] = v;
             }
         }
@@ -489,6 +692,16 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
             }
             accumulate(G[(TILE / 16 - 1) & 1], qv[(TILE / 16 - 1) & 1]);
         } else {
+            T t[RG][D];
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                if constexpr (KEEP_T) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t[rg][k] = t_keep[rg][k];
+                } else {
+                    target_t(rg, t[rg]);
+                }
+            }
             for (int cb = 0; cb < TILE; cb += 16) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -941,11 +1154,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     // that the D coordinate addresses are not all formed up front in scalar
     // registers (which would not fit).
     auto target_t = [&](double dA, const Off *&rp, int k) -> double {
-        const uint64_t bits = __builtin_bit_cast(uint64_t, dA);
-        const unsigned lo = __builtin_amdgcn_readlane(static_cast<unsigned>(bits), k);
-        const unsigned hi = __builtin_amdgcn_readlane(static_cast<unsigned>(bits >> 32), k);
-        const double dk = __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
-        const double td = dk + static_cast<double>(P::off(*rp));
+        const double td = lane_value(dA, k) + static_cast<double>(P::off(*rp));
         rp += a.n_pad_rows;
         asm volatile("" : "+v"(rp));
         return td;
@@ -1194,9 +1403,15 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
                 return hipGetLastError();
             }
         }
-        hipLaunchKernelGGL((k_kmvp_matern<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
-                           static_cast<const typename P::Off *>(a.off), static_cast<const typename P::Q *>(a.q),
-                           a.anchor, static_cast<typename P::T *>(a.out));
+        if constexpr (D > 16) {
+            hipLaunchKernelGGL((k_kmvp_hd<D, PREC, true>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                               static_cast<const typename P::Off *>(a.pm), static_cast<const typename P::T *>(a.qw),
+                               a.anchor, static_cast<typename P::T *>(a.out));
+        } else {
+            hipLaunchKernelGGL((k_kmvp_matern<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                               static_cast<const typename P::Off *>(a.off), static_cast<const typename P::Q *>(a.q),
+                               a.anchor, static_cast<typename P::T *>(a.out));
+        }
         return hipGetLastError();
     }
     if constexpr (D > 16 && D <= 48 && PREC != KRR_FP64) {
@@ -1218,9 +1433,15 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
-                       static_cast<const typename P::Off *>(a.off), static_cast<const typename P::T *>(a.qw),
-                       a.anchor, static_cast<typename P::T *>(a.out));
+    if constexpr (D > 16) {
+        hipLaunchKernelGGL((k_kmvp_hd<D, PREC, false>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                           static_cast<const typename P::Off *>(a.pm), static_cast<const typename P::T *>(a.qw),
+                           a.anchor, static_cast<typename P::T *>(a.out));
+    } else {
+        hipLaunchKernelGGL((k_kmvp<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a,
+                           static_cast<const typename P::Off *>(a.off), static_cast<const typename P::T *>(a.qw),
+                           a.anchor, static_cast<typename P::T *>(a.out));
+    }
     return hipGetLastError();
 }
 
@@ -1292,16 +1513,19 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     switch (prec) {
         case KRR_FP64:
             a.off = C.off64;
+            a.pm = C.pm64;
             a.row_off = R.off64;
             e = launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
             break;
         case KRR_FP32:
             a.off = C.off32;
+            a.pm = C.pm32;
             a.row_off = R.off32;
             e = launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
             break;
         case KRR_BF16:
             a.off = C.off16;
+            a.pm = C.pm16;
             a.row_off = R.off16;
             e = launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
             break;

@@ -122,6 +122,12 @@ struct Prepared {
     float *w32 = nullptr;
     float *w16 = nullptr;
     double *sq64 = nullptr;   // n_pad: ||o_j||^2 (FP64 offsets)
+    // point-major copies of the offsets ([n_pad][dpad]) for dpad > 16: the d
+    // coordinates of a source are contiguous, so the large-d VALU product
+    // reads a group of sources with scalar loads from one base address
+    double *pm64 = nullptr;
+    float *pm32 = nullptr;
+    uint16_t *pm16 = nullptr;
     // split-f16 source slot vectors of the FP32 and BF16 offsets (split16.h):
     // 2 split_chunks(dpad) octets per point, octet-major ([octet][n_pad]), for dpad <= 48
     void *slot32 = nullptr;

@@ -39,6 +39,11 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     P.w32 = cv.take<float>(P.n_pad);
     P.w16 = cv.take<float>(P.n_pad);
     P.sq64 = cv.take<double>(P.n_pad);
+    if (P.dpad > 16) {
+        P.pm64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
+        P.pm32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
+        P.pm16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
+    }
     const int oct = 2 * split_chunks(P.dpad);
     if (oct > 0) {
         P.slot32 = cv.take<half8_t>(static_cast<size_t>(oct) * P.n_pad);
@@ -171,6 +176,11 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
         P.off64[t * P.n_pad + j] = o;
         P.off32[t * P.n_pad + j] = o32;
         P.off16[t * P.n_pad + j] = o16;
+        if (P.pm64 != nullptr) {
+            P.pm64[j * dpad + t] = o;
+            P.pm32[j * dpad + t] = o32;
+            P.pm16[j * dpad + t] = o16;
+        }
         sq64 += o * o;
         sq32 += static_cast<double>(o32) * static_cast<double>(o32);
         sq16 += o16d * o16d;

@@ -312,3 +312,26 @@ def test_kmvp_cross_large_d(prec, d):
     y = _gpu_cross(xt, xs, sigma, q, prec)
     want = oracle.mvp(xt, sigma, q, xs=xs)
     assert _relerr(y, want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("d", [24, 41, 64])
+def test_fp64_large_d_far_and_wide_tiles(d):
+    # the FP64 VALU product at the large compiled dimensions on the
+    # three-cluster set (folded, far and wide tiles) and N(0, I) points
+    rng = np.random.default_rng(41 + d)
+    a = rng.normal(0.0, 0.3, size=(700, d))
+    b = rng.normal(0.0, 0.3, size=(600, d))
+    b[:, 0] += 6.0
+    c = rng.normal(0.0, 0.3, size=(500, d))
+    c[:, 1] += 40.0
+    s = rng.uniform(-300.0, 300.0, size=(400, d))
+    s[:, 2] += 400.0
+    x = np.ascontiguousarray(np.concatenate([a, b, c, s]))
+    q = workloads.random_vector(42 + d, x.shape[0])
+    y = _gpu_mvp(x, 1.0, q, 0.01, "fp64")
+    assert _relerr(y, oracle.mvp(x, 1.0, q, shift=0.01)) <= TOL["fp64"]
+    x = workloads.random_points(43 + d, 1100, d, 1.0, kind="normal")
+    q = workloads.random_vector(44 + d, 1100)
+    sigma = 0.6 * np.sqrt(d)
+    y = _gpu_mvp(x, sigma, q, 0.01, "fp64")
+    assert _relerr(y, oracle.mvp(x, sigma, q, shift=0.01)) <= TOL["fp64"]

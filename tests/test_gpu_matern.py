@@ -34,7 +34,8 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("n,d", [(1, 2), (257, 1), (2000, 2), (1500, 3), (3000, 8), (700, 17)])
+@pytest.mark.parametrize("n,d", [(1, 2), (257, 1), (2000, 2), (1500, 3), (3000, 8), (700, 17), (900, 40),
+                                 (600, 64)])
 def test_matern_product_matches_oracle(prec, n, d):
     x = workloads.random_points(100 + n + d, n, d, 1.0, kind="normal")
     q = workloads.random_vector(101 + n, n)
