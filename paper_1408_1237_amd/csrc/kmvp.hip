@@ -779,6 +779,32 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 // |t'|^2 < 30000 and |2t'| < 350, inside the f16 range.
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 
+// Lane l of a wave holds values of target (l / 32, l % 32); v_permlane32_swap
+// exchanges the upper half of its first operand with the lower half of its
+// second.  Given a lane's lo and hi values, g0 receives lo of target (0, l % 32)
+// in lanes 0-31 and hi of it in lanes 32-63, g1 the same for target (1, l % 32):
+// the B operands of both target groups from one operand build per lane.
+__device__ __forceinline__ void swap_halves(half8_t lo, half8_t hi, half8_t &g0, half8_t &g1) {
+    const uintx4_t L = __builtin_bit_cast(uintx4_t, lo), H = __builtin_bit_cast(uintx4_t, hi);
+    uintx4_t A, B;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const unsigned le = L[e], he = H[e];
+        const auto r = __builtin_amdgcn_permlane32_swap(le, he, false, false);
+        A[e] = r[0];
+        B[e] = r[1];
+    }
+    g0 = __builtin_bit_cast(half8_t, A);
+    g1 = __builtin_bit_cast(half8_t, B);
+}
+// The same for one value per lane: g0 = v of target (0, l % 32), g1 = v of (1, l % 32).
+__device__ __forceinline__ void swap_halves(float v, float &g0, float &g1) {
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    g0 = __builtin_bit_cast(float, static_cast<unsigned>(r[0]));
+    g1 = __builtin_bit_cast(float, static_cast<unsigned>(r[1]));
+}
+
 template <int D, int PREC, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -811,11 +837,11 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     double aI[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
-    float oi[RG][D];
+    // lane l forms the target operand of row row0 + l (group l / 32, target
+    // l % 32) and trades half of it with lane l ^ 32 (see swap_halves)
+    float oi[D];
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-        for (int k = 0; k < D; ++k) oi[rg][k] = P::off(row_off[k * a.n_pad_rows + row0 + rg * 32 + r32]);
+    for (int k = 0; k < D; ++k) oi[k] = P::off(row_off[k * a.n_pad_rows + row0 + lane]);
     float acc[RG];
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.f;
@@ -866,17 +892,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
         const double r2 = a.tile_r2[J];
         const float njf = static_cast<float>(a.tile_nj[J]);  // a small integer
         const float far_t2 = a.tile_far[J];
+        // t = x - a_J of this lane's target
+        float t[D];
+        double tt = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double td = (aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[k]);
+            t[k] = static_cast<float>(td);
+            tt = __builtin_fma(td, td, tt);
+        }
         half8_t bval[RG][KC];
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-            float t[D];
-            double tt = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double td = (aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(oi[rg][k]);
-                t[k] = static_cast<float>(td);
-                tt = __builtin_fma(td, td, tt);
-            }
+        if (r2 <= P::wide) {
             const bool far = static_cast<float>(tt) > far_t2;
             const _Float16 z16 = static_cast<_Float16>(0.f), one16 = static_cast<_Float16>(1.f);
             HiLo v[D], c, c2;
@@ -894,12 +920,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                 c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
                 c2 = HiLo{z16, z16};
             }
+            // this lane holds both octets of chunk kc for its own target; the B
+            // operand wants octet h of targets (group 0, l % 32) and (group 1, l % 32)
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c, c2);
-                const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c, c2);
-                bval[rg][kc] = h ? hi8 : lo8;
-            }
+            for (int kc = 0; kc < KC; ++kc)
+                swap_halves(slot_octet<D, false>(2 * kc, v, c, c2), slot_octet<D, false>(2 * kc + 1, v, c, c2),
+                            bval[0][kc], bval[1][kc]);
         }
         if (r2 <= P::wide) {
             // Software pipeline over the 8 column steps of 32 sources: the matrix
@@ -961,13 +987,9 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
         } else {
             // wide tile: the direct form sum_k (t_k - o_k)^2 on the VALU, the two
             // halves of the wave taking alternate sources (FP32 offsets staged)
-            float t[RG][D];
+            float tg[RG][D];  // t of targets (group 0, l % 32) and (group 1, l % 32)
 #pragma unroll
-            for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    t[rg][k] = static_cast<float>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) +
-                                                  static_cast<double>(oi[rg][k]));
+            for (int k = 0; k < D; ++k) swap_halves(t[k], tg[0][k], tg[1][k]);
             for (int cs = 0; cs < TILE; cs += 2) {
                 const int cj = cs + h;
                 float oc[D];
@@ -984,7 +1006,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                     float ss = 0.f;
 #pragma unroll
                     for (int k = 0; k < D; ++k) {
-                        const float dd = t[rg][k] - oc[k];
+                        const float dd = tg[rg][k] - oc[k];
                         ss = __builtin_fmaf(dd, dd, ss);
                     }
                     if constexpr (MAT) {
@@ -1175,35 +1197,29 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
             // the target operand of tile J: 2t and c = -|t|^2 - N_J split as in k_kmvp_mh
             const float njf = static_cast<float>(a.tile_nj[J]);
             const float far_t2 = a.tile_far[J];
+            // (lane l builds the operand of row row0 + l and trades half of it
+            // with lane l ^ 32, as in k_kmvp_mh)
             const double dA = anchor_diff(J);
+            float t[D];
+            double tt = 0.0;
+            const Off *rp = row_off + (row0 + lane);
 #pragma unroll
-            for (int rg = 0; rg < RG; ++rg) {
-                float t[D];
-                double tt = 0.0;
-                const Off *rp = row_off + (row0 + rg * 32 + r32);
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const double td = target_t(dA, rp, k);
-                    t[k] = static_cast<float>(td);
-                    tt = __builtin_fma(td, td, tt);
-                }
-                const bool far = static_cast<float>(tt) > far_t2;
-                const _Float16 z16 = static_cast<_Float16>(0.f);
-                HiLo v[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
-                const HiLo c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
-                const HiLo c2{z16, z16};
-#pragma unroll
-                for (int kc = 0; kc < KC; ++kc) {
-                    const half8_t lo8 = slot_octet<D, false>(2 * kc, v, c, c2);
-                    const half8_t hi8 = slot_octet<D, false>(2 * kc + 1, v, c, c2);
-                    bval[rg][kc] = h ? hi8 : lo8;
-                }
-                // one target group at a time: the splits of both groups live at
-                // once would not fit the register file
-                __builtin_amdgcn_sched_barrier(0);
+            for (int k = 0; k < D; ++k) {
+                const double td = target_t(dA, rp, k);
+                t[k] = static_cast<float>(td);
+                tt = __builtin_fma(td, td, tt);
             }
+            const bool far = static_cast<float>(tt) > far_t2;
+            const _Float16 z16 = static_cast<_Float16>(0.f);
+            HiLo v[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+            const HiLo c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
+            const HiLo c2{z16, z16};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+                swap_halves(slot_octet<D, false>(2 * kc, v, c, c2), slot_octet<D, false>(2 * kc + 1, v, c, c2),
+                            bval[0][kc], bval[1][kc]);
         }
         if (!wide) {
             // two 32-source steps, each one exponent block per target group on
