@@ -500,6 +500,15 @@ template <>
 struct MG<KRR_BF16> : MG<KRR_FP32> {};
 
 
+// Groups of 16 targets per wave: 4 (a block covers one 256-row tile), or 2
+// for FP64 at d = 16, where four groups' accumulators and operands do not fit
+// two waves per SIMD (a block then covers half a tile; measured 10% faster
+// there, 6% slower at d = 12).
+template <int D, int PREC>
+constexpr int mg_groups() {
+    return (PREC == KRR_FP64 && D >= 16) ? 2 : 4;
+}
+
 template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -510,13 +519,16 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     using Off = typename P::Off;
     using Q = typename P::Q;
     constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
-    constexpr int RG = 4;
-    constexpr int DR = 4 * DK;       // coordinate rows in LDS: d offsets, the constant 1, zeros
+    constexpr int RG = mg_groups<D, PREC>();  // groups of 16 targets per wave
+    constexpr int HB = 4 / RG;                // blocks per 256-row tile
+    // LDS holds the d offset rows; coordinate d (the constant 1) and the zero
+    // padding up to 4 DK are formed in registers (at d = 16 FP64 the four extra
+    // rows would cost the second block per CU)
     constexpr int LDO = TILE + 16;  // padded LDS row: coordinate rows start 16 banks apart
     // The sources of the current column tile (offsets, and q w on folded tiles or
     // q on wide ones) are staged in LDS, double-buffered: the block loads tile
     // J + 1 from memory while it computes tile J.
-    __shared__ T s_off[2][DR][LDO];
+    __shared__ T s_off[2][D][LDO];
     __shared__ __align__(16) T s_q[2][TILE];
     // FP64: the table of 2^(j/256) (exp2_x256)
     constexpr bool TAB = PREC == KRR_FP64;
@@ -528,21 +540,23 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     const T *__restrict__ qw = static_cast<const T *>(a.qw);
     const int64_t n_pad = a.n_pad;
 
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
-    const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
+    const int nrb = a.nrowblocks * HB;
+    const int lb = xcd_remap(blockIdx.x, nrb * a.splits);
+    const int bh = lb % nrb, by = lb / nrb;
+    const int bx = bh / HB;  // row tile
     const int tid = threadIdx.x;
     const int lane = tid % WAVE;
     const int r16 = lane % 16, g = lane / 16;
     // source of A row r16 within a 16-column step
     const int asrc = M::permute_rows ? (r16 % 4) * 4 + r16 / 4 : r16;
-    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (tid / WAVE) * 64;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (bh % HB) * (BLOCK / HB) + (tid / WAVE) * (16 * RG);
 
     double aI[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(bx) * D + k];
-    // the lane's target offsets stay in registers when they fit in 64 VGPRs,
-    // else they are re-read once per column tile
-    constexpr bool KEEP = RG * D * sizeof(T) <= 256;
+    // the lane's target offsets stay in registers when they fit in 64 VGPRs (32
+    // with two groups), else they are re-read once per column tile
+    constexpr bool KEEP = RG * D * sizeof(T) <= (RG == 2 ? 128 : 256);
     T oi[KEEP ? RG : 1][KEEP ? D : 1];
     if constexpr (KEEP) {
 #pragma unroll
@@ -570,11 +584,6 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
         for (int k = 0; k < D; ++k) s_off[buf][k][tid] = st_o[k];
         s_q[buf][tid] = st_q;
     };
-    // rows d .. 4 DK - 1 of both buffers: the constant coordinate 1, then zeros
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int k = D; k < DR; ++k) s_off[b][k][tid] = (k == D) ? T(1) : T(0);
     if (J0 < J1) {
         stage_load(J0);
         stage_store(0);
@@ -598,9 +607,9 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 t[k] = static_cast<T>((aI[k] - a.anchor[static_cast<int64_t>(J) * D + k]) + static_cast<double>(o));
             }
         };
-        // at d = 16 keeping t for the wide path (formed in the same loop as |t|^2)
-        // measured faster than forming it again
-        constexpr bool KEEP_T = D >= 16;
+        // at d = 16 with four groups keeping t for the wide path (formed in the
+        // same loop as |t|^2) measured faster than forming it again
+        constexpr bool KEEP_T = D >= 16 && RG == 4;
         T t_keep[KEEP_T ? RG : 1][KEEP_T ? D : 1];
         T bval[RG][DK];
 #pragma unroll
@@ -656,7 +665,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
             // the VALU exponentiates and accumulates step cb.
             auto load_step = [&](int cb, T (&av)[DK], V4 &qv) {
 #pragma unroll
-                for (int kc = 0; kc < DK; ++kc) av[kc] = s_off[buf][4 * kc + g][cb + asrc];
+                for (int kc = 0; kc < DK; ++kc) {
+                    const int dim = 4 * kc + g;
+                    if (4 * kc + 3 < D) {
+                        av[kc] = s_off[buf][dim][cb + asrc];
+                    } else {
+                        // the last chunk: offsets below d, then the constant 1 and zeros
+                        // (as o * [dim < d] + [dim == d])
+                        const T o = s_off[buf][min(dim, D - 1)][cb + asrc];
+                        av[kc] = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
+                    }
+                }
                 qv = *reinterpret_cast<const V4 *>(&s_q[buf][cb + 4 * g]);
             };
             auto exponents = [&](const T (&av)[DK], V4 (&G)[RG]) {
@@ -1445,7 +1464,8 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
                     return hipGetLastError();
                 }
             }
-            hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * (4 / mg_groups<D, PREC>()) * a.splits),
+                               dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }
