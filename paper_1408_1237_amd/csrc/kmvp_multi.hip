@@ -267,6 +267,37 @@ constexpr int multi_chunk_h() {
     return fit >= 256 ? 256 : fit >= 128 ? 128 : fit >= 64 ? 64 : 32;
 }
 
+// Transpose across the four 16-lane rows of a wave: on entry lane row g holds
+// o[j] = item (g, j); on exit it holds o[j] = item (j, g).  Two exchange steps
+// per 32-bit word: v_permlane32_swap trades the upper lane half of its first
+// operand with the lower half of its second (registers j, j + 2), then
+// v_permlane16_swap the odd 16-lane rows of its first operand with the even
+// rows of its second (registers 2i, 2i + 1).
+__device__ __forceinline__ void transpose_rows(half8_t (&o)[4]) {
+    uintx4_t R[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R[j] = __builtin_bit_cast(uintx4_t, o[j]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const unsigned x = R[j][e], y = R[j + 2][e];
+            const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+            R[j][e] = r[0];
+            R[j + 2][e] = r[1];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const unsigned x = R[2 * i][e], y = R[2 * i + 1][e];
+            const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+            R[2 * i][e] = r[0];
+            R[2 * i + 1][e] = r[1];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = __builtin_bit_cast(half8_t, R[j]);
+}
+
 template <int D, int PREC>
 __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int rbk) {
     using P = MP<PREC>;
@@ -344,11 +375,20 @@ __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int
 
     for (int pass = 0; pass < 4 / RB; ++pass) {
         const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + wave * 64 + pass * RB * 16;
-        float oi[RB][D];
+        // RB = 4: lane l forms the operand of its own target row0 + l (group l / 16)
+        // and the four lane rows trade octets (transpose_rows); RB = 2: every lane
+        // forms the operands of both of its groups
+        constexpr bool XPOSE = RB == 4;
+        float oi[XPOSE ? 1 : RB][D];
+        if constexpr (XPOSE) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int k = 0; k < D; ++k) oi[0][k] = P::off(off[k * n_pad + row0 + lane]);
+        } else {
 #pragma unroll
-            for (int k = 0; k < D; ++k) oi[rb][k] = P::off(off[k * n_pad + row0 + rb * 16 + r16]);
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int k = 0; k < D; ++k) oi[rb][k] = P::off(off[k * n_pad + row0 + rb * 16 + r16]);
+        }
         floatx4 acc[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -358,6 +398,10 @@ __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int
             stage_store(0);
         }
         __syncthreads();
+        // the target operand depends on the column tile only: with RB = 4 formed
+        // at the tile's first chunk and kept over its CPT chunks (with RB = 2,
+        // where registers are short, formed again per chunk)
+        half8_t bval[RB][KC];
         for (int ci = C0; ci < C1; ++ci) {
             const int buf = (ci - C0) & 1;
             if (ci + 1 < C1) stage_load(ci + 1);
@@ -366,9 +410,9 @@ __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int
             if (r2 <= P::wide) {
                 const float njf = static_cast<float>(tile_nj[J]);
                 const float far_t2 = tile_far[J];
-                half8_t bval[RB][KC];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
+                for (int rb = 0; rb < (XPOSE ? 1 : RB); ++rb) {
+                    if (XPOSE && ci % CPT != 0) break;
                     float t[D];
                     double tt = 0.0;
 #pragma unroll
@@ -389,11 +433,16 @@ __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int
 #pragma unroll
                     for (int kc = 0; kc < KC; ++kc) {
                         // octet 4 kc + g of the target vector (lane group g)
-                        const half8_t o0 = slot_octet<D, false>(4 * kc + 0, v, c, c2);
-                        const half8_t o1 = slot_octet<D, false>(4 * kc + 1, v, c, c2);
-                        const half8_t o2 = slot_octet<D, false>(4 * kc + 2, v, c, c2);
-                        const half8_t o3 = slot_octet<D, false>(4 * kc + 3, v, c, c2);
-                        bval[rb][kc] = g == 0 ? o0 : g == 1 ? o1 : g == 2 ? o2 : o3;
+                        half8_t o[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) o[j] = slot_octet<D, false>(4 * kc + j, v, c, c2);
+                        if constexpr (XPOSE) {
+                            transpose_rows(o);
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) bval[j][kc] = o[j];
+                        } else {
+                            bval[rb][kc] = g == 0 ? o[0] : g == 1 ? o[1] : g == 2 ? o[2] : o[3];
+                        }
                     }
                 }
 #pragma unroll 2
@@ -424,9 +473,15 @@ __device__ __forceinline__ void multi_body_h(const MArgs &a, int bx, int by, int
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                    for (int k = 0; k < D; ++k)
+                    for (int k = 0; k < D; ++k) {
+                        float o;
+                        if constexpr (XPOSE)
+                            o = P::off(off[k * n_pad + row0 + rb * 16 + r16]);
+                        else
+                            o = oi[rb][k];
                         t[rb][k] = static_cast<float>((aI[k] - anchor[static_cast<int64_t>(J) * D + k]) +
-                                                      static_cast<double>(oi[rb][k]));
+                                                      static_cast<double>(o));
+                    }
 #pragma unroll 1
                 for (int st = 0; st < SC; st += 16) {
 #pragma unroll

@@ -301,10 +301,11 @@ def test_split_f16_large_d_far_and_wide_tiles(monkeypatch, prec, d):
         assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("d", [20, 40])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d", [20, 40, 64])
 def test_kmvp_cross_large_d(prec, d):
-    # prediction at new points through the staged split-f16 kernel
+    # prediction at new points through the large-d kernels (staged split-f16 for
+    # FP32 / BF16 up to 48, the point-major VALU form otherwise)
     xs = workloads.random_points(800 + d, 1100, d, 1.0, kind="normal")
     xt = workloads.random_points(900 + d, 700, d, 1.0, kind="normal")
     q = workloads.random_vector(1000 + d, 1100)

@@ -45,3 +45,23 @@ def test_predict_mean_only_at_kriging_scale():
     assert var is None
     want = oracle.mvp(xs, p.sigma, w, xs=p.x)
     assert np.linalg.norm(mean.cpu().numpy() - want) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("kernel", ["gauss", "matern32"])
+def test_predict_mean_large_d(kernel):
+    # the posterior mean at d = 20 (cross products through the large-d VALU
+    # kernels in FP64) against the oracle's Cholesky prediction
+    from paper_1408_1237_amd import api
+    d = 20
+    x = workloads.random_points(170, 800, d, 1.0, kind="normal")
+    xs = workloads.random_points(171, 45, d, 1.0, kind="normal")
+    y = np.tanh(x[:, 0] - x[:, 1]) + 0.1 * workloads.random_vector(172, 800)
+    sigma, gamma = 0.6 * np.sqrt(d), 1e-2
+    if kernel == "gauss":
+        w = oracle.direct_solve(x, sigma, gamma, y)
+    else:
+        w = oracle.matern_direct_solve(x, sigma, gamma, y)
+    mean, var, _ = api.krr_predict(_t(x), _t(xs), sigma, gamma, _t(w), want_var=False, kernel=kernel)
+    m_ref, _ = oracle.predict(x, xs, sigma, gamma, y, kernel=kernel)
+    assert var is None
+    assert np.allclose(mean.cpu().numpy(), m_ref, rtol=1e-9, atol=1e-10)
