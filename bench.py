@@ -63,8 +63,9 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     exponentials and 16 FMAs: FP32 / BF16 for d <= 48 (split-f16 kernels)
     ceil((3D + 2) / 16) 32x32x16 f16 matrix-core operations; FP64 for d <= 16
     4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the compiled dimension; FP64
-    exponentials from the 256-entry table, 11 instructions).  Otherwise (VALU
-    kernel) per 64 pairs: d + 1 FMAs and one exponential per lane.  Matrix-core
+    exponentials from the 256-entry table, 11 instructions), the same model for
+    FP64 at d > 16 (staged kernel).  Otherwise (VALU kernel) per 64 pairs: d + 1
+    FMAs and one exponential per lane.  Matrix-core
     and VALU issue counted one after the other (measured by the issue probe).
     """
     tag = {"fp64": "FP64", "bf16": "BF16"}.get(prec, "FP32")
@@ -76,6 +77,13 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core ops + 16 x (exp2 + FMA) "
                 f"per lane, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mhw<{D}, {tag}>"
+    if 16 < d and prec == "fp64" and not valu:
+        D = dpad(d)
+        dk = (D + 4) // 4
+        cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64_TAB + C_FMA)
+        rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + 16 x (exp2 + FMA) per "
+                f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mgw<{D}>"
     if d <= 16 and not valu:
         D = dpad(d)
         if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":

@@ -1318,6 +1318,199 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- FP64 matrix-core exponent, d = 24 .. 64
+//
+// The FP64 product of k_kmvp_mg (the exponent [2t, c] . [o, 1] on the FP64
+// matrix cores with the operand scaled by 256, the table exponential, the far
+// clamp) for the large compiled dimensions.  The sources of a column tile pass
+// through LDS 64 at a time (double buffered), a wave owns 2 groups of 16
+// targets (a block half a row tile), and the target operand is formed per
+// column tile by each lane for its own coordinates 4 kc + g only (lane group
+// g), with |t|^2 summed over the four lane groups by two exchanges: no lane
+// forms or holds all d coordinates.  Wide tiles take the direct form with the
+// same coordinate split (each pair's squared distance summed over the lane
+// groups; the first group accumulates).
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<KRR_FP64>;
+    using V4 = doublex4_t;
+    constexpr int DK = (D + 4) / 4;   // chunks of 4 over the d + 1 coordinates
+    constexpr int RG = 2;             // groups of 16 targets per wave
+    constexpr int HB = 2;             // blocks per 256-row tile
+    constexpr int CH = 64;            // sources per LDS stage
+    constexpr int NCH = TILE / CH;
+    constexpr int LDC = CH + 2;       // padded LDS row
+    constexpr int NA = D * CH / BLOCK;
+    static_assert(D * CH % BLOCK == 0 && D % 4 == 0, "whole staging rounds");
+    __shared__ double s_off[2][D][LDC];
+    __shared__ __align__(32) double s_q[2][CH];
+    __shared__ double s_exp2[256];
+    s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
+    const double *__restrict__ off = static_cast<const double *>(a.off);
+    const double *__restrict__ row_off = static_cast<const double *>(a.row_off);
+    const double *__restrict__ q = static_cast<const double *>(a.q);
+    const double *__restrict__ qw = static_cast<const double *>(a.qw);
+    const int64_t n_pad = a.n_pad;
+
+    const int nrb = a.nrowblocks * HB;
+    const int lb = xcd_remap(blockIdx.x, nrb * a.splits);
+    const int bh = lb % nrb, by = lb / nrb;
+    const int bx = bh / HB;  // row tile
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE;
+    const int r16 = lane % 16, g = lane / 16;
+    // A row r16 of a 16-source step holds source (r16 % 4) * 4 + r16 / 4, so
+    // that lane l's four accumulator rows are the contiguous sources 4 (l / 16) + v
+    const int asrc = (r16 % 4) * 4 + r16 / 4;
+    const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (bh % HB) * (BLOCK / HB) + (tid / WAVE) * (16 * RG);
+    double acc[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.0;
+    double *__restrict__ out = static_cast<double *>(a.out);
+
+    const int J0 = by * a.tps;
+    const int J1 = min(a.ntiles, J0 + a.tps);
+    const int C0 = J0 * NCH, C1 = J1 * NCH;
+    double st_o[NA], st_q = 0.0;
+    auto stage_load = [&](int ci) {
+        const int J = ci / NCH;
+        const int64_t j0 = static_cast<int64_t>(J) * TILE + (ci % NCH) * CH;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            st_o[u] = off[(e / CH) * n_pad + j0 + e % CH];
+        }
+        if (tid < CH) st_q = a.tile_r2[J] > P::wide ? q[j0 + tid] : qw[j0 + tid];
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = u * BLOCK + tid;
+            s_off[buf][e / CH][e % CH] = st_o[u];
+        }
+        if (tid < CH) s_q[buf][tid] = st_q;
+    };
+    // this lane's coordinates 4 kc + g of t = x - a_J for target group rg, and
+    // the partial |t|^2 over them
+    auto target_part = [&](int J, int rg, double (&tv)[DK]) -> double {
+        const int64_t i = row0 + rg * 16 + r16;
+        double tp = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < DK; ++kc) {
+            const int dim = 4 * kc + g;
+            const int dc = min(dim, D - 1);
+            const double td = (a.row_anchor[static_cast<int64_t>(bx) * D + dc] - a.anchor[static_cast<int64_t>(J) * D + dc]) +
+                              row_off[dc * a.n_pad_rows + i];
+            tv[kc] = dim < D ? td : 0.0;
+            tp = __builtin_fma(tv[kc], tv[kc], tp);
+        }
+        return tp;
+    };
+    auto group_sum = [&](double v) -> double {
+        v += __shfl_xor(v, 16, WAVE);
+        return v + __shfl_xor(v, 32, WAVE);
+    };
+
+    if (C0 < C1) {
+        stage_load(C0);
+        stage_store(0);
+    }
+    __syncthreads();
+    double bval[RG][DK];
+    for (int ci = C0; ci < C1; ++ci) {
+        const int buf = (ci - C0) & 1;
+        if (ci + 1 < C1) stage_load(ci + 1);
+        const int J = ci / NCH;
+        const bool wide = a.tile_r2[J] > P::wide;
+        if (!wide && ci % NCH == 0) {
+            const double nj = a.tile_nj[J];
+            const double far_t2 = static_cast<double>(a.tile_far64[J]);
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                double tv[DK];
+                const double tt = group_sum(target_part(J, rg, tv));
+                // operand scaled by 256 for exp2_x256; a target whose every
+                // exponent against the tile is <= -1100 gets -2000 (exp2 is 0 in
+                // FP64 either way), which keeps the scaled exponents in int range
+                const bool far = tt > far_t2;
+                const double c = far ? -2000.0 * 256.0 : (-tt - nj) * 256.0;
+#pragma unroll
+                for (int kc = 0; kc < DK; ++kc) {
+                    const int dim = 4 * kc + g;
+                    bval[rg][kc] = dim < D ? (far ? 0.0 : 512.0 * tv[kc]) : (dim == D ? c : 0.0);
+                }
+            }
+        }
+        if (!wide) {
+#pragma unroll
+            for (int st = 0; st < CH / 16; ++st) {
+                double av[DK];
+#pragma unroll
+                for (int kc = 0; kc < DK; ++kc) {
+                    const int dim = 4 * kc + g;
+                    if (4 * kc + 3 < D) {
+                        av[kc] = s_off[buf][dim][st * 16 + asrc];
+                    } else {
+                        // the last chunk: offsets below d, then the constant 1 and zeros
+                        const double o = s_off[buf][min(dim, D - 1)][st * 16 + asrc];
+                        av[kc] = __builtin_fma(o, static_cast<double>(dim < D), static_cast<double>(dim == D));
+                    }
+                }
+                const V4 qv = *reinterpret_cast<const V4 *>(&s_q[buf][st * 16 + 4 * g]);
+#pragma unroll
+                for (int rg = 0; rg < RG; ++rg) {
+                    V4 G = V4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kc = 0; kc < DK; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc], bval[rg][kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[rg] = __builtin_fma(exp2_x256(G[v], s_exp2), qv[v], acc[rg]);
+                }
+            }
+        } else {
+            // wide tile: the direct form; each pair's squared distance summed over
+            // the lane groups' coordinates, accumulated by the first group
+#pragma unroll 1
+            for (int rg = 0; rg < RG; ++rg) {
+                double tv[DK];
+                target_part(J, rg, tv);
+#pragma unroll 1
+                for (int col = 0; col < CH; ++col) {
+                    double sp = 0.0;
+#pragma unroll
+                    for (int kc = 0; kc < DK; ++kc) {
+                        const int dim = 4 * kc + g;
+                        const double o = s_off[buf][min(dim, D - 1)][col];
+                        const double dd = dim < D ? tv[kc] - o : 0.0;
+                        sp = __builtin_fma(dd, dd, sp);
+                    }
+                    const double ss = group_sum(sp);
+                    const double val = exp2_f64(-ss) * s_q[buf][col];
+                    acc[rg] += g == 0 ? val : 0.0;
+                }
+            }
+        }
+        // close a partial-sum group after the last stage of a tile
+        if (ci % NCH == NCH - 1 && ((J + 1) % a.gtiles == 0 || J + 1 == J1)) {
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) {
+                const double sum = group_sum(acc[rg]);
+                acc[rg] = 0.0;
+                const int64_t i = row0 + rg * 16 + r16;
+                if (g == 0) {
+                    if (a.ngroups == 1) {
+                        out[i] = (i < a.n_rows) ? sum + (a.square ? a.shift * q[i] : 0.0) : 0.0;
+                    } else {
+                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
+                    }
+                }
+            }
+        }
+        if (ci + 1 < C1) stage_store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- plans and tuning
 
 // Partial-sum groups: the sources are cut into groups of gtiles consecutive
@@ -1466,6 +1659,12 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
             }
             hipLaunchKernelGGL((k_kmvp_mg<D, PREC>), dim3(a.nrowblocks * (4 / mg_groups<D, PREC>()) * a.splits),
                                dim3(BLOCK), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (D > 16 && PREC == KRR_FP64) {
+        if (!use_valu_kernel()) {
+            hipLaunchKernelGGL((k_kmvp_mgw<D>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }

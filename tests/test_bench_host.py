@@ -30,8 +30,9 @@ def test_product_peaks_by_hand(monkeypatch):
     # FP32 d = 20 runs at D = 24: ceil(74 / 16) = 5 ops; d = 41 at D = 48: 10 ops
     assert bench.product_peak(20)[0] == pytest.approx(S * 1024 / (5 * 32 + 192))
     assert bench.product_peak(41, "bf16")[0] == pytest.approx(S * 1024 / (10 * 32 + 192))
-    # VALU kernel: FP64 beyond d = 16, every precision beyond d = 48, and on request;
-    # 64 pairs per (d + 1) FMAs + exp2
+    # FP64 at d = 41 runs at D = 48: 4 x 13 FP64 ops + 16 x (11 x 4 + 4)
+    assert bench.product_peak(41, "fp64")[0] == pytest.approx(S * 1024 / (52 * 64 + 768))
+    # VALU kernel: FP32 / BF16 beyond d = 48, and on request; 64 pairs per (d + 1) FMAs + exp2
     assert bench.product_peak(60)[0] == pytest.approx(S * 64 / (61 * 4 + 8))
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
     assert bench.product_peak(20)[0] == pytest.approx(S * 64 / (21 * 4 + 8))

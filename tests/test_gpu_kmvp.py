@@ -336,3 +336,21 @@ def test_fp64_large_d_far_and_wide_tiles(d):
     sigma = 0.6 * np.sqrt(d)
     y = _gpu_mvp(x, sigma, q, 0.01, "fp64")
     assert _relerr(y, oracle.mvp(x, sigma, q, shift=0.01)) <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("d", [17, 24, 29, 32, 41, 48, 64])
+def test_fp64_matrix_core_large_d_matches_valu_kernel(monkeypatch, d):
+    # FP64 products at d > 16 run the staged matrix-core kernel; KRR_KMVP_VALU=1
+    # selects the VALU form; both meet the FP64 bar and agree to FP64 rounding
+    n = 1300
+    x = workloads.random_points(140 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(141 + d, n)
+    sigma = 0.6 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _gpu_mvp(x, sigma, q, 0.03, "fp64")
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _gpu_mvp(x, sigma, q, 0.03, "fp64")
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.mvp(x, sigma, q, shift=0.03)
+    assert _relerr(a, want) <= TOL["fp64"] and _relerr(b, want) <= TOL["fp64"]
+    assert _relerr(a, b) <= 1e-13
