@@ -110,18 +110,19 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
 
 
 def matern_peak(d: int) -> tuple[float, str, str]:
-    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 16 (split-f16 kernel),
+    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 48 (split-f16 kernels),
     per 1024 pairs: ceil((3D + 4) / 16) 32x32x16 f16 matrix-core operations and,
     per lane, 16 x (sqrt + exp2 + 2 FMAs), serial issue (v_sqrt_f32 costs 8
     cycles, as v_exp_f32).  Otherwise (VALU kernel) per 64 pairs: 2d + 3
     FMA-class operations, sqrt and exp2 per lane."""
-    if d <= 16 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
+    if d <= 48 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
         D = dpad(d)
         kc = (3 * D + 4 + 15) // 16
         cyc = kc * C_MFMA_H32 + 16 * (C_SQRT + C_EXP + 2 * C_FMA)
         rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core op(s) + 16 x (sqrt + exp2 + "
                 f"2 FMA) per lane, serial issue; 1024 SIMDs x 2.4 GHz")
-        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, FP32, matern>"
+        kname = f"k_kmvp_mh<{D}, FP32, matern>" if d <= 16 else f"k_kmvp_mhw<{D}, FP32, matern>"
+        return SIMD_CYCLES_S * 1024 / cyc, rule, kname
     cyc = (2 * d + 3) * C_FMA + C_SQRT + C_EXP
     rule = f"64 pairs per {cyc} SIMD cycles: 2d + 3 FMA-class ops + sqrt + exp2 per lane"
     kname = f"k_kmvp_hd<{dpad(d)}, FP32, matern>" if d > 16 else f"k_kmvp_matern<{dpad(d)}, FP32>"

@@ -1109,7 +1109,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad,
 // from memory, and within a 64-source stage the matrix cores form the second
 // 32-source step while the VALU exponentiates the first.  Wide tiles take the
 // direct form on staged FP32 offsets, one target group at a time.
-template <int D, int PREC>
+template <int D, int PREC, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
@@ -1125,6 +1125,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
     __shared__ __align__(16) half8_t s_a[2][NOCT][CH];
     __shared__ __align__(16) float s_q[2][CH];
+    __shared__ __align__(16) float s_q2[MAT ? 2 : 1][MAT ? CH : 4];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -1173,7 +1174,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
                 st_a[u] = slots[c * n_pad + j0 + col];
             }
         }
-        if (tid < CH) st_q = wide ? P::q(q[j0 + tid]) : qw[j0 + tid];
+        if (tid < CH) st_q = (wide || MAT) ? P::q(q[j0 + tid]) : qw[j0 + tid];
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
@@ -1181,7 +1182,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
             const int e = u * BLOCK + tid;
             if (e < NOCT * CH) s_a[buf][e / CH][e % CH] = st_a[u];
         }
-        if (tid < CH) s_q[buf][tid] = st_q;
+        if (tid < CH) {
+            s_q[buf][tid] = st_q;
+            if constexpr (MAT) s_q2[buf][tid] = LN2_F * st_q;
+        }
     };
     // the anchor difference a_B - a_J of the row block and tile J, coordinate
     // k in lane k (uniform values kept in vector registers: as scalars they
@@ -1229,12 +1233,21 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
                 tt = __builtin_fma(td, td, tt);
             }
             const bool far = static_cast<float>(tt) > far_t2;
-            const _Float16 z16 = static_cast<_Float16>(0.f);
-            HiLo v[D];
+            const _Float16 z16 = static_cast<_Float16>(0.f), one16 = static_cast<_Float16>(1.f);
+            HiLo v[D], c, c2;
+            if constexpr (MAT) {
+                // -2 t', |t'|^2 (t' = log2(e) t) and the source constant's (1, 1)
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
-            const HiLo c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
-            const HiLo c2{z16, z16};
+                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : -2.f * LOG2E_F * t[k]);
+                c = far ? HiLo{static_cast<_Float16>(60000.f), z16}
+                        : split_f16(LOG2E_F * LOG2E_F * static_cast<float>(tt));
+                c2 = HiLo{one16, one16};
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
+                c2 = HiLo{z16, z16};
+            }
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc)
                 swap_halves(slot_octet<D, false>(2 * kc, v, c, c2), slot_octet<D, false>(2 * kc + 1, v, c, c2),
@@ -1259,15 +1272,25 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
                             G[rg] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[kc], bval[rg][kc], G[rg], 0, 0, 0);
                     }
                 }
-                floatx4_t qv[4];
+                floatx4_t qv[4], qv2[MAT ? 4 : 1];
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 4; ++m) {
                     qv[m] = *reinterpret_cast<const floatx4_t *>(&s_q[buf][st * 32 + 8 * m + 4 * h]);
+                    if constexpr (MAT) qv2[m] = *reinterpret_cast<const floatx4_t *>(&s_q2[buf][st * 32 + 8 * m + 4 * h]);
+                }
 #pragma unroll
                 for (int v = 0; v < 16; ++v)
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg)
-                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                    for (int rg = 0; rg < RG; ++rg) {
+                        if constexpr (MAT) {
+                            // G = (log2(e) s)^2: (1 + s) e^(-s) q = 2^(-u) (q + u ln2 q), u = sqrt(G)
+                            const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[rg][v]));
+                            const float w = __builtin_fmaf(u, qv2[v / 4][v % 4], qv[v / 4][v % 4]);
+                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-u), w, acc[rg]);
+                        } else {
+                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                        }
+                    }
             }
         } else {
             // wide tile: the direct form on the staged FP32 offsets, the two halves
@@ -1291,7 +1314,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
                         const float dd = t[k] - __builtin_bit_cast(float, wv);
                         ss = __builtin_fmaf(dd, dd, ss);
                     }
-                    acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), s_q[buf][cj], acc[rg]);
+                    if constexpr (MAT) {
+                        const float sd = __builtin_sqrtf(ss);
+                        const float e = __builtin_amdgcn_exp2f(-LOG2E_F * sd);
+                        acc[rg] = __builtin_fmaf(__builtin_fmaf(sd, e, e), s_q[buf][cj], acc[rg]);
+                    } else {
+                        acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-ss), s_q[buf][cj], acc[rg]);
+                    }
                 }
             }
         }
@@ -1625,6 +1654,12 @@ template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     using P = Prec<PREC>;
     if (kernel == KRR_KERNEL_MATERN32) {
+        if constexpr (D > 16 && D <= 48 && PREC != KRR_FP64) {
+            if (!use_valu_kernel()) {
+                hipLaunchKernelGGL((k_kmvp_mhw<D, PREC, true>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+                return hipGetLastError();
+            }
+        }
         if constexpr (D <= 16 && PREC != KRR_FP64) {
             if (!use_valu_kernel()) {
                 hipLaunchKernelGGL((k_kmvp_mh<D, PREC, true>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
@@ -1644,7 +1679,7 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     }
     if constexpr (D > 16 && D <= 48 && PREC != KRR_FP64) {
         if (!use_valu_kernel()) {
-            hipLaunchKernelGGL((k_kmvp_mhw<D, PREC>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_kmvp_mhw<D, PREC, false>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }

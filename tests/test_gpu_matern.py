@@ -108,10 +108,11 @@ def test_matern_unknown_kernel_rejected():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 12, 16])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 8, 12, 16, 17, 24, 33, 48])
 def test_matern_matrix_core_kernel_matches_valu_kernel(monkeypatch, prec, d):
-    # FP32 / BF16 Matern products at d <= 16 form the squared distance on the
-    # matrix cores (split-f16); KRR_KMVP_VALU=1 selects the VALU kernel.  The
+    # FP32 / BF16 Matern products at d <= 48 form the squared distance on the
+    # matrix cores (split-f16; staged sources above 16); KRR_KMVP_VALU=1 selects
+    # the VALU kernel.  The
     # two agree to FP32 rounding on the same rounded inputs; FP32 meets the
     # oracle bar, BF16 inputs do up to d = 8 (at d = 12, 16 the BF16 rounding of
     # the offsets alone reaches about 1e-2, the same for both kernels)
@@ -152,4 +153,27 @@ def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch):
     assert _rel(y, yv) <= 1e-5
     assert _rel(y, want) <= 1e-4
     rows = np.arange(1900, 2400)
+    assert _rel(y[rows], want[rows]) <= 1e-6
+
+
+@pytest.mark.parametrize("d", [24, 48])
+def test_matern_matrix_core_large_d_far_and_wide_tiles(monkeypatch, d):
+    # the same three-cluster construction in d dimensions for the staged kernel
+    rng = np.random.default_rng(25 + d)
+    a = rng.normal(0.0, 0.3, size=(900, d))
+    b = rng.normal(0.0, 0.3, size=(800, d))
+    b[:, 0] += 150.0
+    s = rng.uniform(-3000.0, 3000.0, size=(500, d))
+    s[:, 1] += 5000.0
+    x = np.ascontiguousarray(np.concatenate([a, b, s]))
+    q = workloads.random_vector(26 + d, x.shape[0])
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    y = _mvp(x, 1.0, q, 0.01, "fp32")
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    yv = _mvp(x, 1.0, q, 0.01, "fp32")
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.matern_mvp(x, 1.0, q, shift=0.01)
+    assert _rel(y, yv) <= 1e-5
+    assert _rel(y, want) <= 1e-4
+    rows = np.arange(1700, 2200)
     assert _rel(y[rows], want[rows]) <= 1e-6
