@@ -77,13 +77,16 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"1024 pairs per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core ops + 16 x (exp2 + FMA) "
                 f"per lane, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mhw<{D}, {tag}>"
-    if 16 < d and prec == "fp64" and not valu:
+    if ((16 < d and prec == "fp64") or d > 48) and not valu:
         D = dpad(d)
         dk = (D + 4) // 4
-        cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64_TAB + C_FMA)
-        rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + 16 x (exp2 + FMA) per "
+        if prec == "fp64":
+            cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64_TAB + C_FMA)
+        else:
+            cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
+        rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
                 f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
-        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mgw<{D}>"
+        return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mgw<{D}, {tag}>"
     if d <= 16 and not valu:
         D = dpad(d)
         if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":

@@ -1347,11 +1347,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- FP64 matrix-core exponent, d = 24 .. 64
+// ---------------------------------------------------------------- matrix-core exponent, d = 24 .. 64
 //
-// The FP64 product of k_kmvp_mg (the exponent [2t, c] . [o, 1] on the FP64
-// matrix cores with the operand scaled by 256, the table exponential, the far
-// clamp) for the large compiled dimensions.  The sources of a column tile pass
+// The product of k_kmvp_mg (the exponent [2t, c] . [o, 1] on the matrix cores;
+// in FP64 with the operand scaled by 256, the table exponential and the far
+// clamp) for the large compiled dimensions: FP64 above d = 16, FP32 / BF16
+// above d = 48 (where the split-f16 operands no longer fit).  The sources of a column tile pass
 // through LDS 64 at a time (double buffered), a wave owns 2 groups of 16
 // targets (a block half a row tile), and the target operand is formed per
 // column tile by each lane for its own coordinates 4 kc + g only (lane group
@@ -1359,11 +1360,16 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
 // forms or holds all d coordinates.  Wide tiles take the direct form with the
 // same coordinate split (each pair's squared distance summed over the lane
 // groups; the first group accumulates).
-template <int D>
+template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
-    using P = Prec<KRR_FP64>;
-    using V4 = doublex4_t;
+    using P = Prec<PREC>;
+    using M = MG<PREC>;
+    using T = typename M::T;
+    using V4 = typename M::V4;
+    using Off = typename P::Off;
+    using Q = typename P::Q;
+    constexpr bool TAB = PREC == KRR_FP64;  // table exponential, scaled operand, far clamp
     constexpr int DK = (D + 4) / 4;   // chunks of 4 over the d + 1 coordinates
     constexpr int RG = 2;             // groups of 16 targets per wave
     constexpr int HB = 2;             // blocks per 256-row tile
@@ -1372,14 +1378,14 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     constexpr int LDC = CH + 2;       // padded LDS row
     constexpr int NA = D * CH / BLOCK;
     static_assert(D * CH % BLOCK == 0 && D % 4 == 0, "whole staging rounds");
-    __shared__ double s_off[2][D][LDC];
-    __shared__ __align__(32) double s_q[2][CH];
-    __shared__ double s_exp2[256];
-    s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
-    const double *__restrict__ off = static_cast<const double *>(a.off);
-    const double *__restrict__ row_off = static_cast<const double *>(a.row_off);
-    const double *__restrict__ q = static_cast<const double *>(a.q);
-    const double *__restrict__ qw = static_cast<const double *>(a.qw);
+    __shared__ T s_off[2][D][LDC];
+    __shared__ __align__(32) T s_q[2][CH];
+    __shared__ double s_exp2[TAB ? 256 : 1];
+    if constexpr (TAB) s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const T *__restrict__ qw = static_cast<const T *>(a.qw);
     const int64_t n_pad = a.n_pad;
 
     const int nrb = a.nrowblocks * HB;
@@ -1389,28 +1395,29 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid % WAVE;
     const int r16 = lane % 16, g = lane / 16;
-    // A row r16 of a 16-source step holds source (r16 % 4) * 4 + r16 / 4, so
-    // that lane l's four accumulator rows are the contiguous sources 4 (l / 16) + v
-    const int asrc = (r16 % 4) * 4 + r16 / 4;
+    // FP64: A row r16 of a 16-source step holds source (r16 % 4) * 4 + r16 / 4,
+    // so that lane l's four accumulator rows are the contiguous sources
+    // 4 (l / 16) + v, as they are in FP32 without the permutation
+    const int asrc = M::permute_rows ? (r16 % 4) * 4 + r16 / 4 : r16;
     const int64_t row0 = static_cast<int64_t>(bx) * BLOCK + (bh % HB) * (BLOCK / HB) + (tid / WAVE) * (16 * RG);
-    double acc[RG];
+    T acc[RG];
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) acc[rg] = 0.0;
-    double *__restrict__ out = static_cast<double *>(a.out);
+    for (int rg = 0; rg < RG; ++rg) acc[rg] = T(0);
+    T *__restrict__ out = static_cast<T *>(a.out);
 
     const int J0 = by * a.tps;
     const int J1 = min(a.ntiles, J0 + a.tps);
     const int C0 = J0 * NCH, C1 = J1 * NCH;
-    double st_o[NA], st_q = 0.0;
+    T st_o[NA], st_q = T(0);
     auto stage_load = [&](int ci) {
         const int J = ci / NCH;
         const int64_t j0 = static_cast<int64_t>(J) * TILE + (ci % NCH) * CH;
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = u * BLOCK + tid;
-            st_o[u] = off[(e / CH) * n_pad + j0 + e % CH];
+            st_o[u] = P::off(off[(e / CH) * n_pad + j0 + e % CH]);
         }
-        if (tid < CH) st_q = a.tile_r2[J] > P::wide ? q[j0 + tid] : qw[j0 + tid];
+        if (tid < CH) st_q = a.tile_r2[J] > P::wide ? static_cast<T>(P::q(q[j0 + tid])) : qw[j0 + tid];
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
@@ -1422,7 +1429,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     };
     // this lane's coordinates 4 kc + g of t = x - a_J for target group rg, and
     // the partial |t|^2 over them
-    auto target_part = [&](int J, int rg, double (&tv)[DK]) -> double {
+    auto target_part = [&](int J, int rg, T (&tv)[DK]) -> double {
         const int64_t i = row0 + rg * 16 + r16;
         double tp = 0.0;
 #pragma unroll
@@ -1430,13 +1437,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             const int dim = 4 * kc + g;
             const int dc = min(dim, D - 1);
             const double td = (a.row_anchor[static_cast<int64_t>(bx) * D + dc] - a.anchor[static_cast<int64_t>(J) * D + dc]) +
-                              row_off[dc * a.n_pad_rows + i];
-            tv[kc] = dim < D ? td : 0.0;
-            tp = __builtin_fma(tv[kc], tv[kc], tp);
+                              static_cast<double>(P::off(row_off[dc * a.n_pad_rows + i]));
+            tv[kc] = dim < D ? static_cast<T>(td) : T(0);
+            tp = __builtin_fma(static_cast<double>(tv[kc]), static_cast<double>(tv[kc]), tp);
         }
         return tp;
     };
-    auto group_sum = [&](double v) -> double {
+    auto group_sum = [&](auto v) {
         v += __shfl_xor(v, 16, WAVE);
         return v + __shfl_xor(v, 32, WAVE);
     };
@@ -1446,7 +1453,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
         stage_store(0);
     }
     __syncthreads();
-    double bval[RG][DK];
+    T bval[RG][DK];
     for (int ci = C0; ci < C1; ++ci) {
         const int buf = (ci - C0) & 1;
         if (ci + 1 < C1) stage_load(ci + 1);
@@ -1457,24 +1464,25 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             const double far_t2 = static_cast<double>(a.tile_far64[J]);
 #pragma unroll
             for (int rg = 0; rg < RG; ++rg) {
-                double tv[DK];
+                T tv[DK];
                 const double tt = group_sum(target_part(J, rg, tv));
-                // operand scaled by 256 for exp2_x256; a target whose every
+                // FP64: operand scaled by 256 for exp2_x256; a target whose every
                 // exponent against the tile is <= -1100 gets -2000 (exp2 is 0 in
                 // FP64 either way), which keeps the scaled exponents in int range
-                const bool far = tt > far_t2;
-                const double c = far ? -2000.0 * 256.0 : (-tt - nj) * 256.0;
+                const bool far = TAB && tt > far_t2;
+                const T sc = TAB ? T(256) : T(1);
+                const T c = far ? T(-2000.0 * 256.0) : static_cast<T>(-tt - nj) * sc;
 #pragma unroll
                 for (int kc = 0; kc < DK; ++kc) {
                     const int dim = 4 * kc + g;
-                    bval[rg][kc] = dim < D ? (far ? 0.0 : 512.0 * tv[kc]) : (dim == D ? c : 0.0);
+                    bval[rg][kc] = dim < D ? (far ? T(0) : T(2) * sc * tv[kc]) : (dim == D ? c : T(0));
                 }
             }
         }
         if (!wide) {
 #pragma unroll
             for (int st = 0; st < CH / 16; ++st) {
-                double av[DK];
+                T av[DK];
 #pragma unroll
                 for (int kc = 0; kc < DK; ++kc) {
                     const int dim = 4 * kc + g;
@@ -1482,18 +1490,23 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                         av[kc] = s_off[buf][dim][st * 16 + asrc];
                     } else {
                         // the last chunk: offsets below d, then the constant 1 and zeros
-                        const double o = s_off[buf][min(dim, D - 1)][st * 16 + asrc];
-                        av[kc] = __builtin_fma(o, static_cast<double>(dim < D), static_cast<double>(dim == D));
+                        const T o = s_off[buf][min(dim, D - 1)][st * 16 + asrc];
+                        av[kc] = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
                     }
                 }
                 const V4 qv = *reinterpret_cast<const V4 *>(&s_q[buf][st * 16 + 4 * g]);
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) {
-                    V4 G = V4{0.0, 0.0, 0.0, 0.0};
+                    V4 G = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-                    for (int kc = 0; kc < DK; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kc], bval[rg][kc], G, 0, 0, 0);
+                    for (int kc = 0; kc < DK; ++kc) G = M::mfma(av[kc], bval[rg][kc], G);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[rg] = __builtin_fma(exp2_x256(G[v], s_exp2), qv[v], acc[rg]);
+                    for (int v = 0; v < 4; ++v) {
+                        if constexpr (TAB)
+                            acc[rg] = M::fma(exp2_x256(G[v], s_exp2), qv[v], acc[rg]);
+                        else
+                            acc[rg] = M::fma(P::ex2(G[v]), qv[v], acc[rg]);
+                    }
                 }
             }
         } else {
@@ -1501,21 +1514,21 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             // the lane groups' coordinates, accumulated by the first group
 #pragma unroll 1
             for (int rg = 0; rg < RG; ++rg) {
-                double tv[DK];
+                T tv[DK];
                 target_part(J, rg, tv);
 #pragma unroll 1
                 for (int col = 0; col < CH; ++col) {
-                    double sp = 0.0;
+                    T sp = T(0);
 #pragma unroll
                     for (int kc = 0; kc < DK; ++kc) {
                         const int dim = 4 * kc + g;
-                        const double o = s_off[buf][min(dim, D - 1)][col];
-                        const double dd = dim < D ? tv[kc] - o : 0.0;
-                        sp = __builtin_fma(dd, dd, sp);
+                        const T o = s_off[buf][min(dim, D - 1)][col];
+                        const T dd = dim < D ? tv[kc] - o : T(0);
+                        sp = M::fma(dd, dd, sp);
                     }
-                    const double ss = group_sum(sp);
-                    const double val = exp2_f64(-ss) * s_q[buf][col];
-                    acc[rg] += g == 0 ? val : 0.0;
+                    const T ss = group_sum(sp);
+                    const T val = P::ex2(-ss) * s_q[buf][col];
+                    acc[rg] += g == 0 ? val : T(0);
                 }
             }
         }
@@ -1523,12 +1536,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
         if (ci % NCH == NCH - 1 && ((J + 1) % a.gtiles == 0 || J + 1 == J1)) {
 #pragma unroll
             for (int rg = 0; rg < RG; ++rg) {
-                const double sum = group_sum(acc[rg]);
-                acc[rg] = 0.0;
+                const T sum = group_sum(acc[rg]);
+                acc[rg] = T(0);
                 const int64_t i = row0 + rg * 16 + r16;
                 if (g == 0) {
                     if (a.ngroups == 1) {
-                        out[i] = (i < a.n_rows) ? sum + (a.square ? a.shift * q[i] : 0.0) : 0.0;
+                        out[i] = (i < a.n_rows) ? sum + (a.square ? static_cast<T>(a.shift) * P::q(q[i]) : T(0)) : T(0);
                     } else {
                         out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
                     }
@@ -1697,9 +1710,9 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
             return hipGetLastError();
         }
     }
-    if constexpr (D > 16 && PREC == KRR_FP64) {
+    if constexpr ((D > 16 && PREC == KRR_FP64) || D > 48) {
         if (!use_valu_kernel()) {
-            hipLaunchKernelGGL((k_kmvp_mgw<D>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_kmvp_mgw<D, PREC>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }

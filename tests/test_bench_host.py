@@ -32,8 +32,9 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(41, "bf16")[0] == pytest.approx(S * 1024 / (10 * 32 + 192))
     # FP64 at d = 41 runs at D = 48: 4 x 13 FP64 ops + 16 x (11 x 4 + 4)
     assert bench.product_peak(41, "fp64")[0] == pytest.approx(S * 1024 / (52 * 64 + 768))
-    # VALU kernel: FP32 / BF16 beyond d = 48, and on request; 64 pairs per (d + 1) FMAs + exp2
-    assert bench.product_peak(60)[0] == pytest.approx(S * 64 / (61 * 4 + 8))
+    # FP32 beyond d = 48 runs at D = 64 on the FP32 matrix cores: 4 x 17 ops + 16 x (8 + 4)
+    assert bench.product_peak(60)[0] == pytest.approx(S * 1024 / (68 * 32 + 192))
+    # VALU kernel on request: 64 pairs per (d + 1) FMAs + exp2
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
     assert bench.product_peak(20)[0] == pytest.approx(S * 64 / (21 * 4 + 8))
     monkeypatch.delenv("KRR_KMVP_VALU")

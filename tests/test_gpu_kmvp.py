@@ -354,3 +354,22 @@ def test_fp64_matrix_core_large_d_matches_valu_kernel(monkeypatch, d):
     want = oracle.mvp(x, sigma, q, shift=0.03)
     assert _relerr(a, want) <= TOL["fp64"] and _relerr(b, want) <= TOL["fp64"]
     assert _relerr(a, b) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [49, 64])
+def test_fp32_matrix_core_d64_matches_valu_kernel(monkeypatch, prec, d):
+    # FP32 / BF16 products above d = 48 (compiled at 64) take the staged FP32
+    # matrix-core kernel; it meets the oracle bar and agrees with the VALU form
+    n = 1300
+    x = workloads.random_points(150 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(151 + d, n)
+    sigma = 0.6 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _gpu_mvp(x, sigma, q, 0.03, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _gpu_mvp(x, sigma, q, 0.03, prec)
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.mvp(x, sigma, q, shift=0.03)
+    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    assert _relerr(a, b) <= 1e-5
