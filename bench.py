@@ -384,6 +384,58 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
                                       "1024 SIMDs x 2.4 GHz (time includes prep and the epilogue kernels)"}}
 
 
+def workload_highd(args, api, native, workloads, torch) -> dict:
+    """Regression at the regression table's largest shape (N = 44,484, d = 41):
+    product rates per precision (FP64 and FP32 / BF16 on their large-d
+    matrix-core kernels), the mixed FGMRES solve with the paper's inner rule and
+    plain FP64 CG to 1e-6."""
+    p = workloads.regression_highd()
+    x = torch.from_numpy(p.x).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    rates = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        q = torch.randn(p.n, dtype=torch.float64, device="cuda").to(dt)
+        api.kmvp_gauss(x, p.sigma, q, shift=p.gamma, prec=prec)
+        torch.cuda.synchronize()
+        with native.profile() as prof:
+            for _ in range(5):
+                api.kmvp_gauss(x, p.sigma, q, shift=p.gamma, prec=prec)
+            torch.cuda.synchronize()
+        st = prof.stats[prec]
+        rates[prec] = {"gpair_s": round(st["pairs"] / (st["total_ms"] * 1e-3) / 1e9, 1),
+                       "avg_launch_ms": round(st["total_ms"] / max(st["launches"], 1), 4)}
+    log(f"high-d products: {rates}")
+    opts = dict(inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol, delta=p.delta, restart_m=1000,
+                tol=p.tol, max_outer=args.max_outer or 1000, gs="cgs2")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, **opts)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    log(f"high-d fgmres: {info['outer_iters']} outer, {info['inner_iters']} inner, relres {info['relres_true']:.3e}, "
+        f"{tf:.2f} s")
+    t0 = time.perf_counter()
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=20000,
+                                 cg_check=32)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    log(f"high-d cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
+    peak, rule, kname = product_peak(p.d)
+    ach = rates["fp32"]["gpair_s"]
+    return {"metric": METRIC, "value": ach * 1e9, "unit": "pairs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "higher_is_better": True, "vs_baseline": None,
+            "config": {"workload": "regression N=44484 d=41 x~N(0,I) sigma=sqrt(41) gamma=1e-2; FGMRES with the "
+                                   "paper's inner rule vs FP64 CG", "n": p.n, "d": p.d},
+            "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak / 1e9, 1), "unit": "Gpair/s",
+                         "frac": round(ach * 1e9 / peak, 4), "traffic": None, "kernel": kname, "peak_rule": rule},
+            "products": rates,
+            "fgmres": {"time_s": tf, "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
+                       "relres_true": info["relres_true"]},
+            "cg64": {"time_s": tc, "iters": ic["outer_iters"], "relres_true": ic["relres_true"]},
+            "speedup_fgmres_vs_cg64": tc / tf}
+
+
 def workload_matern(args, api, native, workloads, torch) -> dict:
     """Matern-3/2 GPR (N = 1e5, d = 8): product rates per precision, the mixed
     FGMRES solve (the paper's inner rule) and plain FP64 CG to 1e-6."""
@@ -501,7 +553,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
     ap.add_argument("--kernel-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision of the --kernel-only products")
-    ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "sweep"),
+    ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "highd", "sweep"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
                     help="outer-step budget of the secondary workloads (clustered: default 8; others: "
@@ -524,7 +576,7 @@ def main() -> int:
         return 2
     native.load()
     others = {"clustered": workload_clustered, "batched": workload_batched, "gp": workload_gp,
-              "matern": workload_matern, "sweep": workload_sweep}
+              "matern": workload_matern, "highd": workload_highd, "sweep": workload_sweep}
     if args.workload in others:
         out = others[args.workload](args, api, native, workloads, torch)
         print(json.dumps(out), flush=True)

@@ -138,6 +138,20 @@ def gp_regression(seed: int = 5, n: int = 200_000, d: int = 16) -> Problem:
                    inner_maxit=10, inner_tol=1e-5)
 
 
+def regression_highd(seed: int = 7, n: int = 44_484, d: int = 41) -> Problem:
+    """GPR at the largest dimension and size of the regression table (d = 41,
+    N = 44,484; the datasets themselves are absent and this stands in for their
+    shape): x ~ N(0, I_d), y = tanh(x . w) + N(0, 0.1^2) with w ~ N(0, I/d);
+    sigma = sqrt(d), gamma = 1e-2, delta = 10 gamma.
+    """
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d))
+    wv = rng.standard_normal(d) / np.sqrt(d)
+    y = np.tanh(x @ wv) + 0.1 * rng.standard_normal(n)
+    return Problem("regression_highd", _c(x), _c(y), sigma=float(np.sqrt(d)), gamma=1e-2, delta=1e-1,
+                   inner_maxit=10, inner_tol=1e-5)
+
+
 def matern_classification(seed: int = 6, n: int = 100_000, d: int = 8) -> Problem:
     """GPR on binary labels with the Matern-3/2 kernel (the classification sets of
     Table 2 are absent; this stands in for their shape at a larger N).
