@@ -1373,7 +1373,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     constexpr int DK = (D + 4) / 4;   // chunks of 4 over the d + 1 coordinates
     constexpr int RG = 2;             // groups of 16 targets per wave
     constexpr int HB = 2;             // blocks per 256-row tile
-    constexpr int CH = 64;            // sources per LDS stage
+    // sources per LDS stage (32 at d = 48: the staging registers then leave
+    // room for two waves per SIMD, 29% faster; at d = 64 the smaller stage
+    // keeps one wave and measured slower)
+    constexpr int CH = D == 48 ? 32 : 64;
     constexpr int NCH = TILE / CH;
     constexpr int LDC = CH + 2;       // padded LDS row
     constexpr int NA = D * CH / BLOCK;
