@@ -373,3 +373,19 @@ def test_fp32_matrix_core_d64_matches_valu_kernel(monkeypatch, prec, d):
     want = oracle.mvp(x, sigma, q, shift=0.03)
     assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
     assert _relerr(a, b) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d", [24, 48, 64])
+@pytest.mark.parametrize("nt,ns", [(1, 1), (1, 300), (300, 1), (3, 1100)])
+def test_kmvp_cross_large_d_tiny_sets(prec, d, nt, ns):
+    # single targets or sources through the staged large-d kernels (padded tiles,
+    # one ragged stage)
+    xs = workloads.random_points(1100 + ns + d, ns, d, 1.0, kind="normal")
+    xt = workloads.random_points(1200 + nt + d, nt, d, 1.0, kind="normal")
+    q = workloads.random_vector(1300 + ns, ns)
+    sigma = 0.6 * np.sqrt(d)
+    y = _gpu_cross(xt, xs, sigma, q, prec)
+    want = oracle.mvp(xt, sigma, q, xs=xs)
+    assert y.shape == (nt,)
+    assert _relerr(y, want) <= TOL[prec]
