@@ -1500,9 +1500,20 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                 const V4 qv = *reinterpret_cast<const V4 *>(&s_q[buf][st * 16 + 4 * g]);
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) {
-                    V4 G = V4{T(0), T(0), T(0), T(0)};
+                    // FP64 at d = 32 and 64: two accumulators over alternate chunks
+                    // (half as long a chain of dependent matrix-core operations)
+                    // measured 4% faster; at d = 24 and 48 their registers cost the
+                    // second wave, and FP32 at d = 64 ran slower with them
+                    constexpr bool ACC2 = TAB && (D == 32 || D == 64);
+                    V4 G = V4{T(0), T(0), T(0), T(0)}, G1 = G;
 #pragma unroll
-                    for (int kc = 0; kc < DK; ++kc) G = M::mfma(av[kc], bval[rg][kc], G);
+                    for (int kc = 0; kc < DK; ++kc) {
+                        if (ACC2 && (kc & 1))
+                            G1 = M::mfma(av[kc], bval[rg][kc], G1);
+                        else
+                            G = M::mfma(av[kc], bval[rg][kc], G);
+                    }
+                    if constexpr (ACC2) G += G1;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         if constexpr (TAB)
