@@ -530,10 +530,16 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     // J + 1 from memory while it computes tile J.
     __shared__ T s_off[2][D][LDO];
     __shared__ __align__(16) T s_q[2][TILE];
-    // FP64: the table of 2^(j/256) (exp2_x256)
+    // FP64: the table of 2^(j/N) (exp2_tab): N = 2048 (a degree-3 polynomial,
+    // one FMA fewer per pair) at d <= 3, where it measured 3% faster; N = 256
+    // above (no gain measured there, and at d = 4 the compiler then gave up a
+    // wave per SIMD)
     constexpr bool TAB = PREC == KRR_FP64;
-    __shared__ double s_exp2[TAB ? 256 : 1];
-    if constexpr (TAB) s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
+    constexpr int TN = D <= 3 ? 2048 : 256;
+    __shared__ double s_exp2[TAB ? TN : 1];
+    if constexpr (TAB) {
+        for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE2048[k];
+    }
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -639,15 +645,15 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 }
             }
             T c = static_cast<T>(-tt - nj);
-            // FP64: the operand is scaled by 256 (exactly) for exp2_x256, and a
+            // FP64: the operand is scaled by N (exactly) for exp2_tab, and a
             // target whose every exponent against the tile is <= -1100 (exp2 is
             // 0 in FP64 either way) gets -2000 for the whole tile, which keeps
             // the scaled exponents in int range
-            const T sc = TAB ? T(256) : T(1);
+            const T sc = TAB ? T(TN) : T(1);
             bool far = false;
             if constexpr (TAB) {
                 far = tt > static_cast<double>(a.tile_far64[J]);
-                c = far ? T(-2000.0 * 256.0) : c * sc;
+                c = far ? T(-2000.0 * TN) : c * sc;
             }
             // coordinate 4 kc + g of [2t, c, 0...] for this lane's chunk slots
 #pragma unroll
@@ -692,7 +698,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
 #pragma unroll
                     for (int rg = 0; rg < RG; ++rg) {
                         if constexpr (TAB)
-                            acc[rg] = M::fma(exp2_x256(G[rg][v], s_exp2), qv[v], acc[rg]);
+                            acc[rg] = M::fma(exp2_tab<TN>(G[rg][v], s_exp2), qv[v], acc[rg]);
                         else
                             acc[rg] = M::fma(P::ex2(G[rg][v]), qv[v], acc[rg]);
                     }
@@ -1383,7 +1389,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     static_assert(D * CH % BLOCK == 0 && D % 4 == 0, "whole staging rounds");
     __shared__ T s_off[2][D][LDC];
     __shared__ __align__(32) T s_q[2][CH];
-    __shared__ double s_exp2[TAB ? 256 : 1];
+    // FP64: the table of 2^(j/256) (exp2_tab; the 2048-entry form measured no
+    // faster here)
+    constexpr int TN = 256;
+    __shared__ double s_exp2[TAB ? TN : 1];
     if constexpr (TAB) s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
@@ -1469,12 +1478,12 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             for (int rg = 0; rg < RG; ++rg) {
                 T tv[DK];
                 const double tt = group_sum(target_part(J, rg, tv));
-                // FP64: operand scaled by 256 for exp2_x256; a target whose every
+                // FP64: operand scaled by N for exp2_tab; a target whose every
                 // exponent against the tile is <= -1100 gets -2000 (exp2 is 0 in
                 // FP64 either way), which keeps the scaled exponents in int range
                 const bool far = TAB && tt > far_t2;
-                const T sc = TAB ? T(256) : T(1);
-                const T c = far ? T(-2000.0 * 256.0) : static_cast<T>(-tt - nj) * sc;
+                const T sc = TAB ? T(TN) : T(1);
+                const T c = far ? T(-2000.0 * TN) : static_cast<T>(-tt - nj) * sc;
 #pragma unroll
                 for (int kc = 0; kc < DK; ++kc) {
                     const int dim = 4 * kc + g;
@@ -1517,7 +1526,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         if constexpr (TAB)
-                            acc[rg] = M::fma(exp2_x256(G[v], s_exp2), qv[v], acc[rg]);
+                            acc[rg] = M::fma(exp2_tab<TN>(G[v], s_exp2), qv[v], acc[rg]);
                         else
                             acc[rg] = M::fma(P::ex2(G[v]), qv[v], acc[rg]);
                     }

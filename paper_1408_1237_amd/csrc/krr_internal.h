@@ -61,22 +61,31 @@ __device__ __forceinline__ double exp2_f64(double a) {
     return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
 }
 
-// 2^(x / 256) for the FP64 products (x = 256 times the exponent): with
-// n = rint(x), j = n mod 256, f = x - n (exact, |f| <= 1/2),
-// 2^(x/256) = 2^((n - j)/256) 2^(j/256) 2^(f/256), the middle factor from the
-// correctly rounded table in LDS, the last a degree-4 polynomial (relative
-// error 2e-18; exp2_table.py).  x must lie in int range (the caller clamps far
-// targets); 12 instructions against 15 for exp2_f64.
-__device__ __forceinline__ double exp2_x256(double x, const double *__restrict__ tab) {
+// 2^(x / N) for the FP64 products (x = N times the exponent, N = 256 or 2048):
+// with n = rint(x), j = n mod N, f = x - n (exact, |f| <= 1/2),
+// 2^(x/N) = 2^((n - j)/N) 2^(j/N) 2^(f/N), the middle factor from the correctly
+// rounded table in LDS, the last a polynomial of degree 4 (N = 256) or 3
+// (N = 2048; relative errors 2e-18 and 9e-18, exp2_table.py).  x must lie in
+// int range (the caller clamps far targets); 11 or 10 instructions against 15
+// for exp2_f64.
+template <int N>
+__device__ __forceinline__ double exp2_tab(double x, const double *__restrict__ tab) {
+    static_assert(N == 256 || N == 2048, "table sizes of exp2_table.h");
+    constexpr int SH = N == 256 ? 8 : 11;
     const double n = __builtin_rint(x);
     const double f = x - n;
     const int i = static_cast<int>(n);
-    double p = EXP2_POLY256[0];
-    p = __builtin_fma(p, f, EXP2_POLY256[1]);
-    p = __builtin_fma(p, f, EXP2_POLY256[2]);
-    p = __builtin_fma(p, f, EXP2_POLY256[3]);
-    p = __builtin_fma(p, f, EXP2_POLY256[4]);
-    return __builtin_amdgcn_ldexp(p * tab[i & 255], i >> 8);
+    double p;
+    if constexpr (N == 256) {
+        p = EXP2_POLY256[0];
+#pragma unroll
+        for (int k = 1; k < 5; ++k) p = __builtin_fma(p, f, EXP2_POLY256[k]);
+    } else {
+        p = EXP2_POLY2048[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) p = __builtin_fma(p, f, EXP2_POLY2048[k]);
+    }
+    return __builtin_amdgcn_ldexp(p * tab[i & (N - 1)], i >> SH);
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
