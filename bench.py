@@ -54,6 +54,7 @@ def dpad(d: int) -> int:
     return next(p for p in DIMS if p >= d)
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, index, shift, table product, ldexp
+C_EXP2_F64_TAB2048 = 10 * C_FMA             # the 2048-entry form (d <= 3): 3 FMAs
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
@@ -63,7 +64,8 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     exponentials and 16 FMAs: FP32 / BF16 for d <= 48 (split-f16 kernels)
     ceil((3D + 2) / 16) 32x32x16 f16 matrix-core operations; FP64 for d <= 16
     4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the compiled dimension; FP64
-    exponentials from the 256-entry table, 11 instructions), the same model for
+    exponentials from the 256-entry table, 11 instructions; 10 with the
+    2048-entry table at d <= 3), the same model for
     FP64 at d > 16 (staged kernel).  Otherwise (VALU kernel) per 64 pairs: d + 1
     FMAs and one exponential per lane.  Matrix-core
     and VALU issue counted one after the other (measured by the issue probe).
@@ -97,7 +99,7 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
             return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, {tag}>"
         dk = (D + 4) // 4
         if prec == "fp64":
-            cyc = 4 * dk * C_MFMA64 + 16 * (C_EXP2_F64_TAB + C_FMA)
+            cyc = 4 * dk * C_MFMA64 + 16 * ((C_EXP2_F64_TAB2048 if D <= 3 else C_EXP2_F64_TAB) + C_FMA)
         else:
             cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
