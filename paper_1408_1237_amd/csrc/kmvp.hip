@@ -101,6 +101,7 @@ struct KArgs {
     const void *slots;           // split-f16 kernel: source slot octets of the product's precision
     const void *off;
     const void *pm;  // point-major offsets (dpad > 16)
+    const double *sq;  // |o_j|^2 of the FP64 offsets (Matern matrix-core form)
     const void *q;
     const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
     void *out;
@@ -1366,7 +1367,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
 // forms or holds all d coordinates.  Wide tiles take the direct form with the
 // same coordinate split (each pair's squared distance summed over the lane
 // groups; the first group accumulates).
-template <int D, int PREC>
+template <int D, int PREC, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
@@ -1375,8 +1376,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     using V4 = typename M::V4;
     using Off = typename P::Off;
     using Q = typename P::Q;
-    constexpr bool TAB = PREC == KRR_FP64;  // table exponential, scaled operand, far clamp
-    constexpr int DK = (D + 4) / 4;   // chunks of 4 over the d + 1 coordinates
+    constexpr bool TAB = PREC == KRR_FP64;  // table exponential (Gaussian: scaled operand, far clamp)
+    // chunks of 4 over the d + 1 coordinates [o, 1] (Matern: d + 2, [o, 1, |o'|^2])
+    constexpr int DK = (D + (MAT ? 2 : 1) + 3) / 4;
+    constexpr double L2E = 1.4426950408889634074;
     constexpr int RG = 2;             // groups of 16 targets per wave
     constexpr int HB = 2;             // blocks per 256-row tile
     // sources per LDS stage (32 at d = 48: the staging registers then leave
@@ -1389,6 +1392,9 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     static_assert(D * CH % BLOCK == 0 && D % 4 == 0, "whole staging rounds");
     __shared__ T s_off[2][D][LDC];
     __shared__ __align__(32) T s_q[2][CH];
+    // Matern: ln2 q and the source constant |o'|^2 = log2(e)^2 |o|^2
+    __shared__ __align__(32) T s_q2[MAT ? 2 : 1][MAT ? CH : 4];
+    __shared__ T s_e[MAT ? 2 : 1][MAT ? CH : 1];
     // FP64: the table of 2^(j/256) (exp2_tab; the 2048-entry form measured no
     // faster here)
     constexpr int TN = 256;
@@ -1420,7 +1426,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     const int J0 = by * a.tps;
     const int J1 = min(a.ntiles, J0 + a.tps);
     const int C0 = J0 * NCH, C1 = J1 * NCH;
-    T st_o[NA], st_q = T(0);
+    T st_o[NA], st_q = T(0), st_e = T(0);
     auto stage_load = [&](int ci) {
         const int J = ci / NCH;
         const int64_t j0 = static_cast<int64_t>(J) * TILE + (ci % NCH) * CH;
@@ -1429,7 +1435,10 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             const int e = u * BLOCK + tid;
             st_o[u] = P::off(off[(e / CH) * n_pad + j0 + e % CH]);
         }
-        if (tid < CH) st_q = a.tile_r2[J] > P::wide ? static_cast<T>(P::q(q[j0 + tid])) : qw[j0 + tid];
+        if (tid < CH) {
+            st_q = (MAT || a.tile_r2[J] > P::wide) ? static_cast<T>(P::q(q[j0 + tid])) : qw[j0 + tid];
+            if constexpr (MAT) st_e = static_cast<T>(L2E * L2E * a.sq[j0 + tid]);
+        }
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
@@ -1437,7 +1446,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             const int e = u * BLOCK + tid;
             s_off[buf][e / CH][e % CH] = st_o[u];
         }
-        if (tid < CH) s_q[buf][tid] = st_q;
+        if (tid < CH) {
+            s_q[buf][tid] = st_q;
+            if constexpr (MAT) {
+                s_q2[buf][tid] = static_cast<T>(0.69314718055994530942) * st_q;  // ln 2 in T's precision
+                s_e[buf][tid] = st_e;
+            }
+        }
     };
     // this lane's coordinates 4 kc + g of t = x - a_J for target group rg, and
     // the partial |t|^2 over them
@@ -1481,13 +1496,23 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                 // FP64: operand scaled by N for exp2_tab; a target whose every
                 // exponent against the tile is <= -1100 gets -2000 (exp2 is 0 in
                 // FP64 either way), which keeps the scaled exponents in int range
-                const bool far = TAB && tt > far_t2;
-                const T sc = TAB ? T(TN) : T(1);
-                const T c = far ? T(-2000.0 * TN) : static_cast<T>(-tt - nj) * sc;
+                if constexpr (MAT) {
+                    // [-2 log2(e)^2 t, |t'|^2, 1]: the product forms (log2(e) s)^2
 #pragma unroll
-                for (int kc = 0; kc < DK; ++kc) {
-                    const int dim = 4 * kc + g;
-                    bval[rg][kc] = dim < D ? (far ? T(0) : T(2) * sc * tv[kc]) : (dim == D ? c : T(0));
+                    for (int kc = 0; kc < DK; ++kc) {
+                        const int dim = 4 * kc + g;
+                        bval[rg][kc] = dim < D ? static_cast<T>(-2.0 * L2E * L2E) * tv[kc]
+                                               : (dim == D ? static_cast<T>(L2E * L2E * tt) : (dim == D + 1 ? T(1) : T(0)));
+                    }
+                } else {
+                    const bool far = TAB && tt > far_t2;
+                    const T sc = TAB ? T(TN) : T(1);
+                    const T c = far ? T(-2000.0 * TN) : static_cast<T>(-tt - nj) * sc;
+#pragma unroll
+                    for (int kc = 0; kc < DK; ++kc) {
+                        const int dim = 4 * kc + g;
+                        bval[rg][kc] = dim < D ? (far ? T(0) : T(2) * sc * tv[kc]) : (dim == D ? c : T(0));
+                    }
                 }
             }
         }
@@ -1501,12 +1526,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                     if (4 * kc + 3 < D) {
                         av[kc] = s_off[buf][dim][st * 16 + asrc];
                     } else {
-                        // the last chunk: offsets below d, then the constant 1 and zeros
+                        // the last chunks: offsets below d, then the constant 1 (Matern:
+                        // then |o'|^2) and zeros
                         const T o = s_off[buf][min(dim, D - 1)][st * 16 + asrc];
-                        av[kc] = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
+                        T v = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
+                        if constexpr (MAT) v = M::fma(s_e[buf][st * 16 + asrc], static_cast<T>(dim == D + 1), v);
+                        av[kc] = v;
                     }
                 }
                 const V4 qv = *reinterpret_cast<const V4 *>(&s_q[buf][st * 16 + 4 * g]);
+                V4 qv2;
+                if constexpr (MAT) qv2 = *reinterpret_cast<const V4 *>(&s_q2[buf][st * 16 + 4 * g]);
 #pragma unroll
                 for (int rg = 0; rg < RG; ++rg) {
                     // FP64 at d = 32 and 64: two accumulators over alternate chunks
@@ -1525,10 +1555,22 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                     if constexpr (ACC2) G += G1;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        if constexpr (TAB)
+                        if constexpr (MAT) {
+                            // G = (log2(e) s)^2: (1 + s) e^(-s) q = 2^(-u) (q + u ln2 q), u = sqrt(G)
+                            T u, ex;
+                            if constexpr (TAB) {
+                                u = __builtin_sqrt(__builtin_fabs(G[v]));
+                                ex = exp2_tab<TN>(__builtin_fmax(-u * TN, -2000.0 * TN), s_exp2);
+                            } else {
+                                u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[v]));
+                                ex = __builtin_amdgcn_exp2f(-u);
+                            }
+                            acc[rg] = M::fma(ex, M::fma(u, qv2[v], qv[v]), acc[rg]);
+                        } else if constexpr (TAB) {
                             acc[rg] = M::fma(exp2_tab<TN>(G[v], s_exp2), qv[v], acc[rg]);
-                        else
+                        } else {
                             acc[rg] = M::fma(P::ex2(G[v]), qv[v], acc[rg]);
+                        }
                     }
                 }
             }
@@ -1550,7 +1592,14 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
                         sp = M::fma(dd, dd, sp);
                     }
                     const T ss = group_sum(sp);
-                    const T val = P::ex2(-ss) * s_q[buf][col];
+                    T val;
+                    if constexpr (MAT) {
+                        const T sd = sqrt(ss);
+                        const T ex = P::ex2(-static_cast<T>(L2E) * sd);
+                        val = M::fma(sd, ex, ex) * s_q[buf][col];
+                    } else {
+                        val = P::ex2(-ss) * s_q[buf][col];
+                    }
                     acc[rg] += g == 0 ? val : T(0);
                 }
             }
@@ -1690,6 +1739,15 @@ template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     using P = Prec<PREC>;
     if (kernel == KRR_KERNEL_MATERN32) {
+        // FP64 only: the source constant |o'|^2 is that of the FP64 offsets (with
+        // BF16 offsets in the product it would not match them)
+        if constexpr (PREC == KRR_FP64 && D % 4 == 0) {
+            if (!use_valu_kernel()) {
+                hipLaunchKernelGGL((k_kmvp_mgw<D, PREC, true>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s,
+                                   a);
+                return hipGetLastError();
+            }
+        }
         if constexpr (D > 16 && D <= 48 && PREC != KRR_FP64) {
             if (!use_valu_kernel()) {
                 hipLaunchKernelGGL((k_kmvp_mhw<D, PREC, true>), dim3(a.nrowblocks * a.splits), dim3(BLOCK), 0, s, a);
@@ -1735,7 +1793,7 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     }
     if constexpr ((D > 16 && PREC == KRR_FP64) || D > 48) {
         if (!use_valu_kernel()) {
-            hipLaunchKernelGGL((k_kmvp_mgw<D, PREC>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s, a);
+            hipLaunchKernelGGL((k_kmvp_mgw<D, PREC, false>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s, a);
             return hipGetLastError();
         }
     }
@@ -1792,6 +1850,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.tile_nj = C.tile_nj;
     a.tile_far = C.tile_far;
     a.tile_far64 = C.tile_far64;
+    a.sq = C.sq64;
     a.slots = prec == KRR_FP32 ? C.slot32 : prec == KRR_BF16 ? C.slot16 : nullptr;
     a.q = q;
     a.qw = sc.qw;

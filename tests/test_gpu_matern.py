@@ -177,3 +177,39 @@ def test_matern_matrix_core_large_d_far_and_wide_tiles(monkeypatch, d):
     assert _rel(y, want) <= 1e-4
     rows = np.arange(1700, 2200)
     assert _rel(y[rows], want[rows]) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,d", [("fp64", 4), ("fp64", 8), ("fp64", 12), ("fp64", 16), ("fp64", 24),
+                                    ("fp64", 41), ("fp64", 64)])
+def test_matern_staged_matrix_core_matches_valu_kernel(monkeypatch, prec, d):
+    # FP64 Matern products at compiled dimensions that are multiples of 4 form
+    # (log2(e) s)^2 on the FP64 matrix cores from [o, 1, |o'|^2] .
+    # [-2 log2(e)^2 t, |t'|^2, 1]; they meet the oracle bar and agree with the
+    # VALU form
+    n = 1300
+    x = workloads.random_points(180 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(181 + d, n)
+    h = 0.8 * np.sqrt(d)
+    monkeypatch.setenv("KRR_KMVP_VALU", "0")
+    a = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.setenv("KRR_KMVP_VALU", "1")
+    b = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.delenv("KRR_KMVP_VALU")
+    want = oracle.matern_mvp(x, h, q, shift=0.03)
+    assert _rel(a, want) <= TOL[prec] and _rel(b, want) <= TOL[prec]
+    assert _rel(a, b) <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("d", [8, 24])
+def test_matern_fp64_matrix_core_far_and_wide_tiles(d):
+    # FP64 Matern products on the three-cluster set (folded, far and wide tiles)
+    rng = np.random.default_rng(27 + d)
+    a = rng.normal(0.0, 0.3, size=(700, d))
+    b = rng.normal(0.0, 0.3, size=(600, d))
+    b[:, 0] += 150.0
+    s = rng.uniform(-3000.0, 3000.0, size=(400, d))
+    s[:, 1] += 5000.0
+    x = np.ascontiguousarray(np.concatenate([a, b, s]))
+    q = workloads.random_vector(28 + d, x.shape[0])
+    y = _mvp(x, 1.0, q, 0.01, "fp64")
+    assert _rel(y, oracle.matern_mvp(x, 1.0, q, shift=0.01)) <= TOL["fp64"]
