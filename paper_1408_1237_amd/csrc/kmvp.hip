@@ -1388,8 +1388,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     constexpr int CH = D == 48 ? 32 : 64;
     constexpr int NCH = TILE / CH;
     constexpr int LDC = CH + 2;       // padded LDS row
-    constexpr int NA = D * CH / BLOCK;
-    static_assert(D * CH % BLOCK == 0 && D % 4 == 0, "whole staging rounds");
+    constexpr int NA = (D * CH + BLOCK - 1) / BLOCK;  // staged offsets per thread
     __shared__ T s_off[2][D][LDC];
     __shared__ __align__(32) T s_q[2][CH];
     // Matern: ln2 q and the source constant |o'|^2 = log2(e)^2 |o|^2
@@ -1433,7 +1432,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = u * BLOCK + tid;
-            st_o[u] = P::off(off[(e / CH) * n_pad + j0 + e % CH]);
+            if (D * CH % BLOCK == 0 || e < D * CH) st_o[u] = P::off(off[(e / CH) * n_pad + j0 + e % CH]);
         }
         if (tid < CH) {
             st_q = (MAT || a.tile_r2[J] > P::wide) ? static_cast<T>(P::q(q[j0 + tid])) : qw[j0 + tid];
@@ -1444,7 +1443,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = u * BLOCK + tid;
-            s_off[buf][e / CH][e % CH] = st_o[u];
+            if (D * CH % BLOCK == 0 || e < D * CH) s_off[buf][e / CH][e % CH] = st_o[u];
         }
         if (tid < CH) {
             s_q[buf][tid] = st_q;
@@ -1740,8 +1739,9 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     using P = Prec<PREC>;
     if (kernel == KRR_KERNEL_MATERN32) {
         // FP64 only: the source constant |o'|^2 is that of the FP64 offsets (with
-        // BF16 offsets in the product it would not match them)
-        if constexpr (PREC == KRR_FP64 && D % 4 == 0) {
+        // BF16 offsets in the product it would not match them); at d = 1 the
+        // VALU form measured faster
+        if constexpr (PREC == KRR_FP64 && D >= 2) {
             if (!use_valu_kernel()) {
                 hipLaunchKernelGGL((k_kmvp_mgw<D, PREC, true>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s,
                                    a);

@@ -179,11 +179,10 @@ def test_matern_matrix_core_large_d_far_and_wide_tiles(monkeypatch, d):
     assert _rel(y[rows], want[rows]) <= 1e-6
 
 
-@pytest.mark.parametrize("prec,d", [("fp64", 4), ("fp64", 8), ("fp64", 12), ("fp64", 16), ("fp64", 24),
-                                    ("fp64", 41), ("fp64", 64)])
+@pytest.mark.parametrize("prec,d", [("fp64", 1), ("fp64", 2), ("fp64", 3), ("fp64", 4), ("fp64", 6), ("fp64", 8),
+                                    ("fp64", 12), ("fp64", 16), ("fp64", 24), ("fp64", 41), ("fp64", 64)])
 def test_matern_staged_matrix_core_matches_valu_kernel(monkeypatch, prec, d):
-    # FP64 Matern products at compiled dimensions that are multiples of 4 form
-    # (log2(e) s)^2 on the FP64 matrix cores from [o, 1, |o'|^2] .
+    # FP64 Matern products form (log2(e) s)^2 on the FP64 matrix cores from [o, 1, |o'|^2] .
     # [-2 log2(e)^2 t, |t'|^2, 1]; they meet the oracle bar and agree with the
     # VALU form
     n = 1300
@@ -200,7 +199,7 @@ def test_matern_staged_matrix_core_matches_valu_kernel(monkeypatch, prec, d):
     assert _rel(a, b) <= (1e-12 if prec == "fp64" else 1e-5)
 
 
-@pytest.mark.parametrize("d", [8, 24])
+@pytest.mark.parametrize("d", [2, 8, 24])
 def test_matern_fp64_matrix_core_far_and_wide_tiles(d):
     # FP64 Matern products on the three-cluster set (folded, far and wide tiles)
     rng = np.random.default_rng(27 + d)
