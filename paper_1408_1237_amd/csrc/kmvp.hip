@@ -1354,13 +1354,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- matrix-core exponent, d = 24 .. 64
+// ---------------------------------------------------------------- staged matrix-core exponent
 //
-// The product of k_kmvp_mg (the exponent [2t, c] . [o, 1] on the matrix cores;
-// in FP64 with the operand scaled by 256, the table exponential and the far
-// clamp) for the large compiled dimensions: FP64 above d = 16, FP32 / BF16
-// above d = 48 (where the split-f16 operands no longer fit).  The sources of a column tile pass
-// through LDS 64 at a time (double buffered), a wave owns 2 groups of 16
+// The Gaussian product of k_kmvp_mg (the exponent [2t, c] . [o, 1] on the
+// matrix cores; in FP64 with the operand scaled by 256, the table exponential
+// and the far clamp) for the large compiled dimensions: FP64 above d = 16,
+// FP32 / BF16 above d = 48 (where the split-f16 operands no longer fit).  With
+// MAT, the FP64 Matern-3/2 product at every compiled dimension from 2: the
+// contraction [o, 1, |o'|^2] . [-2 log2(e)^2 t, |t'|^2, 1] gives
+// G = (log2(e) s)^2, and each pair adds 2^(-u) (q + u ln2 q), u = sqrt(G).
+// The sources of a column tile pass through LDS 64 (d = 48: 32) at a time
+// (double buffered), a wave owns 2 groups of 16
 // targets (a block half a row tile), and the target operand is formed per
 // column tile by each lane for its own coordinates 4 kc + g only (lane group
 // g), with |t|^2 summed over the four lane groups by two exchanges: no lane
