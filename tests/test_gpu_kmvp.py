@@ -46,7 +46,7 @@ def test_kmvp_sizes(prec, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("d", [1, 2, 4, 5, 8, 12, 16, 17, 33, 64])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 7, 8, 9, 12, 13, 16, 17, 20, 25, 31, 33, 40, 47, 49, 56, 64])
 def test_kmvp_dims(prec, d):
     n = 700
     x = workloads.random_points(300 + d, n, d, 1.0, kind="normal")

@@ -212,3 +212,15 @@ def test_matern_fp64_matrix_core_far_and_wide_tiles(d):
     q = workloads.random_vector(28 + d, x.shape[0])
     y = _mvp(x, 1.0, q, 0.01, "fp64")
     assert _rel(y, oracle.matern_mvp(x, 1.0, q, shift=0.01)) <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d", [5, 7, 13, 20, 31, 47, 49, 56])
+def test_matern_product_dims(prec, d):
+    # dimensions between the compiled ones (padded) through every Matern kernel
+    n = 700
+    x = workloads.random_points(190 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(191 + d, n)
+    h = 0.7 * np.sqrt(d)
+    bar = TOL[prec] if (prec != "bf16" or d <= 8) else 2e-2
+    assert _rel(_mvp(x, h, q, 0.05, prec), oracle.matern_mvp(x, h, q, shift=0.05)) <= bar
