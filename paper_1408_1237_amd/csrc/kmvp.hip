@@ -1440,7 +1440,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
         }
         if (tid < CH) {
             st_q = (MAT || a.tile_r2[J] > P::wide) ? static_cast<T>(P::q(q[j0 + tid])) : qw[j0 + tid];
-            if constexpr (MAT) st_e = static_cast<T>(L2E * L2E * a.sq[j0 + tid]);
+            if constexpr (MAT && TAB) st_e = static_cast<T>(L2E * L2E * a.sq[j0 + tid]);
         }
     };
     auto stage_store = [&](int buf) {
@@ -1453,7 +1453,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
             s_q[buf][tid] = st_q;
             if constexpr (MAT) {
                 s_q2[buf][tid] = static_cast<T>(0.69314718055994530942) * st_q;  // ln 2 in T's precision
-                s_e[buf][tid] = st_e;
+                if constexpr (TAB) s_e[buf][tid] = st_e;
             }
         }
     };
@@ -1489,6 +1489,17 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
         if (ci + 1 < C1) stage_load(ci + 1);
         const int J = ci / NCH;
         const bool wide = a.tile_r2[J] > P::wide;
+        if constexpr (MAT && !TAB) {
+            // FP32 / BF16: |o'|^2 of the offsets as staged (rounded), so that the
+            // source constant matches the product's offsets
+            if (tid < CH) {
+                T so = T(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) so = M::fma(s_off[buf][k][tid], s_off[buf][k][tid], so);
+                s_e[buf][tid] = static_cast<T>(L2E * L2E) * so;
+            }
+            __syncthreads();
+        }
         if (!wide && ci % NCH == 0) {
             const double nj = a.tile_nj[J];
             const double far_t2 = static_cast<double>(a.tile_far64[J]);
@@ -1742,10 +1753,9 @@ template <int D, int PREC>
 static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     using P = Prec<PREC>;
     if (kernel == KRR_KERNEL_MATERN32) {
-        // FP64 only: the source constant |o'|^2 is that of the FP64 offsets (with
-        // BF16 offsets in the product it would not match them); at d = 1 the
-        // VALU form measured faster
-        if constexpr (PREC == KRR_FP64 && D >= 2) {
+        // FP64 at d >= 2 (at d = 1 the VALU form measured faster), FP32 / BF16
+        // above d = 48 (below, the split-f16 forms)
+        if constexpr ((PREC == KRR_FP64 && D >= 2) || D > 48) {
             if (!use_valu_kernel()) {
                 hipLaunchKernelGGL((k_kmvp_mgw<D, PREC, true>), dim3(a.nrowblocks * 2 * a.splits), dim3(BLOCK), 0, s,
                                    a);
