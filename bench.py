@@ -185,8 +185,19 @@ def read_traffic(name: str):
         return None
 
 
-def cpu_baseline(p, target_s: float = 12.0) -> dict:
-    """FP64 oracle kernel sum on a bounded sample of rows (OpenMP over rows)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, target_s: float = 10.0) -> dict:
+    """FP64 oracle kernel sum on a bounded sample of rows (OpenMP over rows), on
+    all host threads and on one."""
     import numpy as np
 
     import oracle
@@ -194,18 +205,64 @@ def cpu_baseline(p, target_s: float = 12.0) -> dict:
 
     q = workloads.random_vector(7, p.n)
     rng = np.random.default_rng(0)
-    rows = rng.choice(p.n, 64, replace=False)
+
+    def rate(budget_s: float):
+        rows = rng.choice(p.n, 64, replace=False)
+        t0 = time.perf_counter()
+        oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+        dt = time.perf_counter() - t0
+        nrows = int(min(p.n, max(64, 64 * budget_s / max(dt, 1e-3))))
+        rows = rng.choice(p.n, nrows, replace=False)
+        t0 = time.perf_counter()
+        oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
+        dt = time.perf_counter() - t0
+        return float(nrows) * p.n / dt, nrows, dt
+
+    threads = oracle.num_threads()
+    v_all, nr_all, dt_all = rate(target_s)
+    oracle.set_num_threads(1)
+    try:
+        v_one, nr_one, dt_one = rate(target_s / 2)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": v_all, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nr_all} rows x {p.n} sources of (K_hat + gamma I) q, FP64 on-the-fly loop, {dt_all:.1f} s "
+                      f"on {threads} threads",
+            "value_1thread": v_one,
+            "sample_1thread": f"{nr_one} rows x {p.n} sources, {dt_one:.1f} s on 1 thread",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def plain_small_block(api, torch) -> dict:
+    """The small plain case (N = 2000, d = 2, sigma = 0.1, gamma = 1e-2): the
+    oracle's FP64 CG and Cholesky solve on the host against the GPU's plain FP64
+    CG and mixed FGMRES (delta = 0.1, 10 inner iterations), each to 1e-6."""
+    import oracle
+    from paper_1408_1237_amd import workloads
+
+    p = workloads.plain_small()
+    x = torch.from_numpy(p.x).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    out = {"workload": "N=2000 d=2 x~U[0,1]^2 sigma=0.1 gamma=1e-2", "cpu_threads": oracle.num_threads()}
     t0 = time.perf_counter()
-    oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
-    dt = time.perf_counter() - t0
-    nrows = int(min(p.n, max(64, 64 * target_s / max(dt, 1e-3))))
-    rows = rng.choice(p.n, nrows, replace=False)
+    wd = oracle.direct_solve(p.x, p.sigma, p.gamma, p.y)
+    out["cpu_cholesky_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
-    dt = time.perf_counter() - t0
-    pairs = float(nrows) * p.n
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nrows} rows x {p.n} sources of (K_hat + gamma I) q, FP64 on-the-fly loop, {dt:.1f} s"}
+    _, st, it, rel, _ = oracle.cg(p.x, p.sigma, p.gamma, p.y, 20000, p.tol)
+    out["cpu_cg64"] = {"time_s": time.perf_counter() - t0, "iters": it, "relres_true": rel}
+    for label, mode, kw in (("gpu_cg64", "cg64", dict(max_outer=20000)),
+                            ("gpu_fgmres", "fgmres", dict(inner_prec="fp32", inner_maxit=p.inner_maxit,
+                                                          inner_tol=0.0, delta=p.delta, restart_m=100, gs="cgs2"))):
+        api.krr_solve([x], [p.sigma], [p.gamma], [y], mode=mode, **kw)  # tunes the products
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (w,), (i,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode=mode, **kw)
+        torch.cuda.synchronize()
+        wn = w.cpu().numpy()
+        out[label] = {"time_s": time.perf_counter() - t0, "iters": i["outer_iters"], "inner_iters": i["inner_iters"],
+                      "relres_true": oracle.true_relres(p.x, p.sigma, p.gamma, p.y, wn),
+                      "rel_err_vs_cholesky": float(((wn - wd) ** 2).sum() ** 0.5 / (wd ** 2).sum() ** 0.5)}
+    return out
 
 
 def kernel_only(api, native, workloads, torch, p, x, reps: int, prec: str = "fp32") -> int:
@@ -233,7 +290,9 @@ def kernel_only(api, native, workloads, torch, p, x, reps: int, prec: str = "fp3
 
 
 def product_rates(api, native, torch, x, sigma, shift, n, reps, precs=("fp64", "fp32", "bf16")) -> dict:
-    """Average product-kernel launch time and pair rate per precision (HIP events)."""
+    """Average product-kernel launch time and pair rate per precision (HIP
+    events), with the share of pairs in far tile pairs the kernels skipped
+    (exact zeros) and the rate over the pairs they evaluated."""
     out = {}
     for prec in precs:
         dt = torch.float64 if prec == "fp64" else torch.float32
@@ -245,56 +304,78 @@ def product_rates(api, native, torch, x, sigma, shift, n, reps, precs=("fp64", "
                 api.kmvp_gauss(x, sigma, q, shift=shift, prec=prec)
             torch.cuda.synchronize()
         st = prof.stats[prec]
-        out[prec] = {"gpair_s": round(st["pairs"] / (st["total_ms"] * 1e-3) / 1e9, 1),
-                     "avg_launch_ms": round(st["total_ms"] / max(st["launches"], 1), 4), "launches": st["launches"]}
+        sec = st["total_ms"] * 1e-3
+        out[prec] = {"gpair_s": round(st["pairs"] / sec / 1e9, 1),
+                     "avg_launch_ms": round(st["total_ms"] / max(st["launches"], 1), 4), "launches": st["launches"],
+                     "skipped_frac": round(st["pairs_skipped"] / max(st["pairs"], 1.0), 4),
+                     "evaluated_gpair_s": round((st["pairs"] - st["pairs_skipped"]) / sec / 1e9, 1)}
     return out
 
 
 def workload_clustered(args, api, native, workloads, torch) -> dict:
-    """N = 1e6, d = 2 clustered points, BF16-input inner products: product rates
-    per precision and a bounded number of outer steps (the full solve and plain
-    FP64 CG take far longer than a benchmark run; the residual reached is reported)."""
+    """N = 1e6, d = 2 clustered points (50-component mixture, sigma = 1,
+    gamma = 1e-4): product rates per precision, then the mixed solve to a true
+    relative residual of 1e-6 (FP64 outer products, BF16-input inner CG on
+    K_hat + 1e-3 I, inner tolerance 1e-5 and at most 10 inner iterations, or
+    --inner-maxit), and plain FP64 CG given the same wall time (the residual it
+    reaches is reported)."""
     p = workloads.clustered_large()
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
     torch.manual_seed(7)
+    os.environ.setdefault("KRR_PROGRESS", "25")
     rates = product_rates(api, native, torch, x, p.sigma, p.delta, p.n, 3)
     log(f"clustered products: {rates}")
-    budget = args.max_outer or 8
-    opts = dict(inner_prec="bf16", inner_maxit=p.inner_maxit, inner_tol=p.inner_tol, delta=p.delta, restart_m=100,
-                tol=p.tol, max_outer=budget, gs="cgs2")
+    inner_maxit = args.inner_maxit or p.inner_maxit
+    opts = dict(inner_prec="bf16", inner_maxit=inner_maxit, inner_tol=p.inner_tol, delta=p.delta, restart_m=200,
+                tol=p.tol, max_outer=args.max_outer or 3000, gs="cgs2")
+    torch.cuda.synchronize()
+    with native.profile(max_launches=200_000) as prof:
+        t0 = time.perf_counter()
+        w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, **opts)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+    log(f"fgmres bf16 inner: status {info['status']}, {info['outer_iters']} outer, {info['inner_iters']} inner, "
+        f"relres {info['relres_true']:.3e}, {tf:.2f} s")
+    st = prof.stats
+    # plain FP64 CG with the same wall time: iterations from the FP64 product time
+    t_it = rates["fp64"]["avg_launch_ms"] * 1e-3 + 1e-4
+    cg_iters = max(16, int(tf / t_it) // 16 * 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, **opts)
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    log(f"fgmres bf16 inner, {info['outer_iters']} outer steps: relres {info['relres_true']:.3e}, {tf:.2f} s")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol,
-                                 max_outer=budget * (p.inner_maxit + 1), cg_check=16)
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=cg_iters,
+                                 cg_check=16)
     torch.cuda.synchronize()
     tc = time.perf_counter() - t0
-    log(f"cg64 at the same product budget, {ic['outer_iters']} iterations: relres {ic['relres_true']:.3e}, {tc:.2f} s")
+    log(f"cg64 given {cg_iters} iterations (the same wall time): status {ic['status']}, "
+        f"relres {ic['relres_true']:.3e}, {tc:.2f} s")
     peak_pairs, peak_rule, kname = product_peak(p.d, prec="bf16")
-    ach = rates["bf16"]["gpair_s"]
-    return {"metric": METRIC, "value": ach * 1e9, "unit": "pairs/s", "n_gpus": 1, "dtype": "bf16-input/f32",
-            "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
-            "config": {"workload": "clustered N=1e6 d=2 50-component mixture sigma=1 gamma=1e-4; BF16-input inner "
-                                   "products (10 its, tol 1e-5) on K_hat+1e-3 I", "n": p.n, "d": p.d},
+    ach = rates["bf16"]["evaluated_gpair_s"]
+    return {"metric": METRIC, "value": rates["bf16"]["gpair_s"] * 1e9, "unit": "pairs/s", "n_gpus": 1,
+            "dtype": "bf16-input/f32 + f64", "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
+            "config": {"workload": "clustered N=1e6 d=2 50-component mixture sigma=1 gamma=1e-4; FGMRES FP64 outer, "
+                                   f"BF16-input inner CG ({inner_maxit} its, tol 1e-5) on K_hat+1e-3 I, tol 1e-6",
+                       "n": p.n, "d": p.d},
             "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak_pairs / 1e9, 1), "unit": "Gpair/s",
                          "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None, "kernel": kname,
-                         "peak_rule": peak_rule},
+                         "peak_rule": peak_rule + "; achieved over the evaluated (not skipped) pairs"},
             "products": rates,
-            "fgmres_bounded": {"outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
-                               "relres_true": info["relres_true"], "time_s": tf,
-                               "s_per_outer_step": tf / max(info["outer_iters"], 1)},
-            "cg64_same_budget": {"iters": ic["outer_iters"], "relres_true": ic["relres_true"], "time_s": tc}}
+            "fgmres": {"status": info["status"], "outer_iters": info["outer_iters"],
+                       "inner_iters": info["inner_iters"], "mvp64": info["mvp64"], "mvp16": info["mvp16"],
+                       "relres_true": info["relres_true"], "time_to_solution_s": tf,
+                       "t_prep_ms": info["t_prep_ms"], "t_inner_ms": info["t_inner_ms"],
+                       "t_outer_ms": info["t_outer_ms"], "t_ortho_ms": info["t_ortho_ms"],
+                       "product_ms": {k: round(st[k]["total_ms"], 1) for k in ("fp64", "bf16")},
+                       "skipped_frac": {k: round(st[k]["pairs_skipped"] / max(st[k]["pairs"], 1.0), 4)
+                                        for k in ("fp64", "bf16")}},
+            "cg64_same_wall_time": {"iters": ic["outer_iters"], "relres_true": ic["relres_true"], "time_s": tc,
+                                    "status": ic["status"]}}
 
 
 def workload_batched(args, api, native, workloads, torch) -> dict:
-    """64 systems (N_k ~ U{1000..50000}, d in {4, 8}) x 16 right-hand sides, one
-    batched FGMRES solve; the multi-RHS kernel rate on the largest system."""
+    """64 systems (N_k ~ U{1000..50000}, d in {4, 8}) x 16 right-hand sides: the
+    batched mixed FGMRES and the batched plain FP64 CG, each to 1e-6 on every
+    column; the multi-RHS kernel rate on the largest system."""
     import numpy as np
 
     # the library prints a progress line every 50 outer steps (a long solve is one call)
@@ -310,8 +391,18 @@ def workload_batched(args, api, native, workloads, torch) -> dict:
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
     worst = max(i["relres_true"] for i in infos)
-    outer = infos[0]["outer_iters"]
-    log(f"batched: {len(infos)} columns, {outer} outer steps, worst relres {worst:.3e}, {tb:.2f} s")
+    steps = infos[0]["batch_steps"]
+    log(f"batched fgmres: {len(infos)} columns, {steps} outer steps, worst relres {worst:.3e}, {tb:.2f} s, "
+        f"tile {infos[0]['batch_tiles']}, prep {infos[0]['t_prep_ms']:.0f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wc, ic = api.krr_solve(xs, [q.sigma for q in probs], [q.gamma for q in probs], Ys, mode="cg64",
+                           max_outer=args.max_outer or 20000, cg_check=16)
+    torch.cuda.synchronize()
+    tcg = time.perf_counter() - t0
+    worst_cg = max(i["relres_true"] for i in ic)
+    log(f"batched cg64: {ic[0]['batch_steps']} iterations (max column {max(i['outer_iters'] for i in ic)}), "
+        f"worst relres {worst_cg:.3e}, {tcg:.2f} s")
     big = max(range(len(probs)), key=lambda k: probs[k].n)
     q = probs[big]
     rates = {}
@@ -334,7 +425,12 @@ def workload_batched(args, api, native, workloads, torch) -> dict:
             "dtype": "f32+f64", "data": "synthetic", "higher_is_better": False, "vs_baseline": None,
             "config": {"workload": "batched 64 systems N_k~U{1000..50000} d in {4,8} x 16 RHS; FGMRES(30), 10 FP32 "
                                    "inner CG on K_hat+0.1 I, tol 1e-6 per column"},
-            "time_to_solution_s": tb, "outer_iters": outer, "worst_relres_true": worst,
+            "time_to_solution_s": tb, "outer_steps": steps, "worst_relres_true": worst,
+            "max_column_outer": max(i["outer_iters"] for i in infos),
+            "batch_tiles": infos[0]["batch_tiles"], "t_prep_ms": infos[0]["t_prep_ms"],
+            "cg64": {"time_to_solution_s": tcg, "iterations": ic[0]["batch_steps"],
+                     "max_column_iters": max(i["outer_iters"] for i in ic), "worst_relres_true": worst_cg},
+            "speedup_fgmres_vs_cg64": tcg / tb,
             "roofline": {"bound": "mfma", "achieved": ach, "peak": round(peak_pairs / 1e9, 1),
                          "unit": "Gpair-RHS/s", "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None,
                          "kernel": kname, "peak_rule": peak_rule},
@@ -558,8 +654,9 @@ def main() -> int:
     ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "highd", "sweep"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
-                    help="outer-step budget of the secondary workloads (clustered: default 8; others: "
-                         "default to convergence)")
+                    help="outer-step budget of the secondary workloads (default: to convergence)")
+    ap.add_argument("--inner-maxit", type=int, default=0,
+                    help="inner CG iterations of the clustered workload (default: its 10)")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
                     help="only K FP32 products on the workload's points plus one 256 MiB copy "
                          "(the short run used for rocprofv3 counter passes)")
@@ -631,8 +728,17 @@ def main() -> int:
     ach64 = f64["pairs"] / max(f64["total_ms"], 1e-9) / 1e6
     traffic = read_traffic("kmvp_fp32_d3_kriging_counters.txt")
     probe = api.probe_issue_rates()
+    # the same rates against the published vector peaks, at the algorithmic 3d + 1
+    # FLOP per pair (d subtractions, d multiply-adds, the accumulate; the exp2 not
+    # counted): FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s
+    flops_pair = 3 * p.d + 1
+    flop_frac = achieved * 1e9 * flops_pair / 157.3e12
+    flop_frac64 = ach64 * 1e9 * flops_pair / 78.6e12
     roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gpair/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
+                "flop_frac": round(flop_frac, 4),
+                "flop_rule": f"{flops_pair} FLOP per pair (3d + 1) x pairs/s / 157.3e12 (FP32 vector peak)",
+                "fp64_flop_frac": round(flop_frac64, 4),
                 "kernel": kname, "launches": f32["launches"],
                 "avg_launch_ms": round(f32["total_ms"] / max(f32["launches"], 1), 4),
                 "peak_rule": peak_rule,
@@ -682,7 +788,11 @@ def main() -> int:
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p)
-        log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} pairs/s on {out['cpu_baseline']['cores']} threads")
+        cb = out["cpu_baseline"]
+        log(f"cpu oracle: {cb['value']:.3e} pairs/s on {cb['cores']} threads, {cb['value_1thread']:.3e} on 1 "
+            f"({cb['cpu_model']})")
+        out["plain_small"] = plain_small_block(api, torch)
+        log(f"plain small: {out['plain_small']}")
 
     print(json.dumps(out), flush=True)
     return 0

@@ -106,7 +106,8 @@ typedef struct {
     int32_t inner_maxit; /* inner CG iterations cap (>= 1); default 10 */
     double inner_tol;    /* inner stop at ||r|| / ||v|| <= inner_tol; < 0: 10 tol; 0: run to the cap */
     int32_t gs;          /* krr_gs; default KRR_GS_MGS */
-    int32_t cg_check;    /* plain CG: iterations between host checks of the stop flag; default 16 */
+    int32_t cg_check;    /* plain CG: iterations between host checks of the stop flag; several systems or
+                            columns (krr_solve): also the outer steps between checks; default 16 */
     int32_t kernel;      /* krr_kernel of K_hat; default KRR_KERNEL_GAUSS */
 } krr_fgmres_opts;
 
@@ -129,6 +130,18 @@ typedef struct {
      * converges, so the ratio is a lower estimate of the condition number. */
     double lambda_min_est;
     double lambda_max_est;
+    /* Where the time went (ms): point preparation (scaling, sort, tiles; for
+     * several systems also the autotuning of the batched products), and for
+     * fgmres_solve and single-column krr_solve calls in FGMRES mode the inner
+     * solves, the outer FP64 products and the orthogonalisation with the Givens
+     * update, from HIP events on the call's stream (0 where not measured). */
+    double t_prep_ms;
+    double t_inner_ms;
+    double t_outer_ms;
+    double t_ortho_ms;
+    int32_t batch_steps;   /* several systems or columns: outer steps (CG: iterations) the batch ran, else 0 */
+    int32_t batch_tiles;   /* several systems or columns: column tiles per work item of the batched
+                              products (autotuned once per process; first dimension class), else 0 */
 } krr_info;
 
 /* Solver modes of krr_solve. */
@@ -164,7 +177,14 @@ const char *krr_status_string(int status);
 size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob, int32_t nrhs,
                           const krr_fgmres_opts *opts);
 
-/* y = K_hat q + shift q  (section 3.1: the weighted kernel summation, here with
+/* Tuning: the first product call for a (precision, kernel, dimension, tile
+ * count) shape times the candidate launch shapes on `stream` (about 20 products,
+ * waiting for their events) and keeps the fastest for the process (and in the
+ * file KRR_TUNE_CACHE names); that first call is therefore synchronous.  Calls
+ * on a stream that is being captured into a HIP graph use the default shape
+ * instead and never tune.  Results do not depend on the launch shape.
+ *
+ * y = K_hat q + shift q  (section 3.1: the weighted kernel summation, here with
  * the regularisation shift of eq. RegKernel; shift = gamma gives K, shift =
  * delta gives M).  prec KRR_FP64: q, y are double[n]; KRR_FP32 / KRR_BF16:
  * float[n].  The product is computed on the fly; K_hat is never formed.  y may
@@ -233,15 +253,30 @@ int fgmres_solve(const krr_points *pts /* host */, double sigma, double gamma, c
                  krr_stream_t stream);
 
 /* Solve nprob independent systems, each with nrhs right-hand sides:
- * (K_hat_k + gamma_k I) W_k = Y_k.  probs, sigma, gamma, Y, W, ldy are host
+ * (K_hat_k + gamma_k I) W_k = Y_k.  The paper solves one kriging system per week
+ * of data, each on its own points (kriging experiment, section 6.3), and the GPR
+ * posterior variance needs one solve with K_hat + gamma I per test point
+ * (section 2.1, the variance after eq. GPR_mean): the systems share nothing but
+ * the method, and every (system, column) pair is solved as in fgmres_solve.  probs, sigma, gamma, Y, W, ldy are host
  * arrays of length nprob; Y[k] and W[k] are device pointers to column-major
  * n_k x nrhs blocks with leading dimension ldy[k] >= n_k (ldy may be NULL:
  * ld = n_k).  W[k] is overwritten (x0 = 0).  mode is a krr_mode.  infos (host,
  * may be NULL) has nprob*nrhs entries, entry k*nrhs + r for column r of system k.
  * With nprob == 1 and nrhs == 1 this is fgmres_solve / the plain CG.  Several
- * systems or columns run together: their kernel products are batched into
- * multi-column launches and every (system, column) pair stops on its own.
- * Returns the worst status over all pairs. */
+ * systems or columns of the Gaussian kernel run together in modes FGMRES,
+ * GMRES and CG64: their kernel products are batched into multi-column launches
+ * (one per dimension class, its work-item tile autotuned on the first call for
+ * that shape), every (system, column) pair keeps its own solver state and
+ * stops on its own, each outer step of the flexible solver is one HIP graph
+ * replay, and the host reads a small summary every opts->cg_check steps (the
+ * mixed solve) or iterations (CG64).  FGMRES with KRR_FP64 inner products, FCG
+ * and the Matern kernel solve the pairs one after the other.  A right-hand-side
+ * column with a non-finite value is not solved (its W column is zero, its info
+ * status KRR_ENONFINITE) while the other columns are; the call then returns
+ * KRR_ENONFINITE.  A column that breaks down (non-finite or non-positive
+ * curvature during the iteration) is retired with KRR_BREAKDOWN and keeps its
+ * last finite iterate; the others continue.  Otherwise returns the worst status
+ * over all pairs. */
 int krr_solve(const krr_points *probs /* host */, int32_t nprob, const double *sigma /* host */,
               const double *gamma /* host */, int32_t nrhs, const double *const *Y /* host array */,
               const int64_t *ldy /* host, may be NULL */, double *const *W /* host array */,
@@ -285,13 +320,17 @@ int krr_lanczos_extremes(const double *alpha /* host, k */, const double *beta /
  * around the product kernel (the main O(N^2) kernel, not the O(N) partial-sum
  * kernel).  krr_profile_end() waits for the recorded events and returns, per
  * product precision, the launch count, the summed kernel time and the summed
- * algorithmic pair count (n_targets x n_sources, padding excluded).  At most
+ * algorithmic pair count (n_targets x n_sources, padding excluded), of which
+ * pairs_skipped were in far tile pairs (exactly zero, not evaluated).  At most
  * max_launches launches are recorded (later ones are counted in `dropped`).
- * Host-side state only; no device memory is allocated.  Not thread-safe. */
+ * No device memory is allocated (the skipped-pair counters are a static device
+ * array); begin and end synchronise the device.  Not thread-safe. */
 typedef struct {
     int64_t launches;
     double total_ms;
     double pairs;
+    double pairs_skipped; /* of `pairs`, those in tile pairs the product kernels skipped because every
+                             kernel value there is exactly zero in the product's precision (far tiles) */
 } krr_profile_entry;
 
 typedef struct {

@@ -172,12 +172,15 @@ def fgmres_solve(x: torch.Tensor, sigma: float, gamma: float, b: torch.Tensor, x
     return w, info.as_dict()
 
 
-def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | None = None, **opts):
+def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | None = None,
+              return_status: bool = False, **opts):
     """Solve (K_hat_k + gamma_k I) W_k = Y_k for every system k.
 
     xs: list of (n_k, d_k) float64 CUDA tensors; Ys: list of (n_k,) or (n_k, nrhs)
     column-major float64 tensors (same nrhs for all).  Returns (list of W_k, list of
-    info dicts ordered system-major).
+    info dicts ordered system-major); with return_status also the call's status,
+    and a KRR_ENONFINITE status (a non-finite right-hand-side column, the others
+    solved) is returned instead of raised.
     """
     modes = {"fgmres": N.KRR_MODE_FGMRES, "cg64": N.KRR_MODE_CG64, "gmres": N.KRR_MODE_GMRES,
              "fcg": N.KRR_MODE_FCG}
@@ -202,8 +205,11 @@ def krr_solve(xs, sigmas, gammas, Ys, mode: str = "fgmres", ws: torch.Tensor | N
         ws = workspace(need, xs[0].device)
     rc = N.load().krr_solve(pts, k, sig, gam, nrhs, yp, ld, wp, modes[mode], ctypes.byref(o), infos,
                             ws.data_ptr(), ws.numel(), _stream())
-    N.check(rc, "krr_solve")
+    if not (return_status and rc == N.KRR_ENONFINITE):
+        N.check(rc, "krr_solve")
     Ws = [W.reshape(-1) if Y.dim() == 1 else W for W, Y in zip(Ws, Ys)]
+    if return_status:
+        return Ws, [i.as_dict() for i in infos], rc
     return Ws, [i.as_dict() for i in infos]
 
 

@@ -1,5 +1,6 @@
 // C ABI entry points (include/krr.h): argument validation, workspace layout,
 // point preparation and dispatch to the kernels and solver drivers.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -246,7 +247,10 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
             size_t mx = 0;
             for (int k = 0; k < nprob; ++k) {
                 if (probs[k].n < 1 || probs[k].d < 1 || probs[k].d > KRR_MAX_DIM) return 0;
-                const size_t b = layout_bytes(probs[k].n, probs[k].d, o, K_FGMRES);
+                // every mode's single solve: the flexible solvers' basis, or the
+                // plain CG's coefficient history (2 max_outer values)
+                const size_t b = std::max(layout_bytes(probs[k].n, probs[k].d, o, K_FGMRES),
+                                          layout_bytes(probs[k].n, probs[k].d, o, K_CG64));
                 if (b > mx) mx = b;
             }
             if (nprob > 1 || nrhs > 1) {
@@ -259,8 +263,10 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
     }
 }
 
+// tune: time the launch shapes on the first product of a shape (kmvp_tune);
+// false keeps the cached or default shape (no events, no synchronisation).
 static int kmvp_single(const krr_points *pts, int kernel, double sigma, double shift, int32_t prec, const void *q,
-                       void *y, void *ws, size_t ws_bytes, krr_stream_t stream) {
+                       void *y, void *ws, size_t ws_bytes, krr_stream_t stream, bool tune = true) {
     int rc;
     if ((rc = check_points(pts)) || (rc = check_sigma(sigma)) || (rc = check_prec(prec))) return rc;
     if (!is_fin(shift) || q == nullptr || y == nullptr || q == y) return KRR_EINVAL;
@@ -274,7 +280,7 @@ static int kmvp_single(const krr_points *pts, int kernel, double sigma, double s
     KRR_HIP_STATUS(prepare_points(L.P, pts->x, sigma, L.temp, L.temp_bytes, s, kernel));
     if (prec == KRR_FP64) {
         KRR_HIP_STATUS((gather_sorted<double, double>(L.P, static_cast<const double *>(q), static_cast<double *>(L.q), s)));
-        KRR_HIP_STATUS(kmvp_tune(L.P, prec, L.q, L.y, L.W.ksc, s));
+        if (tune) KRR_HIP_STATUS(kmvp_tune(L.P, prec, L.q, L.y, L.W.ksc, s));
         KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, L.q, L.y, L.W.ksc, nullptr, s));
         KRR_HIP_STATUS((scatter_sorted<double, double>(L.P, static_cast<double *>(L.y), static_cast<double *>(y), s)));
     } else {
@@ -285,7 +291,7 @@ static int kmvp_single(const krr_points *pts, int kernel, double sigma, double s
             KRR_HIP_STATUS(to_bf16(qs, L.q16, L.P.n_pad, s));
             qin = L.q16;
         }
-        KRR_HIP_STATUS(kmvp_tune(L.P, prec, qin, L.y, L.W.ksc, s));
+        if (tune) KRR_HIP_STATUS(kmvp_tune(L.P, prec, qin, L.y, L.W.ksc, s));
         KRR_HIP_STATUS(kmvp_sorted(L.P, prec, shift, qin, L.y, L.W.ksc, nullptr, s));
         KRR_HIP_STATUS((scatter_sorted<float, float>(L.P, static_cast<float *>(L.y), static_cast<float *>(y), s)));
     }
@@ -301,6 +307,17 @@ int kmvp_matern(const krr_points *pts, double h, double shift, int32_t prec, con
                 size_t ws_bytes, krr_stream_t stream) {
     return kmvp_single(pts, KRR_KERNEL_MATERN32, h, shift, prec, q, y, ws, ws_bytes, stream);
 }
+
+}  // extern "C"
+
+// The allocation-free product's body (noalloc.hip): kmvp_gauss on a given
+// scratch, without tuning.
+int kmvp_gauss_on_scratch(const krr_points *pts, double sigma, double shift, int32_t prec, const void *q, void *y,
+                          void *scratch, size_t scratch_bytes, krr_stream_t stream) {
+    return kmvp_single(pts, KRR_KERNEL_GAUSS, sigma, shift, prec, q, y, scratch, scratch_bytes, stream, false);
+}
+
+extern "C" {
 
 int kmvp_gauss_multi(const krr_points *pts, double sigma, double shift, int32_t prec, int32_t nrhs, const void *Q,
                      int64_t ldq, void *Y, int64_t ldy, void *ws, size_t ws_bytes, krr_stream_t stream) {
@@ -422,6 +439,7 @@ static int solve_one(const krr_points *pts, double sigma, double gamma, const do
     KRR_HIP_STATUS(hipMemcpyAsync(&flags, L.P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     KRR_HIP_STATUS(hipStreamSynchronize(s));
     if (flags & 1) return KRR_ENONFINITE;
+    const double t_prep = now_ms() - t0;
     KRR_HIP_STATUS((gather_sorted<double, double>(L.P, b, L.W.b, s)));
     if (!x0_zero) KRR_HIP_STATUS((gather_sorted<double, double>(L.P, x, L.W.x, s)));
     else KRR_HIP_STATUS(fill_d(L.W.x, L.P.n_pad, 0.0, s));
@@ -441,6 +459,7 @@ static int solve_one(const krr_points *pts, double sigma, double gamma, const do
     KRR_HIP_STATUS((scatter_sorted<double, double>(L.P, L.W.x, x, s)));
     KRR_HIP_STATUS(hipStreamSynchronize(s));
     tmp.t_total_ms = now_ms() - t0;
+    tmp.t_prep_ms = t_prep;
     tmp.status = rc;
     if (info) *info = tmp;
     return rc;
@@ -480,15 +499,23 @@ int krr_solve(const krr_points *probs, int32_t nprob, const double *sigma, const
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     SolverOpts o0;
     resolve_opts(opts, gamma[0], o0);
-    if ((mode == KRR_MODE_FGMRES || mode == KRR_MODE_GMRES) && (nprob > 1 || nrhs > 1) &&
-        o0.kernel == KRR_KERNEL_GAUSS) {
-        // all systems and columns advance together (one product launch per system
-        // per step for all columns, per-column solver state on the device)
+    const bool several = nprob > 1 || nrhs > 1;
+    const bool fp64_inner = mode == KRR_MODE_FGMRES && o0.inner == KRR_INNER_CG && o0.inner_prec == KRR_FP64;
+    if ((mode == KRR_MODE_FGMRES || mode == KRR_MODE_GMRES) && several && o0.kernel == KRR_KERNEL_GAUSS &&
+        !fp64_inner) {
+        // all systems and columns advance together (one product launch per
+        // dimension class per step for all columns, per-column solver state on
+        // the device)
         SolverOpts o;
         resolve_opts(opts, gamma[0], o);
         o.delta = (opts && opts->delta >= 0) ? opts->delta : -1.0;  // per system: 10 gamma_k
         if (mode == KRR_MODE_GMRES) o.inner = KRR_INNER_NONE;
         return batched_fgmres(probs, nprob, sigma, gamma, nrhs, Y, ldy, W, o, infos, ws, ws_bytes, s);
+    }
+    if (mode == KRR_MODE_CG64 && several && o0.kernel == KRR_KERNEL_GAUSS) {
+        SolverOpts o;
+        resolve_opts(opts, gamma[0], o);
+        return batched_cg64(probs, nprob, sigma, gamma, nrhs, Y, ldy, W, o, infos, ws, ws_bytes, s);
     }
     int worst = KRR_OK;
     for (int k = 0; k < nprob; ++k) {

@@ -67,10 +67,10 @@ struct Prec<KRR_FP32> {
 template <>
 struct Prec<KRR_BF16> {
     using T = float;
-    using Off = uint16_t;
+    using Off = float;  // FP32 values, BF16-rounded on compact tiles (prep)
     using Q = uint16_t;
     static constexpr double wide = WIDE_R2_FP32;
-    static __device__ __forceinline__ T off(Off v) { return bf16_to_f32(v); }
+    static __device__ __forceinline__ T off(Off v) { return v; }
     static __device__ __forceinline__ T q(Q v) { return bf16_to_f32(v); }
     static __device__ __forceinline__ T ex2(T a) { return __builtin_amdgcn_exp2f(a); }
 };
@@ -108,7 +108,30 @@ struct KArgs {
     double shift;    // square products only
     int square;
     const int *active;
+    const double *row_r2;             // targets: squared radius of each row tile (far-tile skipping)
+    unsigned long long *skip_count;   // when profiling: += row-tile rows x column tiles skipped as far
 };
+
+// A row tile (anchor aI, radius rI) and a column tile (anchor aJ) whose every
+// pair is beyond the column tile's far threshold far_t2 on |t|^2 = |x_i - aJ|^2:
+// |x_i - aJ| >= |aI - aJ| - rI for every target, so when (|aI - aJ| - rI)^2
+// exceeds far_t2 (with a 1e-6 margin for the rounding of both sides) each
+// target of the row tile would take the far clamp against the whole column
+// tile, whose pairs then contribute exactly zero (exp2 underflows in the
+// product's precision; also on wide tiles, whose direct exponents are then
+// <= -200, or -1100 in FP64).  The products skip such tile pairs.
+template <int D>
+__device__ __forceinline__ bool tiles_far(const double (&aI)[D], double rI, const double *__restrict__ aJ,
+                                          float far_t2) {
+    double dd = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double v = aI[k] - aJ[k];
+        dd = __builtin_fma(v, v, dd);
+    }
+    const double gap = sqrt(dd) - rI;
+    return gap > 0.0 && gap * gap > 1.000001 * static_cast<double>(far_t2) + 1e-6;
+}
 
 template <int D, int PREC>
 // The source arrays and the output are separate noalias kernel arguments: the
@@ -591,14 +614,48 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
         for (int k = 0; k < D; ++k) s_off[buf][k][tid] = st_o[k];
         s_q[buf][tid] = st_q;
     };
-    if (J0 < J1) {
-        stage_load(J0);
+    // close partial-sum group grp (fixed tile ranges: the result does not
+    // depend on how groups are dealt to blocks, nor on which tiles are skipped)
+    auto close_group = [&](int grp) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            T sum = acc[rg];
+            sum += __shfl_xor(sum, 16, WAVE);
+            sum += __shfl_xor(sum, 32, WAVE);
+            acc[rg] = T(0);
+            const int64_t i = row0 + rg * 16 + r16;
+            if (g == 0) {
+                if (a.ngroups == 1) {
+                    if (i < a.n_rows && a.square) sum += static_cast<T>(a.shift) * P::q(q[i]);
+                    out[i] = (i < a.n_rows) ? sum : T(0);
+                } else {
+                    out[static_cast<int64_t>(grp) * a.n_pad_rows + i] = sum;
+                }
+            }
+        }
+    };
+    // only the column tiles not far from this row tile (tiles_far; FP64: the
+    // -1100 threshold) are staged and computed; groups without one get zero sums
+    const double rI = a.row_r2 != nullptr ? sqrt(a.row_r2[bx]) : INFINITY;  // null: no skipping
+    const float *__restrict__ far_t = TAB ? a.tile_far64 : a.tile_far;
+    auto next_live = [&](int J) {
+        while (J < J1 && tiles_far<D>(aI, rI, a.anchor + static_cast<int64_t>(J) * D, far_t[J])) ++J;
+        return J;
+    };
+    const int gt = a.gtiles, g_last = (J1 - 1) / gt;
+    int J = next_live(J0);
+    int skipped = J - J0;
+    for (int grp = J0 / gt; grp < (J < J1 ? J / gt : g_last + 1); ++grp) close_group(grp);
+    if (J < J1) {
+        stage_load(J);
         stage_store(0);
     }
     __syncthreads();
-    for (int J = J0; J < J1; ++J) {
-        const int buf = (J - J0) & 1;
-        if (J + 1 < J1) stage_load(J + 1);
+    int buf = 0;
+    while (J < J1) {
+        const int Jn = next_live(J + 1);
+        skipped += Jn - J - 1;
+        if (Jn < J1) stage_load(Jn);
         const double r2 = a.tile_r2[J];
         const double nj = a.tile_nj[J];
         // t = x - a_J of target group rg's lane (below d = 16 not kept over the
@@ -749,40 +806,26 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
                 }
             }
         }
-        // close a partial-sum group (fixed tile ranges: the result does not
-        // depend on how groups are dealt to blocks)
-        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
-#pragma unroll
-            for (int rg = 0; rg < RG; ++rg) {
-                T sum = acc[rg];
-                sum += __shfl_xor(sum, 16, WAVE);
-                sum += __shfl_xor(sum, 32, WAVE);
-                acc[rg] = T(0);
-                const int64_t i = row0 + rg * 16 + r16;
-                if (g == 0) {
-                    if (a.ngroups == 1) {
-                        if (i < a.n_rows && a.square) sum += static_cast<T>(a.shift) * P::q(q[i]);
-                        out[i] = (i < a.n_rows) ? sum : T(0);
-                    } else {
-                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
-                    }
-                }
-            }
-        }
-        if (J + 1 < J1) stage_store(buf ^ 1);
+        const int gend = Jn < J1 ? Jn / gt : g_last + 1;
+        for (int grp = J / gt; grp < gend; ++grp) close_group(grp);
+        if (Jn < J1) stage_store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
+        J = Jn;
     }
+    if (a.skip_count != nullptr && tid == 0 && skipped > 0)
+        atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * (BLOCK / HB));
 }
 
 // ---------------------------------------------------------------- split-f16 matrix-core exponent
 //
 // FP32 and BF16 products with the folded exponent formed by the f16 matrix
 // cores.  Every FP32 operand v is split as v = hi + lo, hi = f16(v),
-// lo = f16(v - hi): |v - hi - lo| <= 2^-24 |v| (f16 subnormals are kept), the
-// accuracy of the FP32 operand itself.  The exponent of the form above becomes
-// an inner product over 3d + 2 slots,
+// lo = f16(v - hi): |v - hi - lo| <= 2^-22 |v| (f16 subnormals are kept), four
+// times the rounding of the FP32 operand itself.  The exponent of the form
+// above becomes an inner product over 3d + 2 slots,
 //   arg_ij = sum_k ( o_hi 2t_hi + o_hi 2t_lo + o_lo 2t_hi )_jk,ik + c_hi + c_lo,
-// dropping only the lo * lo terms (below 2^-24 of each product); the products
+// dropping only the lo * lo terms (at most 2^-22 of each product); the products
 // are exact and accumulate in FP32 as in the FP32 matrix-core form.  One
 // v_mfma_f32_32x32x16_f16 covers 32 sources x 32 targets x 16 slots.  Its lane
 // layout: A (sources x slots) lane l holds source l % 32 and slots
@@ -907,14 +950,46 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
         s_q[buf][tid] = st_q;
         if constexpr (MAT) s_q2[buf][tid] = LN2_F * st_q;
     };
-    if (J0 < J1) {
-        stage_load(J0);
+    // close partial-sum group grp (fixed tile ranges: the result does not
+    // depend on how groups are dealt to blocks, nor on which tiles are skipped)
+    auto close_group = [&](int grp) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+            float sum = acc[rg];
+            sum += __shfl_xor(sum, 32, WAVE);
+            acc[rg] = 0.f;
+            const int64_t i = row0 + rg * 32 + r32;
+            if (h == 0) {
+                if (a.ngroups == 1) {
+                    if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
+                    out[i] = (i < a.n_rows) ? sum : 0.f;
+                } else {
+                    out[static_cast<int64_t>(grp) * a.n_pad_rows + i] = sum;
+                }
+            }
+        }
+    };
+    // only the column tiles not far from this row tile (tiles_far) are staged
+    // and computed; groups without one get zero sums
+    const double rI = a.row_r2 != nullptr ? sqrt(a.row_r2[bx]) : INFINITY;  // null: no skipping
+    auto next_live = [&](int J) {
+        while (J < J1 && tiles_far<D>(aI, rI, a.anchor + static_cast<int64_t>(J) * D, a.tile_far[J])) ++J;
+        return J;
+    };
+    const int gt = a.gtiles, g_last = (J1 - 1) / gt;
+    int J = next_live(J0);
+    int skipped = J - J0;
+    for (int grp = J0 / gt; grp < (J < J1 ? J / gt : g_last + 1); ++grp) close_group(grp);
+    if (J < J1) {
+        stage_load(J);
         stage_store(0);
     }
     __syncthreads();
-    for (int J = J0; J < J1; ++J) {
-        const int buf = (J - J0) & 1;
-        if (J + 1 < J1) stage_load(J + 1);
+    int buf = 0;
+    while (J < J1) {
+        const int Jn = next_live(J + 1);
+        skipped += Jn - J - 1;
+        if (Jn < J1) stage_load(Jn);
         const double r2 = a.tile_r2[J];
         const float njf = static_cast<float>(a.tile_nj[J]);  // a small integer
         const float far_t2 = a.tile_far[J];
@@ -1045,28 +1120,15 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
                 }
             }
         }
-        // close a partial-sum group (fixed tile ranges: the result does not
-        // depend on how groups are dealt to blocks)
-        if ((J + 1) % a.gtiles == 0 || J + 1 == J1) {
-#pragma unroll
-            for (int rg = 0; rg < RG; ++rg) {
-                float sum = acc[rg];
-                sum += __shfl_xor(sum, 32, WAVE);
-                acc[rg] = 0.f;
-                const int64_t i = row0 + rg * 32 + r32;
-                if (h == 0) {
-                    if (a.ngroups == 1) {
-                        if (i < a.n_rows && a.square) sum += static_cast<float>(a.shift) * P::q(q[i]);
-                        out[i] = (i < a.n_rows) ? sum : 0.f;
-                    } else {
-                        out[static_cast<int64_t>(J / a.gtiles) * a.n_pad_rows + i] = sum;
-                    }
-                }
-            }
-        }
-        if (J + 1 < J1) stage_store(buf ^ 1);
+        const int gend = Jn < J1 ? Jn / gt : g_last + 1;
+        for (int grp = J / gt; grp < gend; ++grp) close_group(grp);
+        if (Jn < J1) stage_store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
+        J = Jn;
     }
+    if (a.skip_count != nullptr && tid == 0 && skipped > 0)
+        atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * BLOCK);
 }
 
 // qw_j = q_j * w_j (the per-source factor of the folded form), once per product.
@@ -1709,6 +1771,22 @@ void tune_cache_append(const TuneKey &k, int splits) {
 }
 }  // namespace
 
+bool tune_lookup(int key, int dpad, int ntiles, int *value) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tuned.find(TuneKey{key, dpad, ntiles});
+    if (it == g_tuned.end()) return false;
+    *value = it->second;
+    return true;
+}
+
+void tune_store(int key, int dpad, int ntiles, int value) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    g_tuned[TuneKey{key, dpad, ntiles}] = value;
+    tune_cache_append(TuneKey{key, dpad, ntiles}, value);
+}
+
 KmvpPlan kmvp_plan(const Prepared &P, int prec) {
     // KRR_KMVP_SPLITS=k forces k column splits (used to check that results do
     // not depend on the launch shape)
@@ -1743,6 +1821,12 @@ KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
 static bool use_valu_kernel() {
     const char *v = std::getenv("KRR_KMVP_VALU");
     return v && v[0] == '1';
+}
+// KRR_NO_TILE_SKIP=1 computes far tile pairs too (their terms are exactly zero;
+// used to check that skipping them changes nothing)
+static bool use_tile_skip() {
+    const char *v = std::getenv("KRR_NO_TILE_SKIP");
+    return !(v && v[0] == '1');
 }
 static bool use_fp32_matrix_kernel() {
     const char *v = std::getenv("KRR_KMVP_MG32");
@@ -1871,6 +1955,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.shift = square ? shift : 0.0;
     a.square = square ? 1 : 0;
     a.active = active;
+    a.row_r2 = use_tile_skip() ? R.tile_r2 : nullptr;
+    a.skip_count = nullptr;
     a.out = a.ngroups > 1 ? sc.parts : y;
     const void *w = prec == KRR_FP64 ? static_cast<const void *>(C.w64)
                     : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
@@ -1886,7 +1972,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     }
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool timed =
-        timed_slot && profile_slot(prec, static_cast<double>(R.n) * static_cast<double>(C.n), &ev0, &ev1);
+        timed_slot && profile_slot(prec, static_cast<double>(R.n) * static_cast<double>(C.n), &ev0, &ev1,
+                                   static_cast<double>(R.n_pad) * static_cast<double>(C.n_pad), &a.skip_count);
     if (timed) KRR_HIP(hipEventRecord(ev0, s));
     hipError_t e;
     switch (prec) {
@@ -1903,9 +1990,9 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
             e = launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
             break;
         case KRR_BF16:
-            a.off = C.off16;
-            a.pm = C.pm16;
-            a.row_off = R.off16;
+            a.off = C.offb;
+            a.pm = C.pmb;
+            a.row_off = R.offb;
             e = launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
             break;
         default: return hipErrorInvalidValue;
@@ -1963,6 +2050,11 @@ KmvpScratch carve_kmvp_cross_scratch(Carver &cv, const Prepared &T, const Prepar
 // Time every candidate split count on this point set and keep the fastest.
 // q must be a valid input vector of the precision; y is overwritten.
 hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s) {
+    // a stream being captured into a graph gets the default shape: timing it
+    // would synchronise inside the capture
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return hipSuccess;
     const TuneKey key{prec + 16 * P.kernel, P.dpad, P.ntiles};  // kernel type in the key
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2015,12 +2107,29 @@ struct ProfileState {
     bool on = false;
     std::vector<hipEvent_t> ev;  // 2 per record
     std::vector<int> prec;
-    std::vector<double> pairs;
+    std::vector<double> pairs, pad_pairs;
     size_t used = 0;
     int64_t dropped = 0;
 };
 ProfileState g_prof;
 }  // namespace
+
+// Row-tile rows x column tiles that the far-tile skipping products left out,
+// per product precision, while profiling (one 64-bit counter per precision on
+// each device; the kernels add to it through its address).
+__device__ unsigned long long g_skipped[3];
+
+static unsigned long long *skip_counter(int prec) {
+    static unsigned long long *addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_skipped)) != hipSuccess) return nullptr;
+        addr[dev] = static_cast<unsigned long long *>(p);
+    }
+    return addr[dev] + prec;
+}
 
 namespace {
 thread_local bool g_prof_suspended = false;
@@ -2037,7 +2146,8 @@ int progress_every() {
     return every;
 }
 
-bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop) {
+bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop, double pad_pairs,
+                  unsigned long long **skip) {
     if (!g_prof.on || g_prof_suspended) return false;
     if (g_prof.used >= g_prof.prec.size()) {
         ++g_prof.dropped;
@@ -2046,8 +2156,10 @@ bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop) {
     const size_t k = g_prof.used++;
     g_prof.prec[k] = prec;
     g_prof.pairs[k] = pairs;
+    g_prof.pad_pairs[k] = pad_pairs > 0.0 ? pad_pairs : pairs;
     *start = g_prof.ev[2 * k];
     *stop = g_prof.ev[2 * k + 1];
+    if (skip) *skip = skip_counter(prec);
     return true;
 }
 
@@ -2062,8 +2174,13 @@ int profile_begin(int max_launches) {
     }
     g_prof.prec.assign(want, 0);
     g_prof.pairs.assign(want, 0.0);
+    g_prof.pad_pairs.assign(want, 0.0);
     g_prof.used = 0;
     g_prof.dropped = 0;
+    const unsigned long long zero[3] = {0, 0, 0};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_skipped), zero, sizeof(zero), 0, hipMemcpyHostToDevice) != hipSuccess)
+        return KRR_EHIP;
     g_prof.on = true;
     return KRR_OK;
 }
@@ -2073,6 +2190,7 @@ int profile_end(krr_profile_stats *out) {
     g_prof.on = false;
     krr_profile_stats st;
     std::memset(&st, 0, sizeof(st));
+    double pad[3] = {0.0, 0.0, 0.0};
     for (size_t k = 0; k < g_prof.used; ++k) {
         if (hipEventSynchronize(g_prof.ev[2 * k + 1]) != hipSuccess) return KRR_EHIP;
         float ms = 0.0f;
@@ -2081,7 +2199,15 @@ int profile_end(krr_profile_stats *out) {
         e.launches += 1;
         e.total_ms += ms;
         e.pairs += g_prof.pairs[k];
+        pad[g_prof.prec[k]] += g_prof.pad_pairs[k];
     }
+    unsigned long long skipped[3] = {0, 0, 0};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpyFromSymbol(skipped, HIP_SYMBOL(g_skipped), sizeof(skipped), 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return KRR_EHIP;
+    for (int p = 0; p < 3; ++p)
+        if (pad[p] > 0.0)  // skipped tile pairs, in the algorithmic (unpadded) pair count
+            st.prec[p].pairs_skipped = st.prec[p].pairs * (static_cast<double>(skipped[p]) * TILE / pad[p]);
     st.dropped = g_prof.dropped;
     if (out) *out = st;
     return KRR_OK;

@@ -44,8 +44,6 @@ struct ColGate {
     const int *b = nullptr;
 };
 
-constexpr int BATCH_TPS = 32;  // column tiles per work item of a batched product
-
 // A batched product over the systems of one compiled dimension and one
 // precision: device arrays of systems and work items, sizes for the grids.
 struct BatchedProduct {
@@ -57,9 +55,13 @@ struct BatchedProduct {
     double pairs = 0.0;     // sum over systems of n^2
 };
 
-size_t batched_product_scratch_bytes(const Prepared &P, int nrhs);
+// Scratch of one system of a batched product whose work items cover at least
+// min_tps column tiles each (partial sums of every column chunk, and Q').
+size_t batched_product_scratch_bytes(const Prepared &P, int nrhs, int min_tps);
+// The system's product arguments with tps column tiles per work item (tps >=
+// the min_tps its scratch was sized for).
 void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, int64_t base, double shift_in,
-               double shift_out);
+               double shift_out, int tps);
 // Y = K_hat Q + shift Q for every system of bp (inner != 0: shift_in), on the
 // live columns of gate.
 hipError_t batched_product(const BatchedProduct &bp, const void *Qall, void *Yall, int inner, ColGate gate,

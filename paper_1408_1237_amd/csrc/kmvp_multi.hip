@@ -57,8 +57,8 @@ struct MP<KRR_FP32> {
 };
 template <>
 struct MP<KRR_BF16> : MP<KRR_FP32> {
-    using Off = uint16_t;
-    static __device__ __forceinline__ float off(Off v) { return bf16_to_f32(v); }
+    using Off = float;  // FP32 values, BF16-rounded on compact tiles (prep)
+    static __device__ __forceinline__ float off(Off v) { return v; }
 };
 
 }  // namespace krr
@@ -677,15 +677,15 @@ __global__ __launch_bounds__(BLOCK) void k_multi_finish_b(const MSysB *__restric
     Y[idx] = s + static_cast<T>(inner ? m.shift_in : m.shift_out) * qv;
 }
 
-size_t batched_product_scratch_bytes(const Prepared &P, int nrhs) {
+size_t batched_product_scratch_bytes(const Prepared &P, int nrhs, int min_tps) {
     const int nrb = (nrhs + 15) / 16;
-    const int splits = (P.ntiles + BATCH_TPS - 1) / BATCH_TPS;
+    const int splits = (P.ntiles + min_tps - 1) / min_tps;
     return align_up(static_cast<size_t>(splits) * nrb * P.n_pad * 16 * 8, 256) +
            align_up(static_cast<size_t>(nrb) * P.n_pad * 16 * 8, 256);
 }
 
 void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, int64_t base, double shift_in,
-               double shift_out) {
+               double shift_out, int tps) {
     Carver cv(scratch);
     const int nrb = (nrhs + 15) / 16;
     MArgs &a = m.a;
@@ -693,7 +693,7 @@ void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, i
     a.n_pad = P.n_pad;
     a.ntiles = P.ntiles;
     a.nrowblocks = P.ntiles;
-    a.tps = P.ntiles < BATCH_TPS ? P.ntiles : BATCH_TPS;
+    a.tps = P.ntiles < tps ? P.ntiles : tps;
     a.splits = (P.ntiles + a.tps - 1) / a.tps;
     a.nrb = nrb;
     a.anchor = P.anchor;
@@ -705,7 +705,7 @@ void fill_msys(MSysB &m, const Prepared &P, int prec, int nrhs, void *scratch, i
     a.qwt = cv.take<double>(static_cast<size_t>(nrb) * P.n_pad * 16);
     a.off = prec == KRR_FP64 ? static_cast<const void *>(P.off64)
             : prec == KRR_FP32 ? static_cast<const void *>(P.off32)
-                               : static_cast<const void *>(P.off16);
+                               : static_cast<const void *>(P.offb);
     m.w = prec == KRR_FP64 ? static_cast<const void *>(P.w64)
           : prec == KRR_FP32 ? static_cast<const void *>(P.w32)
                              : static_cast<const void *>(P.w16);
@@ -846,7 +846,7 @@ static hipError_t multi_run(const Prepared &P, int nrhs, double shift, const int
                                        : static_cast<const void *>(P.w16);
     a.off = PREC == KRR_FP64 ? static_cast<const void *>(P.off64)
             : PREC == KRR_FP32 ? static_cast<const void *>(P.off32)
-                               : static_cast<const void *>(P.off16);
+                               : static_cast<const void *>(P.offb);
     const int64_t tot_pre = P.n_pad * 16 * nrb;
     hipLaunchKernelGGL(k_multi_prescale<PREC>, dim3((tot_pre + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.n_pad, nrhs,
                        nrb, perm, Q, ldq, w, P.tile_r2, qwt);

@@ -35,8 +35,20 @@ constexpr int BLOCK = 256;
 constexpr int VEC_BLOCKS = 512; // blocks of the vector (reduction) kernels
 
 // Above these squared tile radii (scaled units) a tile uses the direct form.
-constexpr double WIDE_R2_FP32 = 64.0;
+// The folded exponent adds terms of size up to about 2 R^2, so its absolute
+// error grows with R^2: the FP32 / BF16 matrix-core form splits its operands to
+// 2^-22 (split16.h), which at R^2 = 40 leaves per-pair exponent errors of at
+// most about 2e-5 on the pairs that matter.
+constexpr double WIDE_R2_FP32 = 40.0;
 constexpr double WIDE_R2_FP64 = 512.0;
+// BF16 products round a tile's offsets to BF16 only on compact tiles: BF16
+// keeps 8 significant bits, so an offset of length up to R moves by up to
+// 2^-8 R, and a pair at scaled distance r changes its exponent by up to
+// 2 r 2^-8 R.  At R^2 <= 1 (R <= 1) that is at most about 0.5% of the kernel
+// value for the pairs within one scaled unit, which dominate the sums (beside
+// BF16's own rounding of q, 2^-8 per entry); tiles of larger radius keep the
+// FP32 offsets.
+constexpr double COMPACT_R2_BF16 = 1.0;
 
 // 2^a in FP64 for a <= 1023 (device).  a = n + f with n = rint(a) and
 // |f| <= 1/2 (the subtraction is exact); 2^f by a near-minimax polynomial of
@@ -126,7 +138,7 @@ struct Prepared {
     float *tile_far64 = nullptr; // the same for exponents <= -1100 (FP64 Gaussian product)
     double *off64 = nullptr;  // dpad * n_pad
     float *off32 = nullptr;
-    uint16_t *off16 = nullptr;
+    float *offb = nullptr;    // offsets of BF16 products: BF16-rounded on compact tiles (COMPACT_R2_BF16), else FP32
     double *w64 = nullptr;    // n_pad
     float *w32 = nullptr;
     float *w16 = nullptr;
@@ -136,7 +148,7 @@ struct Prepared {
     // reads a group of sources with scalar loads from one base address
     double *pm64 = nullptr;
     float *pm32 = nullptr;
-    uint16_t *pm16 = nullptr;
+    float *pmb = nullptr;
     // split-f16 source slot vectors of the FP32 and BF16 offsets (split16.h):
     // 2 split_chunks(dpad) octets per point, octet-major ([octet][n_pad]), for dpad <= 48
     void *slot32 = nullptr;
@@ -206,6 +218,11 @@ hipError_t kmvp_grad_run(const Prepared &P, int prec, double sigma, double gamma
 // Autotuner: time the candidate column splits for (prec, d, N) on this point
 // set once per process (and KRR_TUNE_CACHE file) and keep the fastest.
 hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const KmvpScratch &sc, hipStream_t s);
+// The autotuner's cache (in-process, and the KRR_TUNE_CACHE file): an integer
+// per (key, dpad, ntiles); single products use key = prec + 16 x kernel, the
+// batched products 64 + prec (ntiles: the class's tiles x RHS blocks).
+bool tune_lookup(int key, int dpad, int ntiles, int *value);
+void tune_store(int key, int dpad, int ntiles, int value);
 
 // Device-resident scalars of one CG solve (T = float for the inner
 // preconditioner solve, double for the plain solver).
@@ -237,7 +254,10 @@ struct FgmresScalars {
 // Launch timing (krr_profile_begin / krr_profile_end): when enabled, returns
 // the event pair to record around one product kernel of `pairs` pair
 // evaluations in precision prec, or false when disabled / the pool is full.
-bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop);
+// pad_pairs: the padded pair count of the launch; skip (optional): receives the
+// device counter the far-tile skipping kernels add their skipped rows x tiles to.
+bool profile_slot(int prec, double pairs, hipEvent_t *start, hipEvent_t *stop, double pad_pairs = 0.0,
+                  unsigned long long **skip = nullptr);
 int profile_begin(int max_launches);
 void profile_suspend(bool on);  // while on, profile_slot hands out no events
 int profile_end(krr_profile_stats *out);

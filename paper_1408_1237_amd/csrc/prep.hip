@@ -34,7 +34,7 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     P.tile_far64 = cv.take<float>(P.ntiles);
     P.off64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.off32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
-    P.off16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
+    P.offb = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
     P.w64 = cv.take<double>(P.n_pad);
     P.w32 = cv.take<float>(P.n_pad);
     P.w16 = cv.take<float>(P.n_pad);
@@ -42,7 +42,7 @@ Prepared carve_prepared(Carver &cv, int64_t n, int d) {
     if (P.dpad > 16) {
         P.pm64 = cv.take<double>(static_cast<size_t>(P.dpad) * P.n_pad);
         P.pm32 = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
-        P.pm16 = cv.take<uint16_t>(static_cast<size_t>(P.dpad) * P.n_pad);
+        P.pmb = cv.take<float>(static_cast<size_t>(P.dpad) * P.n_pad);
     }
     const int oct = 2 * split_chunks(P.dpad);
     if (oct > 0) {
@@ -153,37 +153,67 @@ __global__ __launch_bounds__(BLOCK) void k_morton(const double *__restrict__ x, 
 }
 
 // One block per tile: anchor, offsets, radius, normaliser and weights.
+//
+// The anchor is the coordinate-wise (lower) median of the tile's points: on a
+// compact tile it sits near the centre, and on a tile that a space-filling
+// order fills with a dense group plus a few far points it stays inside the
+// group, whose offsets then stay short and keep their absolute precision when
+// rounded to FP32 or BF16 (with the bounding-box centre the group's offsets
+// would be as long as the tile, and its pairs' distances would carry that
+// rounding).
 __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, int64_t n, int d, int dpad,
                                                 double scale, const int32_t *__restrict__ sorted_idx,
                                                 Prepared P, int matern) {
     __shared__ double lds[TILE / WAVE];
+    __shared__ double vals[TILE];
+    __shared__ double med;
     const int J = blockIdx.x;
     const int64_t j = static_cast<int64_t>(J) * TILE + threadIdx.x;
     const bool real = j < n;
     const int32_t idx = real ? sorted_idx[j] : -1;
+    const int64_t t0 = static_cast<int64_t>(J) * TILE;
+    const int nreal = static_cast<int>(n - t0 < TILE ? n - t0 : TILE);  // real points come first in a tile
     P.perm[j] = idx;
     double sq64 = 0.0, sq32 = 0.0, sq16 = 0.0;
     for (int t = 0; t < dpad; ++t) {
         const double v = (real && t < d) ? x[static_cast<int64_t>(idx) * d + t] * scale : 0.0;
-        const double lo = block_reduce(real ? v : INFINITY, MinOp(), lds);
-        const double hi = block_reduce(real ? v : -INFINITY, MaxOp(), lds);
-        const double a = (t < d) ? 0.5 * (lo + hi) : 0.0;
+        // rank of this point's coordinate among the tile's real points (ties by
+        // position); the point of rank (nreal - 1) / 2 is the median
+        vals[threadIdx.x] = v;
+        if (threadIdx.x == 0) med = v;  // replaced below (kept only if a non-finite value breaks the ranks)
+        __syncthreads();
+        if (real) {
+            int rank = 0;
+            for (int k = 0; k < nreal; ++k) {
+                const double u = vals[k];
+                rank += (u < v || (u == v && k < static_cast<int>(threadIdx.x))) ? 1 : 0;
+            }
+            if (rank == (nreal - 1) / 2) med = v;
+        }
+        __syncthreads();
+        const double a = (t < d) ? med : 0.0;
+        __syncthreads();  // vals and med are rewritten for the next coordinate
         const double o = real ? v - a : 0.0;
         const float o32 = static_cast<float>(o);
-        const uint16_t o16 = f32_to_bf16_rne(o32);
-        const double o16d = static_cast<double>(bf16_to_f32(o16));
         if (threadIdx.x == 0) P.anchor[static_cast<size_t>(J) * dpad + t] = a;
         P.off64[t * P.n_pad + j] = o;
         P.off32[t * P.n_pad + j] = o32;
-        P.off16[t * P.n_pad + j] = o16;
         if (P.pm64 != nullptr) {
             P.pm64[j * dpad + t] = o;
             P.pm32[j * dpad + t] = o32;
-            P.pm16[j * dpad + t] = o16;
         }
         sq64 += o * o;
         sq32 += static_cast<double>(o32) * static_cast<double>(o32);
-        sq16 += o16d * o16d;
+    }
+    // offsets of the BF16 products: rounded to BF16 on a compact tile (this
+    // thread reads back the FP32 offsets it wrote)
+    const bool compact = block_reduce(sq64, MaxOp(), lds) <= COMPACT_R2_BF16;
+    for (int t = 0; t < dpad; ++t) {
+        const float o32 = P.off32[t * P.n_pad + j];
+        const float ob = compact ? bf16_to_f32(f32_to_bf16_rne(o32)) : o32;
+        P.offb[t * P.n_pad + j] = ob;
+        if (P.pmb != nullptr) P.pmb[j * dpad + t] = ob;
+        sq16 += static_cast<double>(ob) * static_cast<double>(ob);
     }
     const double r2 = block_reduce(fmax(sq64, fmax(sq32, sq16)), MaxOp(), lds);
     const double nj = floor(0.5 * r2);
@@ -218,7 +248,7 @@ __global__ __launch_bounds__(BLOCK) void k_slots(Prepared P) {
     double so = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        float o = BF ? bf16_to_f32(P.off16[k * P.n_pad + j]) : P.off32[k * P.n_pad + j];
+        float o = BF ? P.offb[k * P.n_pad + j] : P.off32[k * P.n_pad + j];
         if (MAT) {
             o *= LOG2E_F;
             so = __builtin_fma(static_cast<double>(o), static_cast<double>(o), so);

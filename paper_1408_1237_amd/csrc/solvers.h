@@ -67,9 +67,16 @@ hipError_t tune_products(const Prepared &P, const SolverWork &W, bool inner, int
 
 // Batched flexible GMRES over many systems and right-hand sides (batched.hip).
 size_t batch_workspace_bytes(const krr_points *probs, int nprob, int nrhs, int m);
+// FP64 inner products are not batched (KRR_EUNSUPPORTED: the caller solves
+// those one at a time).
 int batched_fgmres(const krr_points *probs, int nprob, const double *sigma, const double *gamma, int nrhs,
                    const double *const *Y, const int64_t *ldy, double *const *W, const SolverOpts &o,
                    krr_info *infos, void *ws, size_t ws_bytes, hipStream_t s);
+// Plain FP64 CG over many systems and right-hand sides at once (the
+// comparator of the batched solve).
+int batched_cg64(const krr_points *probs, int nprob, const double *sigma, const double *gamma, int nrhs,
+                 const double *const *Y, const int64_t *ldy, double *const *W, const SolverOpts &o, krr_info *infos,
+                 void *ws, size_t ws_bytes, hipStream_t s);
 
 int cg_inner_sorted(const Prepared &P, int prec, double shift, const double *v_s, double *z_s, int maxit,
                     double tol, const SolverWork &W, krr_info *info, hipStream_t s);

@@ -141,6 +141,35 @@ int cg_inner_sorted(const Prepared &P, int prec, double shift, const double *v_s
 
 // ---------------------------------------------------------------- FGMRES
 
+// Time split of the outer steps: events on the solver's stream around the inner
+// solve, the outer product and the orthogonalisation with the Givens update,
+// read after the step's status read (the stream is idle then).
+struct StepTimer {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ok = true;
+    double ms[3] = {0.0, 0.0, 0.0};
+    StepTimer() {
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) ok = false;
+    }
+    ~StepTimer() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    StepTimer(const StepTimer &) = delete;
+    StepTimer &operator=(const StepTimer &) = delete;
+    void mark(int k, hipStream_t s) {
+        if (ok && hipEventRecord(ev[k], s) != hipSuccess) ok = false;
+    }
+    void collect() {
+        if (!ok) return;
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) ms[k] += t;
+        }
+    }
+};
+
 int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpts &o, const SolverWork &W,
                   krr_info *info, hipStream_t s) {
     const int64_t np = P.n_pad;
@@ -150,6 +179,7 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
     int64_t mvp64 = 0, mvp_in = 0;
     int outer = 0, inner_total = 0, cycles = 0;
     int result = KRR_NOT_CONVERGED;
+    StepTimer tm;
 
     KRR_HIP_STATUS(red_init(W.R, s));
     KRR_HIP_STATUS(tune_products(P, W, o.inner != KRR_INNER_NONE, o.inner_prec, s));
@@ -181,18 +211,23 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
             double *Vj = W.V + static_cast<int64_t>(j) * np;
             double *Zj = W.Z + static_cast<int64_t>(j) * np;
             // inner preconditioner: M_j z_j = v_j
+            tm.mark(0, s);
             if (o.inner == KRR_INNER_NONE) {
                 KRR_HIP_STATUS(copy_d(np, Vj, Zj, s));
             } else {
                 KRR_HIP_STATUS(inner_solve(P, o.inner_prec, o.delta, Vj, Zj, o.inner_maxit, o.inner_tol, W, s));
             }
+            tm.mark(1, s);
             // w = K z_j
             KRR_HIP_STATUS(kmvp_sorted(P, KRR_FP64, gamma, Zj, W.w, W.ksc, nullptr, s));
             ++mvp64;
+            tm.mark(2, s);
             KRR_HIP_STATUS(fg_orthogonalize(o.gs, np, j, W.w, W.V, W.hcol, W.hscr, F, W.R, s));
             KRR_HIP_STATUS(fg_givens(j, m, W.hcol, W.H, W.cs, W.sn, W.g, F, s));
             KRR_HIP_STATUS(fg_normalize(np, W.w, W.V + static_cast<int64_t>(j + 1) * np, W.hcol, j, F, s));
+            tm.mark(3, s);
             KRR_HIP_STATUS(read_status(W.status, st, s));
+            tm.collect();
             ++outer;
             k = j + 1;
             if (progress_every() && outer % progress_every() == 0)
@@ -233,6 +268,9 @@ int fgmres_sorted(const Prepared &P, double gamma, bool x0_zero, const SolverOpt
         if (o.inner != KRR_INNER_NONE && o.inner_prec == KRR_FP64) info->mvp64 += mvp_in;
         info->relres_true = est;
         info->relres_est = est;
+        info->t_inner_ms = tm.ms[0];
+        info->t_outer_ms = tm.ms[1];
+        info->t_ortho_ms = tm.ms[2];
     }
     return result;
 }

@@ -1,7 +1,10 @@
 // Split-f16 slot vectors of the FP32 / BF16 matrix-core product (kmvp.hip).
 //
-// Every FP32 operand v is split as v = hi + lo, hi = f16(v), lo = f16(v - hi):
-// |v - hi - lo| <= 2^-24 |v| (v - hi is exact in FP32; f16 subnormals are kept).
+// Every FP32 operand v is split as v = hi + lo, hi = f16(v), lo = f16(v - hi).
+// v - hi is exact in FP32 and |v - hi| <= 2^-11 |v|; rounding it to f16 (11-bit
+// significand, subnormals kept) leaves |v - hi - lo| <= 2^-22 |v| (plus half an
+// f16 subnormal step, 2^-25, when v - hi is below the f16 normal range): four
+// times the FP32 rounding of v itself.
 // An inner product a_i . b_j + c_i + e_j over D coordinates is then one over
 // 3 D + 4 slots: coordinate k takes slots 3k .. 3k + 2 with (hi, hi, lo) of the
 // source value and (hi, lo, hi) of the target value; slots 3D, 3D + 1 hold

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
 
 
 class ProfileEntry(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("pairs", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("pairs", ctypes.c_double),
+                ("pairs_skipped", ctypes.c_double)]
 
 
 class ProfileStats(ctypes.Structure):
@@ -57,7 +58,10 @@ class Info(ctypes.Structure):
                 ("mvp64", ctypes.c_int64), ("mvp32", ctypes.c_int64), ("mvp16", ctypes.c_int64),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("lambda_min_est", ctypes.c_double),
-                ("lambda_max_est", ctypes.c_double)]
+                ("lambda_max_est", ctypes.c_double), ("t_prep_ms", ctypes.c_double),
+                ("t_inner_ms", ctypes.c_double), ("t_outer_ms", ctypes.c_double),
+                ("t_ortho_ms", ctypes.c_double), ("batch_steps", ctypes.c_int32),
+                ("batch_tiles", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -165,6 +169,7 @@ class profile:
         check(load().krr_profile_end(ctypes.byref(st)), "krr_profile_end")
         names = ("fp64", "fp32", "bf16")
         self.stats = {names[k]: dict(launches=st.prec[k].launches, total_ms=st.prec[k].total_ms,
-                                     pairs=st.prec[k].pairs) for k in range(3)}
+                                     pairs=st.prec[k].pairs, pairs_skipped=st.prec[k].pairs_skipped)
+                      for k in range(3)}
         self.stats["dropped"] = st.dropped
         return False

@@ -55,7 +55,12 @@ def test_grad_same_lambda_and_w(prec):
     gx, gs, gg = _grad(x, 1.5, 0.01, w, w, same=True, prec=prec)
     ox, os_, og = oracle.grad(x, 1.5, 0.01, w, w)
     assert np.linalg.norm(gx - ox) / np.linalg.norm(ox) <= BAR[prec]
-    assert gs == pytest.approx(os_, rel=BAR[prec])
+    # d/dlog sigma is a sum of N^2 terms lam_i w_j K_ij |x_i - x_j|^2 of both
+    # signs (random w: the sum is about 1/80 of the sum of their magnitudes); an
+    # FP32 accumulation is held to the bar relative to that magnitude sum, which
+    # the oracle gives for |w| (every term positive), FP64 to the sum itself
+    scale = abs(oracle.grad(x, 1.5, 0.01, np.abs(w), np.abs(w))[1]) if prec == "fp32" else abs(os_)
+    assert abs(gs - os_) <= BAR[prec] * scale
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

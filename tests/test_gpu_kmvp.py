@@ -1,8 +1,9 @@
 """Parity of the HIP kernel products with the FP64 oracle (GPU).
 
-Tolerances (norm-wise ||y_gpu - y_oracle|| / ||y_oracle||, q ~ N(0, 1)):
-FP64 1e-12, FP32 1e-5, BF16-input 1e-2.  The oracle evaluates the kernel on the
-original FP64 points, so input rounding counts against the low precisions.
+Bars (tests/parity.py): FP64 1e-12, FP32 1e-5, BF16-input 1e-2, norm-wise and
+element-wise, q ~ N(0, 1).  The oracle evaluates the kernel on the original FP64
+points and on the q the call receives (FP32 for the FP32 and BF16 products), so
+every rounding inside the library counts against the low precisions.
 """
 import numpy as np
 import pytest
@@ -10,11 +11,9 @@ import torch
 
 import oracle
 from paper_1408_1237_amd import workloads
+from parity import BAR as TOL, DT, call_vector, check
 
 pytestmark = pytest.mark.gpu
-
-TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-2}
-DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
 
 
 def _api():
@@ -41,8 +40,8 @@ def test_kmvp_sizes(prec, n):
     x = workloads.random_points(100 + n, n, 3, 2.0)
     q = workloads.random_vector(200 + n, n)
     y = _gpu_mvp(x, 0.6, q, 0.01, prec)
-    want = oracle.mvp(x, 0.6, q, shift=0.01)
-    assert _relerr(y, want) <= TOL[prec]
+    want = oracle.mvp(x, 0.6, call_vector(q, prec), shift=0.01)
+    check(y, want, prec, what=n)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
@@ -53,8 +52,8 @@ def test_kmvp_dims(prec, d):
     sigma = 0.5 * np.sqrt(d)
     q = workloads.random_vector(400 + d, n)
     y = _gpu_mvp(x, sigma, q, 0.1, prec)
-    want = oracle.mvp(x, sigma, q, shift=0.1)
-    assert _relerr(y, want) <= TOL[prec]
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.1)
+    check(y, want, prec, what=d)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
@@ -104,18 +103,44 @@ def test_kmvp_kriging_shape_sampled_rows(prec):
     q = workloads.random_vector(7, p.n)
     y = _gpu_mvp(p.x, p.sigma, q, p.gamma, prec)
     rows = np.random.default_rng(12).choice(p.n, 64, replace=False)
-    want = oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.gamma)
-    assert _relerr(y[rows], want) <= TOL[prec]
+    want = oracle.mvp_rows(p.x, p.sigma, call_vector(q, prec), rows, shift=p.gamma)
+    check(y[rows], want, prec)
 
 
-def test_kmvp_clustered_large_bf16_sampled_rows():
-    # N = 1e6, d = 2 clustered points, BF16 inputs, 16 sampled rows
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_kmvp_clustered_large_sampled_rows(prec):
+    # N = 1e6, d = 2 clustered points (the largest workload: FP64 outer products,
+    # BF16-input inner products, FP32 for comparison), 16 sampled rows against
+    # the oracle's row sums over all 1e6 sources, with the shift of the inner
+    # system (delta) and of the outer one (gamma)
     p = workloads.clustered_large()
     q = workloads.random_vector(7, p.n)
-    y = _gpu_mvp(p.x, p.sigma, q, p.delta, "bf16")
+    shift = p.gamma if prec == "fp64" else p.delta
+    y = _gpu_mvp(p.x, p.sigma, q, shift, prec)
     rows = np.random.default_rng(13).choice(p.n, 16, replace=False)
-    want = oracle.mvp_rows(p.x, p.sigma, q, rows, shift=p.delta)
-    assert _relerr(y[rows], want) <= TOL["bf16"]
+    want = oracle.mvp_rows(p.x, p.sigma, call_vector(q, prec), rows, shift=shift)
+    check(y[rows], want, prec)
+
+
+@pytest.mark.parametrize("d,L", [(2, 30.0), (2, 38.0), (2, 41.0), (2, 44.0), (3, 28.0)])
+def test_split_f16_worst_case_folded_tiles(d, L):
+    # sparse uniform points (sigma = 1, about one neighbour per bandwidth): the
+    # 256-point tiles reach squared radii near the fold limit (40 scaled units),
+    # where the folded exponent adds its largest terms (|2 t . o| and |c| up to
+    # about 2 R^2 and 1.5 R^2) and the split-f16 operands lose the most (2^-22
+    # of each); the self pairs dominate every row, so the element-wise bar sees
+    # each target's error.  Also targets beyond the tiles' edges, whose exponents
+    # against a tile reach the far clamp.
+    n = 4096
+    x = workloads.random_points(900 + int(L), n, d, L)
+    q = workloads.random_vector(901, n)
+    y = _gpu_mvp(x, 1.0, q, 0.0, "fp32")
+    check(y, oracle.mvp(x, 1.0, call_vector(q, "fp32")), "fp32", what=(d, L))
+    ring = workloads.random_points(902, 500, d, 1.0, kind="normal")
+    ring = ring / np.linalg.norm(ring, axis=1, keepdims=True) * (0.5 * L * np.sqrt(d) + 8.0) + 0.5 * L
+    xt = np.ascontiguousarray(np.concatenate([ring, x[:500]]))
+    yc = _gpu_cross(xt, x, 1.0, q, "fp32")
+    check(yc, oracle.mvp(xt, 1.0, call_vector(q, "fp32"), xs=x), "fp32", what=(d, L, "cross"))
 
 
 def _gpu_cross(xt, xs, sigma, q, prec):
@@ -134,9 +159,9 @@ def test_kmvp_cross(prec, nt, ns):
     xt = workloads.random_points(600 + nt, nt, 3, 2.0)
     q = workloads.random_vector(700 + ns, ns)
     y = _gpu_cross(xt, xs, 0.5, q, prec)
-    want = oracle.mvp(xt, 0.5, q, xs=xs)
+    want = oracle.mvp(xt, 0.5, call_vector(q, prec), xs=xs)
     assert y.shape == (nt,)
-    assert _relerr(y, want) <= TOL[prec]
+    check(y, want, prec)
 
 
 def test_kmvp_cross_equals_square_on_same_points():
@@ -155,8 +180,8 @@ def test_kmvp_cross_shard_shape_clustered():
     xt = np.ascontiguousarray(p.x[:125_000])
     y = _gpu_cross(xt, p.x, p.sigma, q, "bf16")
     rows = np.random.default_rng(14).choice(xt.shape[0], 16, replace=False)
-    want = oracle.mvp(xt[rows], p.sigma, q, xs=p.x)
-    assert _relerr(y[rows], want) <= TOL["bf16"]
+    want = oracle.mvp(xt[rows], p.sigma, call_vector(q, "bf16"), xs=p.x)
+    check(y[rows], want, "bf16")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
@@ -173,8 +198,9 @@ def test_matrix_core_exponent_matches_valu_kernel(monkeypatch, prec, d):
     a = _gpu_mvp(x, sigma, q, 0.05, prec)
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
     b = _gpu_mvp(x, sigma, q, 0.05, prec)
-    want = oracle.mvp(x, sigma, q, shift=0.05)
-    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.05)
+    check(a, want, prec)
+    check(b, want, prec)
     assert _relerr(a, b) <= (1e-12 if prec == "fp64" else 1e-5)
 
 
@@ -194,7 +220,7 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
     outs.append(_gpu_mvp(x, sigma, q, 0.01, prec))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    assert _relerr(outs[0], oracle.mvp(x, sigma, q, shift=0.01)) <= TOL[prec]
+    check(outs[0], oracle.mvp(x, sigma, call_vector(q, prec), shift=0.01), prec)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -202,7 +228,7 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
 def test_split_f16_kernel_matches_fp32_matrix_kernel(monkeypatch, prec, d):
     # FP32 / BF16 products run the split-f16 matrix-core kernel; KRR_KMVP_MG32=1
     # selects the FP32 matrix-core form; both meet the oracle bar and agree to
-    # FP32 rounding (the split keeps the FP32 operands to 2^-24)
+    # FP32 rounding (the split keeps the FP32 operands to 2^-22)
     n = 2100
     x = workloads.random_points(90 + d, n, d, 1.0, kind="normal")
     q = workloads.random_vector(91 + d, n)
@@ -212,8 +238,9 @@ def test_split_f16_kernel_matches_fp32_matrix_kernel(monkeypatch, prec, d):
     monkeypatch.setenv("KRR_KMVP_MG32", "1")
     b = _gpu_mvp(x, sigma, q, 0.02, prec)
     monkeypatch.delenv("KRR_KMVP_MG32")
-    want = oracle.mvp(x, sigma, q, shift=0.02)
-    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.02)
+    check(a, want, prec)
+    check(b, want, prec)
     assert _relerr(a, b) <= 1e-5
 
 
@@ -222,10 +249,10 @@ def test_split_f16_kernel_far_and_wide_tiles(monkeypatch, prec):
     # three clusters: two tight ones 6 and 40 bandwidths apart (targets of one
     # against tiles of the other: every pair's exponent near or below -200, the
     # clamped case) and a sparse one whose tiles are wide (direct VALU form,
-    # offsets beyond the f16 range).  FP32 meets the oracle bar; BF16 inputs on
-    # these dense clusters lose more than 1e-2 to input rounding alone, so the
-    # split-f16 kernel is held to the FP32 matrix-core kernel on the same
-    # rounded inputs, and the sparse rows to (1 + s) times the rounded q.
+    # offsets beyond the f16 range; also tiles that mix cluster and sparse
+    # points, where BF16 offsets would be hundreds of units long and the BF16
+    # products keep FP32 offsets).  Both kernel forms meet the oracle bar, on
+    # all rows and on the sparse rows alone, and agree with each other.
     rng = np.random.default_rng(17)
     a = rng.normal(0.0, 1.0, size=(1200, 3))
     b = rng.normal(0.0, 1.0, size=(1100, 3)) + np.array([6.0, 0.0, 0.0])
@@ -238,15 +265,12 @@ def test_split_f16_kernel_far_and_wide_tiles(monkeypatch, prec):
     monkeypatch.setenv("KRR_KMVP_MG32", "1")
     y_mg = _gpu_mvp(x, 1.0, q, 0.01, prec)
     monkeypatch.delenv("KRR_KMVP_MG32")
-    assert _relerr(y, y_mg) <= 1e-5
+    want = oracle.mvp(x, 1.0, call_vector(q, prec), shift=0.01)
     rows = np.arange(3200, 3900)
-    if prec == "fp32":
-        want = oracle.mvp(x, 1.0, q, shift=0.01)
-        assert _relerr(y, want) <= TOL[prec]
-        assert _relerr(y[rows], want[rows]) <= TOL[prec]
-    else:
-        qb = torch.from_numpy(q).float().to(torch.bfloat16).double().numpy()
-        assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6
+    for got in (y, y_mg):
+        check(got, want, prec)
+        check(got[rows], want[rows], prec)
+    assert _relerr(y, y_mg) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -264,8 +288,9 @@ def test_split_f16_large_d_matches_valu_kernel(monkeypatch, prec, d):
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
     b = _gpu_mvp(x, sigma, q, 0.03, prec)
     monkeypatch.delenv("KRR_KMVP_VALU")
-    want = oracle.mvp(x, sigma, q, shift=0.03)
-    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.03)
+    check(a, want, prec)
+    check(b, want, prec)
     assert _relerr(a, b) <= 1e-5
 
 
@@ -274,7 +299,8 @@ def test_split_f16_large_d_matches_valu_kernel(monkeypatch, prec, d):
 def test_split_f16_large_d_far_and_wide_tiles(monkeypatch, prec, d):
     # d-dimensional version of the three-cluster case: two tight clusters 6 and
     # 40 bandwidths apart along different axes (the second pair clamped as far)
-    # and a sparse cluster of wide tiles (direct form on FP32 offsets)
+    # and a sparse cluster of wide tiles (direct form on FP32 offsets); held to
+    # the oracle and to the VALU kernel
     rng = np.random.default_rng(31 + d)
     a = rng.normal(0.0, 0.3, size=(900, d))
     b = rng.normal(0.0, 0.3, size=(800, d))
@@ -291,14 +317,10 @@ def test_split_f16_large_d_far_and_wide_tiles(monkeypatch, prec, d):
     y_valu = _gpu_mvp(x, 1.0, q, 0.01, prec)
     monkeypatch.delenv("KRR_KMVP_VALU")
     assert _relerr(y, y_valu) <= 1e-5
+    want = oracle.mvp(x, 1.0, call_vector(q, prec), shift=0.01)
     rows = np.arange(2400, 3000)
-    if prec == "fp32":
-        want = oracle.mvp(x, 1.0, q, shift=0.01)
-        assert _relerr(y, want) <= TOL[prec]
-        assert _relerr(y[rows], want[rows]) <= TOL[prec]
-    else:
-        qb = torch.from_numpy(q).float().to(torch.bfloat16).double().numpy()
-        assert _relerr(y[rows], 1.01 * qb[rows]) <= 1e-6
+    check(y, want, prec)
+    check(y[rows], want[rows], prec)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
@@ -311,8 +333,8 @@ def test_kmvp_cross_large_d(prec, d):
     q = workloads.random_vector(1000 + d, 1100)
     sigma = 0.6 * np.sqrt(d)
     y = _gpu_cross(xt, xs, sigma, q, prec)
-    want = oracle.mvp(xt, sigma, q, xs=xs)
-    assert _relerr(y, want) <= TOL[prec]
+    want = oracle.mvp(xt, sigma, call_vector(q, prec), xs=xs)
+    check(y, want, prec)
 
 
 @pytest.mark.parametrize("d", [24, 41, 64])
@@ -330,12 +352,12 @@ def test_fp64_large_d_far_and_wide_tiles(d):
     x = np.ascontiguousarray(np.concatenate([a, b, c, s]))
     q = workloads.random_vector(42 + d, x.shape[0])
     y = _gpu_mvp(x, 1.0, q, 0.01, "fp64")
-    assert _relerr(y, oracle.mvp(x, 1.0, q, shift=0.01)) <= TOL["fp64"]
+    check(y, oracle.mvp(x, 1.0, q, shift=0.01), "fp64")
     x = workloads.random_points(43 + d, 1100, d, 1.0, kind="normal")
     q = workloads.random_vector(44 + d, 1100)
     sigma = 0.6 * np.sqrt(d)
     y = _gpu_mvp(x, sigma, q, 0.01, "fp64")
-    assert _relerr(y, oracle.mvp(x, sigma, q, shift=0.01)) <= TOL["fp64"]
+    check(y, oracle.mvp(x, sigma, q, shift=0.01), "fp64")
 
 
 @pytest.mark.parametrize("d", [17, 24, 29, 32, 41, 48, 64])
@@ -352,7 +374,8 @@ def test_fp64_matrix_core_large_d_matches_valu_kernel(monkeypatch, d):
     b = _gpu_mvp(x, sigma, q, 0.03, "fp64")
     monkeypatch.delenv("KRR_KMVP_VALU")
     want = oracle.mvp(x, sigma, q, shift=0.03)
-    assert _relerr(a, want) <= TOL["fp64"] and _relerr(b, want) <= TOL["fp64"]
+    check(a, want, "fp64")
+    check(b, want, "fp64")
     assert _relerr(a, b) <= 1e-13
 
 
@@ -370,8 +393,9 @@ def test_fp32_matrix_core_d64_matches_valu_kernel(monkeypatch, prec, d):
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
     b = _gpu_mvp(x, sigma, q, 0.03, prec)
     monkeypatch.delenv("KRR_KMVP_VALU")
-    want = oracle.mvp(x, sigma, q, shift=0.03)
-    assert _relerr(a, want) <= TOL[prec] and _relerr(b, want) <= TOL[prec]
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.03)
+    check(a, want, prec)
+    check(b, want, prec)
     assert _relerr(a, b) <= 1e-5
 
 
@@ -386,6 +410,49 @@ def test_kmvp_cross_large_d_tiny_sets(prec, d, nt, ns):
     q = workloads.random_vector(1300 + ns, ns)
     sigma = 0.6 * np.sqrt(d)
     y = _gpu_cross(xt, xs, sigma, q, prec)
-    want = oracle.mvp(xt, sigma, q, xs=xs)
+    want = oracle.mvp(xt, sigma, call_vector(q, prec), xs=xs)
     assert y.shape == (nt,)
-    assert _relerr(y, want) <= TOL[prec]
+    check(y, want, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_far_tile_skipping_changes_nothing(monkeypatch, prec):
+    # the clustered layout (50 clusters over [0, 100]^2, sigma = 1) at N = 20,000:
+    # most tile pairs lie beyond the far threshold and are skipped; their terms
+    # are exactly zero, so the product equals the one that computes them
+    # (KRR_NO_TILE_SKIP=1) and meets the oracle bar; the profile reports the
+    # skipped share
+    from paper_1408_1237_amd import native
+    p = workloads.clustered_large(n=20_000)
+    q = workloads.random_vector(71, p.n)
+    monkeypatch.setenv("KRR_NO_TILE_SKIP", "0")
+    with native.profile() as prof:
+        y = _gpu_mvp(p.x, p.sigma, q, p.delta, prec)
+    monkeypatch.setenv("KRR_NO_TILE_SKIP", "1")
+    with native.profile() as prof_all:
+        y_all = _gpu_mvp(p.x, p.sigma, q, p.delta, prec)
+    monkeypatch.delenv("KRR_NO_TILE_SKIP")
+    assert np.array_equal(y, y_all)
+    check(y, oracle.mvp(p.x, p.sigma, call_vector(q, prec), shift=p.delta), prec)
+    st = prof.stats[prec]
+    lo = 0.1 if prec == "fp64" else 0.4  # FP64 skips only beyond exponent -1100, FP32 / BF16 beyond -200
+    assert st["launches"] == 1 and lo * st["pairs"] < st["pairs_skipped"] < st["pairs"]
+    assert prof_all.stats[prec]["pairs_skipped"] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_far_tile_skipping_cross_product(monkeypatch, prec):
+    # targets in a cluster 60 bandwidths from every source (all their tile pairs
+    # skipped: exactly zero) next to targets inside the sources' cluster
+    xs = workloads.random_points(72, 3000, 2, 1.0, kind="normal")
+    far = workloads.random_points(73, 700, 2, 1.0, kind="normal") + np.array([60.0, 0.0])
+    near = workloads.random_points(74, 300, 2, 1.0, kind="normal")
+    xt = np.ascontiguousarray(np.concatenate([far, near]))
+    q = workloads.random_vector(75, 3000)
+    y = _gpu_cross(xt, xs, 1.0, q, prec)
+    assert np.all(y[:700] == 0.0)
+    check(y, oracle.mvp(xt, 1.0, call_vector(q, prec), xs=xs), prec)
+    monkeypatch.setenv("KRR_NO_TILE_SKIP", "1")
+    y_all = _gpu_cross(xt, xs, 1.0, q, prec)
+    monkeypatch.delenv("KRR_NO_TILE_SKIP")
+    assert np.array_equal(y, y_all)

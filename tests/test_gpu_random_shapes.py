@@ -1,18 +1,20 @@
 """Seeded random shapes through every product kernel (GPU): point count, dimension,
 precision, kernel family and square / cross form drawn per case, each result
-held to the oracle at its precision's bar (FP64 1e-12, FP32 1e-5, BF16 inputs
-2e-2 norm-wise)."""
+held to the oracle at its precision's bar, norm-wise and element-wise
+(tests/parity.py: FP64 1e-12, FP32 1e-5, BF16 inputs 1e-2).  The Matern-3/2
+kernel is flat near zero distance, so at large d many comparable terms of both
+signs enter every row; there the BF16 rounding of q alone can move the exact
+product by more than 1e-2, and its BF16 bar is 1.25 times that format floor (the
+oracle on the BF16-rounded q against the oracle on q)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1408_1237_amd import workloads
+from parity import DT, call_vector, check, format_floor
 
 pytestmark = pytest.mark.gpu
-
-BAR = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-2}
-DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
 
 
 def _case(seed):
@@ -32,16 +34,16 @@ def test_random_shape_square_product(seed):
     q = workloads.random_vector(6100 + seed, n)
     h = 0.7 * np.sqrt(d)
     xt, qt = torch.from_numpy(x).cuda(), torch.from_numpy(q).to(DT[prec]).cuda()
+    q32 = call_vector(q, prec)
     if kind == "gauss":
         y = api.kmvp_gauss(xt, h, qt, shift=0.02, prec=prec)
-        want = oracle.mvp(x, h, q, shift=0.02)
+        ref = lambda v: oracle.mvp(x, h, v, shift=0.02)  # noqa: E731
     else:
         y = api.kmvp_matern(xt, h, qt, shift=0.02, prec=prec)
-        want = oracle.matern_mvp(x, h, q, shift=0.02)
+        ref = lambda v: oracle.matern_mvp(x, h, v, shift=0.02)  # noqa: E731
     torch.cuda.synchronize()
-    y = y.double().cpu().numpy()
-    err = np.linalg.norm(y - want) / max(np.linalg.norm(want), 1e-300)
-    assert err <= BAR[prec], (n, d, prec, kind, err)
+    floor = format_floor(ref, q32) if (prec == "bf16" and kind == "matern") else (0.0, 0.0)
+    check(y.double().cpu().numpy(), ref(q32), prec, floor=floor, what=(n, d, kind))
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -57,6 +59,6 @@ def test_random_shape_cross_product(seed):
                              torch.from_numpy(q).to(DT[prec]).cuda(), prec=prec)
     torch.cuda.synchronize()
     y = y.double().cpu().numpy()
-    want = oracle.mvp(xt, h, q, xs=xs)
-    err = np.linalg.norm(y - want) / max(np.linalg.norm(want), 1e-300)
-    assert y.shape == (nt,) and err <= BAR[prec], (nt, n, d, prec, err)
+    want = oracle.mvp(xt, h, call_vector(q, prec), xs=xs)
+    assert y.shape == (nt,)
+    check(y, want, prec, what=(nt, n, d))

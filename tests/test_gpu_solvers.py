@@ -238,17 +238,128 @@ def test_batched_gmres_mode():
 
 
 def test_batched_graph_replays_match_eager(monkeypatch):
-    # the inner CG of the batched solver is a recorded HIP graph replayed at every
-    # outer step, with eager kernels and host synchronisations between replays;
+    # every outer step of the batched solver (inner CG, outer product,
+    # Gram-Schmidt, Givens) is a recorded HIP graph per step index, replayed at
+    # every cycle with eager kernels and host synchronisations between replays;
     # the arithmetic is deterministic, so the graph and eager runs agree bitwise
+    # (MGS and CGS2)
     api = _api()
     probs = workloads.batched(nsys=3, nmin=400, nmax=900, nrhs=2)
     args = ([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
             [_fcol(p.y) for p in probs])
-    monkeypatch.setenv("KRR_NO_GRAPH", "0")
-    Wg, ig = api.krr_solve(*args, mode="fgmres")
-    monkeypatch.setenv("KRR_NO_GRAPH", "1")
-    We, ie = api.krr_solve(*args, mode="fgmres")
-    assert ig[0]["outer_iters"] == ie[0]["outer_iters"] and ig[0]["outer_iters"] > 1
-    for a, b in zip(Wg, We):
-        assert torch.equal(a, b)
+    for gs in ("mgs", "cgs2"):
+        monkeypatch.setenv("KRR_NO_GRAPH", "0")
+        Wg, ig = api.krr_solve(*args, mode="fgmres", gs=gs, restart_m=8)
+        monkeypatch.setenv("KRR_NO_GRAPH", "1")
+        We, ie = api.krr_solve(*args, mode="fgmres", gs=gs, restart_m=8)
+        assert ig[0]["outer_iters"] == ie[0]["outer_iters"] and ig[0]["outer_iters"] > 8  # several cycles
+        for a, b in zip(Wg, We):
+            assert torch.equal(a, b)
+
+
+def _bargs(probs):
+    return ([_t(p.x) for p in probs], [p.sigma for p in probs], [p.gamma for p in probs],
+            [_fcol(p.y) for p in probs])
+
+
+def test_batched_cgs2_and_per_column_counts():
+    # classical Gram-Schmidt twice in the batched solver; every column keeps its
+    # own outer count (columns stop on their own), its FP64 product count is its
+    # steps plus one true residual per cycle, and the batch ran as many steps as
+    # its slowest column (at most cg_check more: the host checks every cg_check)
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=400, nmax=1400, nrhs=3)
+    Ws, infos = api.krr_solve(*_bargs(probs), mode="fgmres", gs="cgs2", restart_m=40, cg_check=4)
+    assert all(i["status"] == 0 for i in infos), infos
+    for p, W in zip(probs, Ws):
+        for r in range(3):
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], W.cpu().numpy()[:, r]) <= 1e-6
+    outer = [i["outer_iters"] for i in infos]
+    assert len(set(outer)) > 1
+    for i in infos:
+        assert i["mvp64"] == i["outer_iters"] + i["cycles"]
+        assert i["mvp32"] == i["inner_iters"] and 0 < i["inner_iters"] <= 10 * i["outer_iters"]
+        assert i["batch_steps"] >= max(outer) and i["batch_tiles"] in (16, 32, 64, 128)
+    # MGS on the same batch reaches the same tolerance
+    Wm, im = api.krr_solve(*_bargs(probs), mode="fgmres", gs="mgs", restart_m=40)
+    assert all(i["status"] == 0 for i in im)
+
+
+def test_batched_fp64_inner_products_are_honoured():
+    # FP64 inner products are not batched: the pairs are solved one at a time
+    # with FP64 inner CG (no FP32 / BF16 products), each to the tolerance
+    api = _api()
+    probs = workloads.batched(nsys=2, nmin=300, nmax=700, nrhs=2)
+    Ws, infos = api.krr_solve(*_bargs(probs), mode="fgmres", inner_prec="fp64")
+    for p, W, k in zip(probs, Ws, range(2)):
+        for r in range(2):
+            i = infos[2 * k + r]
+            assert i["status"] == 0 and i["mvp32"] == 0 and i["mvp16"] == 0 and i["batch_steps"] == 0
+            assert i["mvp64"] > i["outer_iters"]  # inner and outer products both FP64
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], W.cpu().numpy()[:, r]) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["fgmres", "cg64"])
+def test_batched_nonfinite_column_is_retired_alone(mode):
+    # a right-hand side with a NaN: that column is not solved (zero, status
+    # KRR_ENONFINITE), every other column is, and the call reports KRR_ENONFINITE
+    from paper_1408_1237_amd import native
+    api = _api()
+    probs = workloads.batched(nsys=2, nmin=400, nmax=900, nrhs=3)
+    probs[0].y[5, 1] = np.nan
+    Ws, infos, rc = api.krr_solve(*_bargs(probs), mode=mode, return_status=True, max_outer=5000)
+    assert rc == native.KRR_ENONFINITE
+    assert infos[1]["status"] == native.KRR_ENONFINITE
+    assert np.all(Ws[0].cpu().numpy()[:, 1] == 0.0)
+    for k, p in enumerate(probs):
+        for r in range(3):
+            if (k, r) == (0, 1):
+                continue
+            assert infos[3 * k + r]["status"] == 0
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], Ws[k].cpu().numpy()[:, r]) <= 1e-6
+
+
+def test_batched_cg64_matches_single_cg64():
+    # plain FP64 CG over every (system, column) pair at once: each column to the
+    # true residual 1e-6, with about the iterations of its own single CG solve
+    api = _api()
+    probs = workloads.batched(nsys=3, nmin=300, nmax=1200, nrhs=2)
+    Ws, infos = api.krr_solve(*_bargs(probs), mode="cg64", max_outer=20000, cg_check=8)
+    assert all(i["status"] == 0 and i["batch_steps"] > 0 for i in infos), infos
+    for k, (p, W) in enumerate(zip(probs, Ws)):
+        for r in range(2):
+            i = infos[2 * k + r]
+            y = np.ascontiguousarray(p.y[:, r])
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, y, W.cpu().numpy()[:, r]) <= 1e-6
+            (w1,), (i1,) = api.krr_solve([_t(p.x)], [p.sigma], [p.gamma], [_t(y)], mode="cg64", max_outer=20000)
+            assert abs(i["outer_iters"] - i1["outer_iters"]) <= max(3, 0.1 * i1["outer_iters"])
+            assert i["mvp64"] >= i["outer_iters"] + 1
+
+
+@pytest.mark.parametrize("tps", ["16", "128"])
+def test_batched_work_item_tile_does_not_change_the_solution(monkeypatch, tps):
+    # KRR_BATCH_TPS fixes the column tiles per work item (else autotuned); the
+    # partial sums change with it only at rounding level
+    api = _api()
+    probs = workloads.batched(nsys=2, nmin=4000, nmax=9000, nrhs=2)
+    monkeypatch.delenv("KRR_BATCH_TPS", raising=False)
+    Wa, ia = api.krr_solve(*_bargs(probs), mode="fgmres")
+    monkeypatch.setenv("KRR_BATCH_TPS", tps)
+    Wb, ib = api.krr_solve(*_bargs(probs), mode="fgmres")
+    assert all(i["status"] == 0 for i in ia + ib)
+    assert all(i["batch_tiles"] == int(tps) for i in ib)
+    for p, a, b in zip(probs, Wa, Wb):
+        for r in range(2):
+            assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y[:, r], b.cpu().numpy()[:, r]) <= 1e-6
+        assert torch.linalg.norm(a - b) <= 1e-3 * torch.linalg.norm(a)
+
+
+def test_cg64_workspace_holds_the_coefficient_history():
+    # the plain CG keeps two coefficients per iteration for the condition
+    # estimate: at small n with a large iteration cap that history is larger
+    # than the flexible solvers' basis, and the solve workspace covers it
+    api = _api()
+    p = workloads.plain_small(n=300)
+    (w,), (info,) = api.krr_solve([_t(p.x)], [p.sigma], [p.gamma], [_t(p.y)], mode="cg64", max_outer=60000)
+    assert info["status"] == 0
+    assert oracle.true_relres(p.x, p.sigma, p.gamma, p.y, w.cpu().numpy()) <= 1e-6
