@@ -285,6 +285,7 @@ def kernel_only(api, native, workloads, torch, p, x, reps: int, prec: str = "fp3
     ach = st["pairs"] / (st["total_ms"] * 1e-3) / 1e9
     print(json.dumps({"mode": "kernel-only", "prec": prec, "n": p.n, "d": p.d, "launches": st["launches"],
                       "avg_launch_ms": st["total_ms"] / max(st["launches"], 1), "gpair_s": ach,
+                      "skipped_frac": st["pairs_skipped"] / max(st["pairs"], 1.0),
                       "copy_bytes": 2 * a.numel() * 4}), flush=True)
     return 0
 
@@ -327,8 +328,9 @@ def workload_clustered(args, api, native, workloads, torch) -> dict:
     rates = product_rates(api, native, torch, x, p.sigma, p.delta, p.n, 3)
     log(f"clustered products: {rates}")
     inner_maxit = args.inner_maxit or p.inner_maxit
-    opts = dict(inner_prec="bf16", inner_maxit=inner_maxit, inner_tol=p.inner_tol, delta=p.delta, restart_m=200,
-                tol=p.tol, max_outer=args.max_outer or 3000, gs="cgs2")
+    inner_prec = args.inner_prec or "bf16"
+    opts = dict(inner_prec=inner_prec, inner_maxit=inner_maxit, inner_tol=p.inner_tol, delta=p.delta,
+                restart_m=args.restart or 200, tol=p.tol, max_outer=args.max_outer or 3000, gs="cgs2")
     torch.cuda.synchronize()
     with native.profile(max_launches=200_000) as prof:
         t0 = time.perf_counter()
@@ -341,20 +343,22 @@ def workload_clustered(args, api, native, workloads, torch) -> dict:
     # plain FP64 CG with the same wall time: iterations from the FP64 product time
     t_it = rates["fp64"]["avg_launch_ms"] * 1e-3 + 1e-4
     cg_iters = max(16, int(tf / t_it) // 16 * 16)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=cg_iters,
-                                 cg_check=16)
-    torch.cuda.synchronize()
-    tc = time.perf_counter() - t0
-    log(f"cg64 given {cg_iters} iterations (the same wall time): status {ic['status']}, "
-        f"relres {ic['relres_true']:.3e}, {tc:.2f} s")
+    ic, tc = {"outer_iters": 0, "relres_true": None, "status": None}, 0.0
+    if not args.no_cg:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=cg_iters,
+                                     cg_check=16)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        log(f"cg64 given {cg_iters} iterations (the same wall time): status {ic['status']}, "
+            f"relres {ic['relres_true']:.3e}, {tc:.2f} s")
     peak_pairs, peak_rule, kname = product_peak(p.d, prec="bf16")
     ach = rates["bf16"]["evaluated_gpair_s"]
     return {"metric": METRIC, "value": rates["bf16"]["gpair_s"] * 1e9, "unit": "pairs/s", "n_gpus": 1,
             "dtype": "bf16-input/f32 + f64", "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
             "config": {"workload": "clustered N=1e6 d=2 50-component mixture sigma=1 gamma=1e-4; FGMRES FP64 outer, "
-                                   f"BF16-input inner CG ({inner_maxit} its, tol 1e-5) on K_hat+1e-3 I, tol 1e-6",
+                                   f"{inner_prec} inner CG ({inner_maxit} its, tol 1e-5) on K_hat+1e-3 I, tol 1e-6",
                        "n": p.n, "d": p.d},
             "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak_pairs / 1e9, 1), "unit": "Gpair/s",
                          "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None, "kernel": kname,
@@ -443,6 +447,7 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
     p = workloads.gp_regression()
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
+    os.environ.setdefault("KRR_PROGRESS", "100")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     w, info = api.fgmres_solve(x, p.sigma, p.gamma, y, inner_prec="fp32", inner_maxit=p.inner_maxit,
@@ -451,6 +456,21 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     log(f"gp forward solve: {info['outer_iters']} outer, relres {info['relres_true']:.3e}, {ts:.2f} s")
+    # the paper's inner rule (inner tolerance 10x the outer one, at most 100
+    # inner iterations) and plain FP64 CG on the same system
+    t0 = time.perf_counter()
+    wp, ip = api.fgmres_solve(x, p.sigma, p.gamma, y, inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol,
+                              delta=p.delta, restart_m=1000, gs="cgs2", max_outer=args.max_outer or 1000)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log(f"gp fgmres (paper inner rule): {ip['outer_iters']} outer, {ip['inner_iters']} inner, "
+        f"relres {ip['relres_true']:.3e}, {tp:.2f} s")
+    t0 = time.perf_counter()
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=20000,
+                                 cg_check=32)
+    torch.cuda.synchronize()
+    tc = time.perf_counter() - t0
+    log(f"gp cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
     d = p.d
     times = {}
     for prec in ("fp64", "fp32"):
@@ -473,7 +493,14 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
             "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
             "config": {"workload": "gp_regression N=2e5 d=16 sigma=4 gamma=1e-2: gradient of y^T K^-1 y", "n": p.n,
                        "d": d},
-            "forward_solve": {"time_s": ts, "outer_iters": info["outer_iters"], "relres_true": info["relres_true"]},
+            "forward_solve": {"time_s": ts, "outer_iters": info["outer_iters"], "relres_true": info["relres_true"],
+                              "t_inner_ms": info["t_inner_ms"], "t_outer_ms": info["t_outer_ms"],
+                              "settings": "FGMRES(100), 10 FP32 inner CG iterations on K_hat + 0.1 I"},
+            "fgmres_paper_rule": {"time_s": tp, "outer_iters": ip["outer_iters"], "inner_iters": ip["inner_iters"],
+                                  "relres_true": ip["relres_true"], "status": ip["status"]},
+            "cg64": {"time_s": tc, "iters": ic["outer_iters"], "relres_true": ic["relres_true"],
+                     "status": ic["status"]},
+            "speedup_fgmres_paper_rule_vs_cg64": tc / tp,
             "gradient_pass_ms": times,
             "roofline": {"bound": "alu", "achieved": round(rate / 1e9, 1), "peak": round(peak / 1e9, 1),
                          "unit": "Gpair/s", "frac": round(rate / peak, 4), "traffic": None,
@@ -651,12 +678,18 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
     ap.add_argument("--kernel-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision of the --kernel-only products")
+    ap.add_argument("--kernel-points", default="kriging", choices=("kriging", "gp", "clustered"),
+                    help="point set of the --kernel-only products (kriging N=1e5 d=3, gp N=2e5 d=16, "
+                         "clustered N=1e6 d=2)")
     ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "highd", "sweep"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
                     help="outer-step budget of the secondary workloads (default: to convergence)")
     ap.add_argument("--inner-maxit", type=int, default=0,
                     help="inner CG iterations of the clustered workload (default: its 10)")
+    ap.add_argument("--inner-prec", default="", choices=("", "fp32", "bf16"),
+                    help="inner product precision of the clustered workload (default: its bf16)")
+    ap.add_argument("--restart", type=int, default=0, help="restart length of the clustered workload (default 200)")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
                     help="only K FP32 products on the workload's points plus one 256 MiB copy "
                          "(the short run used for rocprofv3 counter passes)")
@@ -680,11 +713,14 @@ def main() -> int:
         out = others[args.workload](args, api, native, workloads, torch)
         print(json.dumps(out), flush=True)
         return 0
+    if args.kernel_only:
+        pk = {"kriging": lambda: workloads.kriging(n=args.n), "gp": workloads.gp_regression,
+              "clustered": workloads.clustered_large}[args.kernel_points]()
+        xk = torch.from_numpy(pk.x).cuda()
+        return kernel_only(api, native, workloads, torch, pk, xk, args.kernel_only, args.kernel_prec)
     p = workloads.kriging(n=args.n)
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
-    if args.kernel_only:
-        return kernel_only(api, native, workloads, torch, p, x, args.kernel_only, args.kernel_prec)
     opts = dict(inner_prec="fp32", inner_maxit=p.inner_maxit, inner_tol=0.0, delta=p.delta, restart_m=100,
                 tol=p.tol, max_outer=5000, gs="cgs2")
     paper_opts = dict(inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol, delta=p.delta, restart_m=1000,

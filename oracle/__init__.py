@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "krr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")  # AddressSanitizer + UBSan build (host code only)
 _lock = threading.Lock()
 _lib = None
 
@@ -33,23 +34,28 @@ _int = ctypes.c_int
 _dbl = ctypes.c_double
 
 
-def build(force: bool = False) -> str:
-    """Compile ``krr_oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
-               "-o", tmp, _SRC, "-lm"]
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile ``krr_oracle.c`` into ``liboracle.so`` (gcc, -O2, OpenMP); with
+    sanitize, into ``liboracle_san.so`` with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host C code; load it with the ASan runtime
+    preloaded and KRR_ORACLE_SANITIZE=1)."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + f".tmp{os.getpid()}"
+        opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        cmd = ["gcc", *opt, "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_LIB)
+            sanitize = os.environ.get("KRR_ORACLE_SANITIZE", "0") == "1"
+            lib = ctypes.CDLL(build(sanitize=sanitize))
             lib.or_num_threads.restype = _int
             lib.or_set_num_threads.argtypes = [_int]
             lib.or_gauss.restype = _dbl
