@@ -193,6 +193,24 @@ size_t krr_workspace_size(int32_t which, const krr_points *probs, int32_t nprob,
 int kmvp_gauss(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
                const void *q, void *y, void *ws, size_t ws_bytes, krr_stream_t stream);
 
+/* kmvp_gauss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product, y = K_hat q + shift q, with the same arguments except the workspace,
+ * which is a fixed static device array of krr_noalloc_scratch_bytes() bytes
+ * (64 MiB) that every device the library runs on holds until the process ends.
+ * Nothing is allocated or freed, no launch shape is tuned (the tuned shape of
+ * an earlier kmvp_gauss call on the same shape, else the default one; the result
+ * does not depend on it) and nothing is synchronised.  Every call on a device
+ * shares that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  Errors as kmvp_gauss, and KRR_EUNSUPPORTED when the
+ * product's scratch (krr_workspace_size(KRR_WS_KMVP, ...): about 460 bytes per
+ * point plus 17 MiB at d = 3, so up to about 100,000 points there) exceeds the
+ * array. */
+size_t krr_noalloc_scratch_bytes(void);
+int kmvp_gauss_noalloc(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
+                       const void *q, void *y, krr_stream_t stream);
+
 /* The same product with the Matern-3/2 kernel (eq. MaternKernel, section 6):
  * y = K_hat q + shift q, K_hat_ij = (1 + sqrt(3) d_ij) exp(-sqrt(3) d_ij),
  * d_ij = ||x_i - x_j|| / h.  Arguments, layouts and errors as in kmvp_gauss

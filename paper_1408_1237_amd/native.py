@@ -29,7 +29,7 @@ KRR_MAX_DIM = 64
 EXPORTED = ("krr_default_opts", "krr_status_string", "krr_workspace_size", "kmvp_gauss", "kmvp_matern",
             "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve", "fgmres_solve",
             "krr_solve", "krr_predict", "krr_profile_begin", "krr_profile_end", "krr_probe_workspace_size",
-            "krr_probe_issue_rates", "krr_lanczos_extremes")
+            "krr_probe_issue_rates", "krr_lanczos_extremes", "kmvp_gauss_noalloc", "krr_noalloc_scratch_bytes")
 
 
 class Points(ctypes.Structure):
@@ -116,8 +116,11 @@ def load(path: str | None = None):
         lib.krr_lanczos_extremes.restype = ctypes.c_int
         lib.krr_lanczos_extremes.argtypes = [_P(_dbl), _P(_dbl), _i32, _P(_dbl), _P(_dbl)]
         lib.krr_profile_end.restype = ctypes.c_int
+        lib.kmvp_gauss_noalloc.argtypes = [_P(Points), _dbl, _dbl, _i32, _vp, _vp, _vp]
+        lib.krr_noalloc_scratch_bytes.argtypes = []
+        lib.krr_noalloc_scratch_bytes.restype = _sz
         for name in ("kmvp_gauss", "kmvp_matern", "kmvp_gauss_multi", "kmvp_gauss_cross", "kmvp_grad", "cg_inner_solve",
-                     "fgmres_solve", "krr_solve"):
+                     "fgmres_solve", "krr_solve", "kmvp_gauss_noalloc"):
             getattr(lib, name).restype = ctypes.c_int
         if path is None:
             _lib = lib
