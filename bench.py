@@ -54,7 +54,7 @@ def dpad(d: int) -> int:
     return next(p for p in DIMS if p >= d)
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, index, shift, table product, ldexp
-C_EXP2_F64_TAB2048 = 10 * C_FMA             # the 2048-entry form (d <= 3): 3 FMAs
+C_EXP2_F64_TAB4096 = 9 * C_FMA              # the 4096-entry form (d <= 3): 2 FMAs
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
@@ -64,8 +64,8 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
     exponentials and 16 FMAs: FP32 / BF16 for d <= 48 (split-f16 kernels)
     ceil((3D + 2) / 16) 32x32x16 f16 matrix-core operations; FP64 for d <= 16
     4 ceil((D + 1) / 4) 16x16x4 FP64 ones (D the compiled dimension; FP64
-    exponentials from the 256-entry table, 11 instructions; 10 with the
-    2048-entry table at d <= 3), the same model for
+    exponentials from the 256-entry table, 11 instructions; 9 with the
+    4096-entry table at d <= 3), the same model for
     FP64 at d > 16 (staged kernel).  Otherwise (VALU kernel) per 64 pairs: d + 1
     FMAs and one exponential per lane.  Matrix-core
     and VALU issue counted one after the other (measured by the issue probe).
@@ -99,7 +99,7 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
             return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mh<{D}, {tag}>"
         dk = (D + 4) // 4
         if prec == "fp64":
-            cyc = 4 * dk * C_MFMA64 + 16 * ((C_EXP2_F64_TAB2048 if D <= 3 else C_EXP2_F64_TAB) + C_FMA)
+            cyc = 4 * dk * C_MFMA64 + 16 * ((C_EXP2_F64_TAB4096 if D <= 3 else C_EXP2_F64_TAB) + C_FMA)
         else:
             cyc = 4 * dk * C_MFMA32 + 16 * (C_EXP + C_FMA)
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
@@ -321,12 +321,31 @@ def workload_clustered(args, api, native, workloads, torch) -> dict:
     --inner-maxit), and plain FP64 CG given the same wall time (the residual it
     reaches is reported)."""
     p = workloads.clustered_large()
+    if args.gamma > 0:  # the same points with another regulariser (delta = 10 gamma)
+        p.gamma, p.delta = args.gamma, 10 * args.gamma
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
     torch.manual_seed(7)
     os.environ.setdefault("KRR_PROGRESS", "25")
     rates = product_rates(api, native, torch, x, p.sigma, p.delta, p.n, 3)
     log(f"clustered products: {rates}")
+    if args.cg_only:
+        # plain FP64 CG alone for --max-outer iterations (its comparison run)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol,
+                                     max_outer=args.max_outer or 1000, cg_check=16)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        log(f"cg64 alone, {ic['outer_iters']} iterations: status {ic['status']}, relres {ic['relres_true']:.3e}, "
+            f"{tc:.2f} s")
+        return {"metric": METRIC, "value": tc, "unit": "s", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                "higher_is_better": False, "vs_baseline": None,
+                "config": {"workload": f"clustered N=1e6 d=2 sigma=1 gamma={p.gamma:g}; plain FP64 CG for "
+                                       f"{args.max_outer or 1000} iterations", "n": p.n, "d": p.d},
+                "products": rates,
+                "cg64": {"iters": ic["outer_iters"], "relres_true": ic["relres_true"], "time_s": tc,
+                         "status": ic["status"]}}
     inner_maxit = args.inner_maxit or p.inner_maxit
     inner_prec = args.inner_prec or "bf16"
     opts = dict(inner_prec=inner_prec, inner_maxit=inner_maxit, inner_tol=p.inner_tol, delta=p.delta,
@@ -357,8 +376,9 @@ def workload_clustered(args, api, native, workloads, torch) -> dict:
     ach = rates["bf16"]["evaluated_gpair_s"]
     return {"metric": METRIC, "value": rates["bf16"]["gpair_s"] * 1e9, "unit": "pairs/s", "n_gpus": 1,
             "dtype": "bf16-input/f32 + f64", "data": "synthetic", "higher_is_better": True, "vs_baseline": None,
-            "config": {"workload": "clustered N=1e6 d=2 50-component mixture sigma=1 gamma=1e-4; FGMRES FP64 outer, "
-                                   f"{inner_prec} inner CG ({inner_maxit} its, tol 1e-5) on K_hat+1e-3 I, tol 1e-6",
+            "config": {"workload": f"clustered N=1e6 d=2 50-component mixture sigma=1 gamma={p.gamma:g}; FGMRES FP64 "
+                                   f"outer, {inner_prec} inner CG ({inner_maxit} its, tol 1e-5) on K_hat+{p.delta:g} I, "
+                                   "tol 1e-6",
                        "n": p.n, "d": p.d},
             "roofline": {"bound": "alu", "achieved": ach, "peak": round(peak_pairs / 1e9, 1), "unit": "Gpair/s",
                          "frac": round(ach * 1e9 / peak_pairs, 4), "traffic": None, "kernel": kname,
@@ -678,9 +698,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000, help="points (default: the full workload)")
     ap.add_argument("--kernel-prec", default="fp32", choices=("fp64", "fp32", "bf16"),
                     help="precision of the --kernel-only products")
-    ap.add_argument("--kernel-points", default="kriging", choices=("kriging", "gp", "clustered"),
+    ap.add_argument("--kernel-points", default="kriging", choices=("kriging", "gp", "clustered", "highd"),
                     help="point set of the --kernel-only products (kriging N=1e5 d=3, gp N=2e5 d=16, "
-                         "clustered N=1e6 d=2)")
+                         "clustered N=1e6 d=2, highd N=44484 d=41)")
     ap.add_argument("--workload", default="kriging", choices=("kriging", "clustered", "batched", "gp", "matern", "highd", "sweep"),
                     help="kriging (default, the headline line); the others print their own line")
     ap.add_argument("--max-outer", type=int, default=0,
@@ -689,7 +709,12 @@ def main() -> int:
                     help="inner CG iterations of the clustered workload (default: its 10)")
     ap.add_argument("--inner-prec", default="", choices=("", "fp32", "bf16"),
                     help="inner product precision of the clustered workload (default: its bf16)")
-    ap.add_argument("--restart", type=int, default=0, help="restart length of the clustered workload (default 200)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="restart length of the timed solve (default 100; clustered workload: 200)")
+    ap.add_argument("--gamma", type=float, default=0.0,
+                    help="clustered workload: another regulariser gamma for the same points (delta = 10 gamma)")
+    ap.add_argument("--cg-only", action="store_true",
+                    help="clustered workload: only plain FP64 CG, for --max-outer iterations")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
                     help="only K FP32 products on the workload's points plus one 256 MiB copy "
                          "(the short run used for rocprofv3 counter passes)")
@@ -715,14 +740,14 @@ def main() -> int:
         return 0
     if args.kernel_only:
         pk = {"kriging": lambda: workloads.kriging(n=args.n), "gp": workloads.gp_regression,
-              "clustered": workloads.clustered_large}[args.kernel_points]()
+              "clustered": workloads.clustered_large, "highd": workloads.regression_highd}[args.kernel_points]()
         xk = torch.from_numpy(pk.x).cuda()
         return kernel_only(api, native, workloads, torch, pk, xk, args.kernel_only, args.kernel_prec)
     p = workloads.kriging(n=args.n)
     x = torch.from_numpy(p.x).cuda()
     y = torch.from_numpy(p.y).cuda()
-    opts = dict(inner_prec="fp32", inner_maxit=p.inner_maxit, inner_tol=0.0, delta=p.delta, restart_m=100,
-                tol=p.tol, max_outer=5000, gs="cgs2")
+    opts = dict(inner_prec="fp32", inner_maxit=p.inner_maxit, inner_tol=0.0, delta=p.delta,
+                restart_m=args.restart or 100, tol=p.tol, max_outer=5000, gs="cgs2")
     paper_opts = dict(inner_prec="fp32", inner_maxit=100, inner_tol=10 * p.tol, delta=p.delta, restart_m=1000,
                       tol=p.tol, max_outer=1000, gs="cgs2")
     need = max(native.workspace_size(native.KRR_WS_FGMRES, [(p.n, p.d)], opts=api.make_opts(**o))
@@ -764,33 +789,40 @@ def main() -> int:
     ach64 = f64["pairs"] / max(f64["total_ms"], 1e-9) / 1e6
     traffic = read_traffic("kmvp_fp32_d3_kriging_counters.txt")
     probe = api.probe_issue_rates()
-    # the same rates against the published vector peaks, at the algorithmic 3d + 1
-    # FLOP per pair (d subtractions, d multiply-adds, the accumulate; the exp2 not
-    # counted): FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s
+    # Roofline of the dominant kernel against the published FP32 vector peak
+    # (157.3 TFLOP/s: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz)
+    # at the algorithmic 3d + 1 FLOP per pair (d subtractions, d multiply-adds,
+    # the accumulate; the exp2 is not counted); the FP64 product against 78.6
+    # TFLOP/s.  Beside it, the issue model of the kernel's own instruction mix
+    # (product_peak), which also prices the exponentials and the matrix-core work.
     flops_pair = 3 * p.d + 1
-    flop_frac = achieved * 1e9 * flops_pair / 157.3e12
-    flop_frac64 = ach64 * 1e9 * flops_pair / 78.6e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gpair/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "flop_frac": round(flop_frac, 4),
-                "flop_rule": f"{flops_pair} FLOP per pair (3d + 1) x pairs/s / 157.3e12 (FP32 vector peak)",
-                "fp64_flop_frac": round(flop_frac64, 4),
+    tflops = achieved * 1e9 * flops_pair / 1e12
+    tflops64 = ach64 * 1e9 * flops_pair / 1e12
+    roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
+                "frac": round(tflops / 157.3, 4), "traffic": traffic,
+                "flop_rule": f"{flops_pair} FLOP per pair (3d + 1, d = {p.d}) x pair rate; peak: published FP32 "
+                             "vector rate (packed FMA, which this build does not issue)",
                 "kernel": kname, "launches": f32["launches"],
                 "avg_launch_ms": round(f32["total_ms"] / max(f32["launches"], 1), 4),
-                "peak_rule": peak_rule,
-                "fp64_kernel": kname64, "fp64_achieved": round(ach64, 1), "fp64_peak": round(peak64 / 1e9, 1),
-                "fp64_frac": round(ach64 * 1e9 / peak64, 4),
-                "fp64_avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4),
+                "pair_rate_gpair_s": round(achieved, 1),
+                "issue_model": {"achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "Gpair/s",
+                                "frac": round(achieved / peak, 4), "rule": peak_rule},
+                "fp64": {"kernel": kname64, "achieved": round(tflops64, 3), "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": round(tflops64 / 78.6, 4), "pair_rate_gpair_s": round(ach64, 1),
+                         "issue_model_peak_gpair_s": round(peak64 / 1e9, 1),
+                         "issue_model_frac": round(ach64 * 1e9 / peak64, 4),
+                         "avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4)},
                 "issue_probe": {k: float(f"{v:.4g}") for k, v in probe.items()}}
     log(f"kernel fp32: {f32['launches']} launches, {roofline['avg_launch_ms']} ms avg, {achieved:.0f} Gpair/s "
-        f"({100 * achieved / peak:.1f}% of {peak:.0f}); fp64: {ach64:.0f} Gpair/s "
-        f"({100 * roofline['fp64_frac']:.1f}% of {peak64 / 1e9:.0f}); probe {roofline['issue_probe']}")
+        f"({100 * achieved / peak:.1f}% of {peak:.0f}; {tflops:.1f} TFLOP/s, {100 * tflops / 157.3:.1f}% of 157.3); "
+        f"fp64: {ach64:.0f} Gpair/s ({100 * ach64 * 1e9 / peak64:.1f}% of {peak64 / 1e9:.0f}; "
+        f"{100 * tflops64 / 78.6:.1f}% of 78.6 TFLOP/s); probe {roofline['issue_probe']}")
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": f"kriging-shaped N={p.n} d=3 x~U[0,10]^3 sigma=0.5 gamma=1e-3; "
-                                  "FGMRES(100) FP64 outer, 10 FP32 inner CG on K_hat+1e-2 I, tol 1e-6",
+                                  f"FGMRES({opts['restart_m']}) FP64 outer, 10 FP32 inner CG on K_hat+1e-2 I, tol 1e-6",
                       "n": p.n, "d": p.d, "parallelism": "single GPU"},
            "fgmres": {"time_to_solution_s": ms_per_step / 1e3, "outer_iters": infos[-1]["outer_iters"],
                       "inner_iters": infos[-1]["inner_iters"], "mvp64": infos[-1]["mvp64"],

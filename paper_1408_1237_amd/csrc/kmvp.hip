@@ -554,15 +554,16 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     // J + 1 from memory while it computes tile J.
     __shared__ T s_off[2][D][LDO];
     __shared__ __align__(16) T s_q[2][TILE];
-    // FP64: the table of 2^(j/N) (exp2_tab): N = 2048 (a degree-3 polynomial,
-    // one FMA fewer per pair) at d <= 3, where it measured 3% faster; N = 256
-    // above (no gain measured there, and at d = 4 the compiler then gave up a
+    // FP64: the table of 2^(j/N) (exp2_tab): N = 4096 (32 KiB; a degree-2
+    // polynomial, two FMAs fewer per pair than N = 256, relative error 2.5e-14,
+    // far below the 1e-12 bar of the products) at d <= 3; N = 256 above (larger
+    // tables measured no faster there, and at d = 4 the compiler then gave up a
     // wave per SIMD)
     constexpr bool TAB = PREC == KRR_FP64;
-    constexpr int TN = D <= 3 ? 2048 : 256;
+    constexpr int TN = D <= 3 ? 4096 : 256;
     __shared__ double s_exp2[TAB ? TN : 1];
     if constexpr (TAB) {
-        for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE2048[k];
+        for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE4096[k];
     }
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
@@ -1460,8 +1461,8 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     // Matern: ln2 q and the source constant |o'|^2 = log2(e)^2 |o|^2
     __shared__ __align__(32) T s_q2[MAT ? 2 : 1][MAT ? CH : 4];
     __shared__ T s_e[MAT ? 2 : 1][MAT ? CH : 1];
-    // FP64: the table of 2^(j/256) (exp2_tab; the 2048-entry form measured no
-    // faster here)
+    // FP64: the table of 2^(j/256) (exp2_tab; a 2048-entry form with one FMA
+    // fewer measured no faster here)
     constexpr int TN = 256;
     __shared__ double s_exp2[TAB ? TN : 1];
     if constexpr (TAB) s_exp2[threadIdx.x] = EXP2_TABLE256[threadIdx.x];

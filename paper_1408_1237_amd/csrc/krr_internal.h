@@ -73,17 +73,17 @@ __device__ __forceinline__ double exp2_f64(double a) {
     return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
 }
 
-// 2^(x / N) for the FP64 products (x = N times the exponent, N = 256 or 2048):
+// 2^(x / N) for the FP64 products (x = N times the exponent, N = 256 or 4096):
 // with n = rint(x), j = n mod N, f = x - n (exact, |f| <= 1/2),
 // 2^(x/N) = 2^((n - j)/N) 2^(j/N) 2^(f/N), the middle factor from the correctly
-// rounded table in LDS, the last a polynomial of degree 4 (N = 256) or 3
-// (N = 2048; relative errors 2e-18 and 9e-18, exp2_table.py).  x must lie in
-// int range (the caller clamps far targets); 11 or 10 instructions against 15
-// for exp2_f64.
+// rounded table in LDS, the last a polynomial of degree 4 (N = 256) or 2
+// (N = 4096; relative errors 2e-18 and 2.5e-14, exp2_table.py).  x must lie in
+// int range (the caller clamps far targets); 11 or 9 FP64 instructions against
+// 15 for exp2_f64.
 template <int N>
 __device__ __forceinline__ double exp2_tab(double x, const double *__restrict__ tab) {
-    static_assert(N == 256 || N == 2048, "table sizes of exp2_table.h");
-    constexpr int SH = N == 256 ? 8 : 11;
+    static_assert(N == 256 || N == 4096, "table sizes of exp2_table.h");
+    constexpr int SH = N == 256 ? 8 : 12;
     const double n = __builtin_rint(x);
     const double f = x - n;
     const int i = static_cast<int>(n);
@@ -93,9 +93,9 @@ __device__ __forceinline__ double exp2_tab(double x, const double *__restrict__ 
 #pragma unroll
         for (int k = 1; k < 5; ++k) p = __builtin_fma(p, f, EXP2_POLY256[k]);
     } else {
-        p = EXP2_POLY2048[0];
+        p = EXP2_POLY4096[0];
 #pragma unroll
-        for (int k = 1; k < 4; ++k) p = __builtin_fma(p, f, EXP2_POLY2048[k]);
+        for (int k = 1; k < 3; ++k) p = __builtin_fma(p, f, EXP2_POLY4096[k]);
     }
     return __builtin_amdgcn_ldexp(p * tab[i & (N - 1)], i >> SH);
 }

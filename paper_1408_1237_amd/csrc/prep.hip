@@ -154,19 +154,21 @@ __global__ __launch_bounds__(BLOCK) void k_morton(const double *__restrict__ x, 
 
 // One block per tile: anchor, offsets, radius, normaliser and weights.
 //
-// The anchor is the coordinate-wise (lower) median of the tile's points: on a
-// compact tile it sits near the centre, and on a tile that a space-filling
-// order fills with a dense group plus a few far points it stays inside the
-// group, whose offsets then stay short and keep their absolute precision when
-// rounded to FP32 or BF16 (with the bounding-box centre the group's offsets
-// would be as long as the tile, and its pairs' distances would carry that
-// rounding).
+// The anchor is the centre of the tile's bounding box, which minimises the
+// largest offset, whenever that keeps the tile narrow enough to fold its
+// exponent.  A tile too wide to fold anyway (typically a dense group plus a few
+// far points that a space-filling order put together) takes the
+// coordinate-wise (lower) median instead: it stays inside the group, whose
+// offsets then stay short and keep their absolute precision when rounded to
+// FP32 or BF16 (with the box centre the group's offsets would be as long as the
+// tile, and its pairs' distances would carry that rounding).
 __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, int64_t n, int d, int dpad,
                                                 double scale, const int32_t *__restrict__ sorted_idx,
                                                 Prepared P, int matern) {
     __shared__ double lds[TILE / WAVE];
     __shared__ double vals[TILE];
-    __shared__ double med;
+    __shared__ double s_centre[KRR_MAX_DIM];
+    __shared__ double s_median[KRR_MAX_DIM];
     const int J = blockIdx.x;
     const int64_t j = static_cast<int64_t>(J) * TILE + threadIdx.x;
     const bool real = j < n;
@@ -174,13 +176,21 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
     const int64_t t0 = static_cast<int64_t>(J) * TILE;
     const int nreal = static_cast<int>(n - t0 < TILE ? n - t0 : TILE);  // real points come first in a tile
     P.perm[j] = idx;
-    double sq64 = 0.0, sq32 = 0.0, sq16 = 0.0;
-    for (int t = 0; t < dpad; ++t) {
-        const double v = (real && t < d) ? x[static_cast<int64_t>(idx) * d + t] * scale : 0.0;
+    auto coord = [&](int t) { return (real && t < d) ? x[static_cast<int64_t>(idx) * d + t] * scale : 0.0; };
+    // pass 1: both candidate anchors, and the radius about the box centre
+    double sqc = 0.0;
+    for (int t = 0; t < d; ++t) {
+        const double v = coord(t);
+        const double lo = block_reduce(real ? v : INFINITY, MinOp(), lds);
+        const double hi = block_reduce(real ? v : -INFINITY, MaxOp(), lds);
+        const double c = 0.5 * (lo + hi);
         // rank of this point's coordinate among the tile's real points (ties by
         // position); the point of rank (nreal - 1) / 2 is the median
         vals[threadIdx.x] = v;
-        if (threadIdx.x == 0) med = v;  // replaced below (kept only if a non-finite value breaks the ranks)
+        if (threadIdx.x == 0) {
+            s_centre[t] = c;
+            s_median[t] = c;  // replaced below (kept only if a non-finite value breaks the ranks)
+        }
         __syncthreads();
         if (real) {
             int rank = 0;
@@ -188,12 +198,18 @@ __global__ __launch_bounds__(TILE) void k_tiles(const double *__restrict__ x, in
                 const double u = vals[k];
                 rank += (u < v || (u == v && k < static_cast<int>(threadIdx.x))) ? 1 : 0;
             }
-            if (rank == (nreal - 1) / 2) med = v;
+            if (rank == (nreal - 1) / 2) s_median[t] = v;
         }
-        __syncthreads();
-        const double a = (t < d) ? med : 0.0;
-        __syncthreads();  // vals and med are rewritten for the next coordinate
-        const double o = real ? v - a : 0.0;
+        __syncthreads();  // vals is rewritten for the next coordinate
+        const double o = real ? v - c : 0.0;
+        sqc += o * o;
+    }
+    const bool median = block_reduce(sqc, MaxOp(), lds) > WIDE_R2_FP32;
+    // pass 2: offsets from the chosen anchor (padding coordinates are zero)
+    double sq64 = 0.0, sq32 = 0.0, sq16 = 0.0;
+    for (int t = 0; t < dpad; ++t) {
+        const double a = t < d ? (median ? s_median[t] : s_centre[t]) : 0.0;
+        const double o = real ? coord(t) - a : 0.0;
         const float o32 = static_cast<float>(o);
         if (threadIdx.x == 0) P.anchor[static_cast<size_t>(J) * dpad + t] = a;
         P.off64[t * P.n_pad + j] = o;

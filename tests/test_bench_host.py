@@ -25,8 +25,8 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / 224)
     # FP32 d = 16: ceil(52 / 16) = 4 ops
     assert bench.product_peak(16)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
-    # FP64 d = 3: four 16x16x4 FP64 ops (64 each) + 16 x (10 x 4 + 4) (2048-entry table)
-    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 704))
+    # FP64 d = 3: four 16x16x4 FP64 ops (64 each) + 16 x (9 x 4 + 4) (4096-entry table)
+    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 640))
     # FP64 d = 8: the 256-entry table, 11 instructions
     assert bench.product_peak(8, "fp64")[0] == pytest.approx(S * 1024 / (4 * 3 * 64 + 768))
     # FP32 d = 20 runs at D = 24: ceil(74 / 16) = 5 ops; d = 41 at D = 48: 10 ops

@@ -52,7 +52,7 @@ TAB_HDR = os.path.join(os.path.dirname(__file__), "..", "paper_1408_1237_amd", "
 
 def _table_header(size: int = 256):
     src = open(TAB_HDR).read()
-    deg = {256: 4, 2048: 3}[size]
+    deg = {256: 4, 4096: 2}[size]
     poly = src[src.index(f"EXP2_POLY{size}[{deg + 1}] = {{"):]
     poly = [float(v) for v in re.findall(r"[-0-9.e+]+", poly[poly.index("{") + 1: poly.index("}")])]
     tab = src[src.index(f"EXP2_TABLE{size}[{size}] = {{"):]
@@ -99,36 +99,39 @@ def test_exp2_x256_scheme_float64():
     assert np.ldexp(1.0 * tab[i & 255], i >> 8) == 0.0
 
 
-def test_exp2_table2048_correctly_rounded_and_poly():
-    # the 2048-entry form: 2^(j/2048) rounded to nearest double, and the degree-3
-    # polynomial of 2^(f/2048) on |f| <= 1/2 evaluated exactly against mpmath
+def test_exp2_table4096_correctly_rounded_and_poly():
+    # the 4096-entry form of the products at d <= 3: 2^(j/4096) rounded to
+    # nearest double, and the degree-2 polynomial of 2^(f/4096) on |f| <= 1/2
+    # evaluated exactly against mpmath: 2.5e-14 relative, within a factor 1.2 of
+    # the degree-2 minimax bound h^3 / 24 (h = ln 2 / 8192)
     import mpmath as mp
     mp.mp.dps = 50
-    poly, tab = _table_header(2048)
-    assert len(poly) == 4 and poly[-1] == 1.0 and len(tab) == 2048
-    for j in range(0, 2048, 7):
-        assert tab[j] == float(mp.power(2, mp.mpf(j) / 2048))
-    assert tab[2047] == float(mp.power(2, mp.mpf(2047) / 2048))
+    poly, tab = _table_header(4096)
+    assert len(poly) == 3 and len(tab) == 4096
+    for j in range(0, 4096, 11):
+        assert tab[j] == float(mp.power(2, mp.mpf(j) / 4096))
+    assert tab[4095] == float(mp.power(2, mp.mpf(4095) / 4096))
     worst = 0.0
     for k in range(2001):
         f = Fraction(-1, 2) + Fraction(k, 2000)
         p = Fraction(0)
         for v in poly:
             p = p * f + Fraction(v)
-        ref = mp.power(2, mp.mpf(f.numerator) / f.denominator / 2048)
+        ref = mp.power(2, mp.mpf(f.numerator) / f.denominator / 4096)
         worst = max(worst, float(abs(mp.mpf(p.numerator) / p.denominator / ref - 1)))
-    assert worst < 2e-17
+    h = np.log(2.0) / 8192
+    assert 0.5 * h ** 3 / 24 < worst < 1.2 * h ** 3 / 24 and worst < 3e-14
 
 
-def test_exp2_x2048_scheme_float64():
-    # 2^(x/2048) = 2^((n - j)/2048) 2^(j/2048) p(x - n) in float64 against mpmath,
-    # including the clamp value -2000 * 2048 (result 0)
+def test_exp2_x4096_scheme_float64():
+    # 2^(x/4096) = 2^((n - j)/4096) 2^(j/4096) p(x - n) in float64 against mpmath,
+    # including the clamp value -2000 * 4096 (result 0)
     import mpmath as mp
     mp.mp.dps = 40
-    poly, tab = _table_header(2048)
-    rng = np.random.default_rng(4)
-    xs = np.concatenate([rng.uniform(-1100 * 2048, 256 * 2048, 3000), rng.uniform(-4096, 4096, 1000),
-                         np.arange(-300, 300) + 0.5, [0.0, -0.5, 0.5, 2047.5, -2048.5]])
+    poly, tab = _table_header(4096)
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.uniform(-1100 * 4096, 256 * 4096, 3000), rng.uniform(-8192, 8192, 1000),
+                         np.arange(-300, 300) + 0.5, [0.0, -0.5, 0.5, 4095.5, -4096.5]])
     worst = 0.0
     for x in xs:
         n = np.rint(x)
@@ -137,11 +140,11 @@ def test_exp2_x2048_scheme_float64():
         p = poly[0]
         for c in poly[1:]:
             p = p * f + c
-        got = np.ldexp(p * tab[i & 2047], i >> 11)
-        want = mp.power(2, mp.mpf(float(x)) / 2048)
+        got = np.ldexp(p * tab[i & 4095], i >> 12)
+        want = mp.power(2, mp.mpf(float(x)) / 4096)
         if want < mp.mpf(2) ** -1000:
             continue
         worst = max(worst, float(abs(mp.mpf(float(got)) / want - 1)))
-    assert worst < 5e-16
-    i = -2000 * 2048
-    assert np.ldexp(1.0 * tab[i & 2047], i >> 11) == 0.0
+    assert worst < 3e-14
+    i = -2000 * 4096
+    assert np.ldexp(1.0 * tab[i & 4095], i >> 12) == 0.0
