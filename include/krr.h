@@ -197,7 +197,7 @@ int kmvp_gauss(const krr_points *pts /* host */, double sigma, double shift, int
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product, y = K_hat q + shift q, with the same arguments except the workspace,
  * which is a fixed static device array of krr_noalloc_scratch_bytes() bytes
- * (64 MiB) that every device the library runs on holds until the process ends.
+ * (128 MiB) that every device the library runs on holds until the process ends.
  * Nothing is allocated or freed, no launch shape is tuned (the tuned shape of
  * an earlier kmvp_gauss call on the same shape, else the default one; the result
  * does not depend on it) and nothing is synchronised.  Every call on a device

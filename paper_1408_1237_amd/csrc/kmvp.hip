@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "krr_internal.h"
@@ -22,14 +23,13 @@
 
 namespace krr {
 
-// Block index remap: consecutive hardware block ids are dealt round-robin to
-// the 8 XCDs; give each XCD a contiguous range of logical blocks so that the
-// blocks sharing a column range (and its source data in L2) run on one XCD.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int tall = nb / 8, extra = nb % 8;
-    const int xcd = b % 8, local = b / 8;
-    return xcd < extra ? xcd * (tall + 1) + local : extra * (tall + 1) + (xcd - extra) * tall + local;
-}
+// Block order: the hardware deals consecutive block ids round-robin to the 8
+// XCDs, and the products keep that order (block id = row tile + row tiles x
+// column split).  Their source data is a few MB (it sits in every XCD's L2
+// either way) and they are bound by arithmetic, so the round-robin deal, which
+// spreads dense and sparse row tiles over all XCDs, beats giving each XCD a
+// contiguous range of row tiles: measured 4-5% faster on uniform points and
+// 14-16% on clustered ones, whose row tiles carry very different work.
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -104,6 +104,7 @@ struct KArgs {
     const double *sq;  // |o_j|^2 of the FP64 offsets (Matern matrix-core form)
     const void *q;
     const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
+    const void *w;   // w_j in the arithmetic type (symmetric product: the source terms)
     void *out;
     double shift;    // square products only
     int square;
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp(KArgs a, const typename Prec<PRE
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
     const int64_t n_pad = a.n_pad;
 
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_matern(KArgs a, const typename P
     constexpr int U = unroll_cols<D, PREC>();
     constexpr double LOG2E = 1.4426950408889634074;
     const int64_t n_pad = a.n_pad;
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_hd(KArgs a, const typename Prec<
     static_assert(D <= WAVE && TILE % UC == 0, "one anchor coordinate per lane; whole groups per tile");
     constexpr double LOG2E = 1.4426950408889634074;
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int64_t i = static_cast<int64_t>(bx) * BLOCK + threadIdx.x;
     const int lane = threadIdx.x % WAVE;
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
     const int64_t n_pad = a.n_pad;
 
     const int nrb = a.nrowblocks * HB;
-    const int lb = xcd_remap(blockIdx.x, nrb * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bh = lb % nrb, by = lb / nrb;
     const int bx = bh / HB;  // row tile
     const int tid = threadIdx.x;
@@ -818,6 +819,370 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mg(KArgs a) {
         atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * (BLOCK / HB));
 }
 
+// ---------------------------------------------------------------- symmetric FP64 product
+//
+// K_hat is symmetric, so one exponential serves both of its terms: k_ij q_j in
+// y_i and k_ij q_i in y_j.  The tiles are cut into groups of gs = a.gtiles
+// consecutive tiles; block (R, C), R <= C, takes the tile pairs (I, J) with I
+// in group R, J in group C and I < J, evaluating each pair once for both
+// directions, plus on the diagonal (R == C) the tiles I == J one-sided.  The
+// exponents are those of k_kmvp_mg with the operands exchanged: the targets
+// form the A operand of v_mfma_f64_16x16x4f64 (rows in the order 0, 4, 8, 12,
+// 1, 5, ...) and the sources the B operand, so lane l holds source l % 16 of
+// the step against targets 4 (l / 16) + v of each target group.  The terms
+// for the targets then accumulate per lane over the whole column loop (summed
+// over the 16 source lanes once per row tile); those for the sources are
+// summed per step over the lane's 16 targets, over the 4 lane rows by two
+// cross-lane steps and over the 4 waves in LDS once per tile pair.  On folded
+// tiles the exponent lacks the source factor w_j = 2^(N_J - |o_j|^2), which the
+// source terms take once per tile pair (the target terms read q_j w_j).
+//
+// Partial sums: slot g of row i (a.out[g n_pad + i], a.ngroups slots) is
+// written by exactly one block: for i in group X, block (X, g) when g > X (its
+// target terms), block (g, X) when g < X (its source terms) and block (X, X)
+// (both).  A block clears its source-side slots first; every later change of
+// an entry comes from the thread that cleared it, so the sums are formed in a
+// fixed order, independent of the launch.
+// v + v of lane l ^ 32 (v_permlane32_swap on both halves of the double): the
+// same sum, in the same order, in both lanes
+__device__ __forceinline__ double join64(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double sum_halves32(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(b), hi = static_cast<unsigned>(b >> 32);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return join64(l[0], h[0]) + join64(l[1], h[1]);
+}
+// v + v of lane l ^ 16 (v_permlane16_swap: rows of 16 lanes), likewise
+__device__ __forceinline__ double sum_rows16(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(b), hi = static_cast<unsigned>(b >> 32);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return join64(l[0], h[0]) + join64(l[1], h[1]);
+}
+
+// Largest group (tiles) of the symmetric product's launch (kmvp_sym_group_tiles
+// stays below it up to 6.7e7 points).
+constexpr int MS_MAX_GROUP_TILES = 512;
+
+template <int D>
+constexpr bool ms_supported() {
+    return D <= 12;
+}
+
+template <int D>
+__global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using M = MG<KRR_FP64>;
+    using T = double;
+    using V4 = doublex4_t;
+    constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
+    constexpr int RG = 4;            // groups of 16 targets per wave
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int LDO = TILE + 16;
+    constexpr int TN = D <= 3 ? 4096 : 256;  // exp2_tab table (as k_kmvp_mg)
+    // target offsets kept in registers at small d, else re-read per tile pair
+    constexpr bool KEEP = D <= 4;
+    __shared__ T s_off[2][D][LDO];
+    __shared__ __align__(16) T s_q[2][TILE];
+    __shared__ double s_exp2[TN];
+    // per wave: the source terms of the current tile pair (and, at the end of a
+    // row tile, the block's target terms)
+    __shared__ T s_z[NW * TILE];
+    // the column tiles of group C not far from the current row tile
+    __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
+    for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE4096[k];
+    const T *__restrict__ off = static_cast<const T *>(a.off);
+    const T *__restrict__ row_off = static_cast<const T *>(a.row_off);
+    const T *__restrict__ q = static_cast<const T *>(a.q);
+    const T *__restrict__ qw = static_cast<const T *>(a.qw);
+    const T *__restrict__ wsrc = static_cast<const T *>(a.w);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const int64_t n_pad = a.n_pad;
+    const int ng = a.ngroups, gs = a.gtiles;
+
+    // block -> group pair (R, C): the ng (ng - 1) / 2 off-diagonal pairs first
+    // (row-major over R < C; pair row R starts at R (2 ng - R - 1) / 2), then
+    // the ng diagonal ones, which carry about half the work.  Consecutive
+    // blocks go to different XCDs: where far tile pairs are skipped the work
+    // sits near the diagonal, a few blocks of every row, and contiguous ranges
+    // per XCD (rows of very different lengths) would load them unevenly.
+    const int nb_off = ng * (ng - 1) / 2;
+    const int b = blockIdx.x;
+    int R, C;
+    if (b < nb_off) {
+        const double m = 2.0 * ng - 1.0;
+        int r = static_cast<int>(0.5 * (m - sqrt(m * m - 8.0 * b)));
+        r = r < 0 ? 0 : (r > ng - 2 ? ng - 2 : r);
+        while (r > 0 && r * (2 * ng - r - 1) / 2 > b) --r;
+        while ((r + 1) * (2 * ng - r - 2) / 2 <= b) ++r;
+        R = r;
+        C = r + 1 + (b - r * (2 * ng - r - 1) / 2);
+    } else {
+        R = C = b - nb_off;
+    }
+    const bool diag = R == C;
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const int r16 = lane % 16, g = lane / 16;
+    const int asrc = (r16 % 4) * 4 + r16 / 4;  // target of A row r16 within a group of 16
+    const int I0 = R * gs, I1 = min(a.ntiles, I0 + gs);
+    const int C0 = C * gs, C1 = min(a.ntiles, C0 + gs);
+    T *__restrict__ zslot = out + static_cast<int64_t>(R) * n_pad;  // source terms of the tiles of group C
+    T *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;  // target terms of the tiles of group R
+    for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = T(0);
+
+    T st_o[D], st_q;
+    auto stage_load = [&](int J) {
+        const int64_t j = static_cast<int64_t>(J) * TILE + tid;
+#pragma unroll
+        for (int k = 0; k < D; ++k) st_o[k] = off[k * n_pad + j];
+        st_q = a.tile_r2[J] > WIDE_R2_FP64 ? q[j] : qw[j];
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) s_off[buf][k][tid] = st_o[k];
+        s_q[buf][tid] = st_q;
+    };
+    // the source terms of one step (lane-local sum zl over the lane's targets):
+    // summed over the 4 lane rows (the same sum, in the same order, in each;
+    // all four lanes store it)
+    auto emit_z = [&](T zl, int cb) {
+        zl = sum_halves32(sum_rows16(zl));
+        s_z[wv * TILE + cb + r16] = zl;
+    };
+    int skipped = 0;
+    for (int I = I0; I < I1; ++I) {
+        const int64_t row0 = static_cast<int64_t>(I) * TILE + wv * (16 * RG);
+        double aI[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(I) * D + k];
+        const double rI = a.row_r2 != nullptr ? sqrt(a.row_r2[I]) : INFINITY;  // null: no skipping
+        // which column tiles are live: one thread per tile
+        const int Js = diag ? I : C0;
+        for (int jj = tid; jj < C1 - Js; jj += BLOCK) {
+            const int Jt = Js + jj;
+            s_live[jj] = tiles_far<D>(aI, rI, a.anchor + static_cast<int64_t>(Jt) * D, a.tile_far64[Jt]) ? 0 : 1;
+        }
+        __syncthreads();
+        auto next_live = [&](int J) {
+            while (J < C1 && s_live[J - Js] == 0) ++J;
+            return J;
+        };
+        int J = next_live(Js);
+        skipped += J - Js;
+        if (J >= C1) {
+            // no live column tile: zero target terms (the source-side slots stay as they are)
+            const int64_t i = static_cast<int64_t>(I) * TILE + tid;
+            if (!diag) yslot[i] = T(0);
+            __syncthreads();  // s_live is rewritten for the next row tile
+            continue;
+        }
+        T oi[KEEP ? RG : 1][KEEP ? D : 1];
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                for (int k = 0; k < D; ++k) oi[rg][k] = row_off[k * a.n_pad_rows + row0 + rg * 16 + asrc];
+        }
+        // q of the lane's output targets (unweighted; 0 on the padding)
+        V4 qt[RG], acc[RG];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = row0 + rg * 16 + 4 * g + v;
+                qt[rg][v] = i < a.n_rows ? q[i] : T(0);
+            }
+            acc[rg] = V4{T(0), T(0), T(0), T(0)};
+        }
+        {
+            stage_load(J);
+            stage_store(0);
+        }
+        __syncthreads();
+        int buf = 0;
+        while (J < C1) {
+            const int Jn = next_live(J + 1);
+            skipped += Jn - J - 1;
+            if (Jn < C1) stage_load(Jn);
+            const double r2 = a.tile_r2[J];
+            const double nj = a.tile_nj[J];
+            const double *__restrict__ aJ = a.anchor + static_cast<int64_t>(J) * D;
+            auto tile = [&](auto sym_c) {
+                constexpr bool SYM = decltype(sym_c)::value;
+                if (r2 <= WIDE_R2_FP64) {
+                    // A operand: [2t, c, 0...] of target asrc(r16) of group rg, scaled by TN
+                    T bval[RG][DK];
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg) {
+                        T t[D];
+                        double tt = 0.0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            T o;
+                            if constexpr (KEEP)
+                                o = oi[rg][k];
+                            else
+                                o = row_off[k * a.n_pad_rows + row0 + rg * 16 + asrc];
+                            t[k] = (aI[k] - aJ[k]) + o;
+                            tt = __builtin_fma(t[k], t[k], tt);
+                        }
+                        // a target whose every exponent against the tile is <= -1100
+                        // gets -2000 for the whole tile (exp2 is 0 either way)
+                        const bool far = tt > static_cast<double>(a.tile_far64[J]);
+                        const T c = far ? T(-2000.0 * TN) : (-tt - nj) * T(TN);
+#pragma unroll
+                        for (int kc = 0; kc < DK; ++kc) {
+                            const int dim = 4 * kc + g;
+                            T v = (dim == D) ? c : T(0);
+#pragma unroll
+                            for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2 * TN) * t[k]) : v;
+                            bval[rg][kc] = v;
+                        }
+                    }
+                    auto load_step = [&](int cb, T (&av)[DK], T &qs) {
+#pragma unroll
+                        for (int kc = 0; kc < DK; ++kc) {
+                            const int dim = 4 * kc + g;
+                            if (4 * kc + 3 < D) {
+                                av[kc] = s_off[buf][dim][cb + r16];
+                            } else {
+                                const T o = s_off[buf][min(dim, D - 1)][cb + r16];
+                                av[kc] = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
+                            }
+                        }
+                        qs = s_q[buf][cb + r16];
+                    };
+                    auto exponents = [&](const T (&av)[DK], V4 (&G)[RG]) {
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg) {
+                            G[rg] = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+                            for (int kc = 0; kc < DK; ++kc) G[rg] = M::mfma(bval[rg][kc], av[kc], G[rg]);
+                        }
+                    };
+                    auto accumulate = [&](const V4 (&G)[RG], T qs, int cb) {
+                        T zl = T(0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+#pragma unroll
+                            for (int rg = 0; rg < RG; ++rg) {
+                                const T e = exp2_tab<TN>(G[rg][v], s_exp2);
+                                acc[rg][v] = M::fma(e, qs, acc[rg][v]);
+                                if constexpr (SYM) zl = M::fma(e, qt[rg][v], zl);
+                            }
+                        if constexpr (SYM) emit_z(zl, cb);
+                    };
+                    // software pipeline over the 16 column steps (as k_kmvp_mg)
+                    T av[2][DK], qs[2];
+                    V4 G[2][RG];
+                    load_step(0, av[0], qs[0]);
+                    exponents(av[0], G[0]);
+#pragma unroll
+                    for (int st = 1; st < TILE / 16; ++st) {
+                        load_step(st * 16, av[st & 1], qs[st & 1]);
+                        exponents(av[st & 1], G[st & 1]);
+                        accumulate(G[(st - 1) & 1], qs[(st - 1) & 1], (st - 1) * 16);
+                    }
+                    accumulate(G[(TILE / 16 - 1) & 1], qs[(TILE / 16 - 1) & 1], TILE - 16);
+                } else {
+                    // wide tile: the direct form, in chunks of 4 column steps, one
+                    // output target at a time (few registers: wide tiles are rare)
+#pragma unroll 1
+                    for (int ch = 0; ch < TILE / 64; ++ch) {
+                        T zs[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 1
+                        for (int rv = 0; rv < 4 * RG; ++rv) {
+                            const int rg = rv / 4, v = rv % 4;
+                            const int64_t i = row0 + rg * 16 + 4 * g + v;
+                            T t[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) t[k] = (aI[k] - aJ[k]) + row_off[k * a.n_pad_rows + i];
+                            const T qi = i < a.n_rows ? q[i] : T(0);
+                            T sacc = T(0);
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4) {
+                                const int cj = (4 * ch + s4) * 16 + r16;
+                                T ss = T(0);
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    const T dd = t[k] - s_off[buf][k][cj];
+                                    ss = M::fma(dd, dd, ss);
+                                }
+                                const T e = exp2_tab<TN>(__builtin_fmax(-ss * TN, -2000.0 * TN), s_exp2);
+                                sacc = M::fma(e, s_q[buf][cj], sacc);
+                                if constexpr (SYM) zs[s4] = M::fma(e, qi, zs[s4]);
+                            }
+                            // into acc[rg][v] (rg, v vary at run time here)
+#pragma unroll
+                            for (int ra = 0; ra < RG; ++ra)
+#pragma unroll
+                                for (int va = 0; va < 4; ++va) acc[ra][va] += (ra == rg && va == v) ? sacc : T(0);
+                        }
+                        if constexpr (SYM) {
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4) emit_z(zs[s4], (4 * ch + s4) * 16);
+                        }
+                    }
+                }
+            };
+            const bool sym = J != I;
+            // the slot entry this thread adds the tile pair's source terms to (its
+            // own earlier store; read before the compute to hide the latency)
+            const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
+            const T zold = sym ? zslot[jz] : T(0);
+            const T wj = (sym && r2 <= WIDE_R2_FP64) ? wsrc[jz] : T(1);
+            if (sym)
+                tile(std::true_type{});
+            else
+                tile(std::false_type{});
+            if (Jn < C1) stage_store(buf ^ 1);
+            __syncthreads();
+            if (sym) {
+                // the tile pair's source terms: summed over the waves, times w_j on a folded tile
+                const T z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
+                zslot[jz] = zold + z * wj;
+                __syncthreads();  // s_z is rewritten by the next tile pair
+            }
+            buf ^= 1;
+            J = Jn;
+        }
+        // the row tile's target terms: summed over the 16 source lanes; lane
+        // column 0 holds targets rg 16 + 4 g + v of the wave
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T x = acc[rg][v];
+                x += __shfl_xor(x, 1, WAVE);
+                x += __shfl_xor(x, 2, WAVE);
+                x += __shfl_xor(x, 4, WAVE);
+                x += __shfl_xor(x, 8, WAVE);
+                acc[rg][v] = x;
+            }
+        if (r16 == 0) {
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) s_z[wv * (16 * RG) + rg * 16 + 4 * g + v] = acc[rg][v];
+        }
+        __syncthreads();
+        const int64_t i = static_cast<int64_t>(I) * TILE + tid;
+        if (diag)
+            yslot[i] += s_z[tid];
+        else
+            yslot[i] = s_z[tid];
+        __syncthreads();
+    }
+    // both directions of every skipped tile pair (rows x column tiles)
+    if (a.skip_count != nullptr && tid == 0 && skipped > 0)
+        atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * 2 * TILE);
+}
+
 // ---------------------------------------------------------------- split-f16 matrix-core exponent
 //
 // FP32 and BF16 products with the folded exponent formed by the f16 matrix
@@ -897,7 +1262,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     const float *__restrict__ qw = static_cast<const float *>(a.qw);
     const int64_t n_pad = a.n_pad;
 
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int tid = threadIdx.x;
     const int lane = tid % WAVE;
@@ -1203,7 +1568,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
     const half8_t *__restrict__ slots = static_cast<const half8_t *>(a.slots);
     const int64_t n_pad = a.n_pad;
 
-    const int lb = xcd_remap(blockIdx.x, a.nrowblocks * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks, by = lb / a.nrowblocks;
     const int tid = threadIdx.x;
     const int lane = tid % WAVE;
@@ -1473,7 +1838,7 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mgw(KArgs a) {
     const int64_t n_pad = a.n_pad;
 
     const int nrb = a.nrowblocks * HB;
-    const int lb = xcd_remap(blockIdx.x, nrb * a.splits);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bh = lb % nrb, by = lb / nrb;
     const int bx = bh / HB;  // row tile
     const int tid = threadIdx.x;
@@ -1721,6 +2086,30 @@ int kmvp_ngroups(const Prepared &C) {
 // Column splits (blocks per row tile): from 1 to the group count.
 int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
+// The symmetric FP64 product (k_kmvp_ms): Gaussian point sets up to the
+// compiled dimension 12, groups of gs tiles with gs fixed by the tile count, so
+// that the summation order does not depend on tuning: about 100 groups up to
+// 1000 tiles, groups of 10 tiles above (clustered sets skip most tile pairs, and
+// small groups leave enough blocks with work), and at most about 512 groups
+// (the partial sums hold one slot per group and point).
+static bool sym_capable(const Prepared &P) {
+    return P.kernel == KRR_KERNEL_GAUSS && P.dpad <= 12 && P.ntiles <= 512 * MS_MAX_GROUP_TILES;
+}
+int kmvp_sym_group_tiles(const Prepared &P) {
+    const int a = (P.ntiles + 99) / 100, b = (P.ntiles + 511) / 512;
+    const int gs = a < 10 ? a : 10;
+    return gs > b ? gs : b;
+}
+int kmvp_sym_ngroups(const Prepared &P) {
+    const int gs = kmvp_sym_group_tiles(P);
+    return (P.ntiles + gs - 1) / gs;
+}
+// Partial-sum slots of a square product's scratch (either layout).
+int kmvp_parts_slots(const Prepared &P) {
+    const int a = kmvp_ngroups(P), b = sym_capable(P) ? kmvp_sym_ngroups(P) : 0;
+    return a > b ? a : b;
+}
+
 static KmvpPlan plan_for(const Prepared &P, int splits) {
     KmvpPlan pl;
     const int ng = kmvp_ngroups(P), gt = kmvp_group_tiles(P);
@@ -1803,13 +2192,13 @@ KmvpPlan kmvp_plan(const Prepared &P, int prec) {
 }
 
 size_t kmvp_scratch_bytes(const Prepared &P) {
-    const size_t parts = static_cast<size_t>(kmvp_max_splits(P)) * P.n_pad * 8;
+    const size_t parts = static_cast<size_t>(kmvp_parts_slots(P)) * P.n_pad * 8;
     return align_up(parts, 256) + align_up(static_cast<size_t>(P.n_pad) * 8, 256);
 }
 
 KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P) {
     KmvpScratch k;
-    k.parts = cv.take<double>(static_cast<size_t>(kmvp_max_splits(P)) * P.n_pad);
+    k.parts = cv.take<double>(static_cast<size_t>(kmvp_parts_slots(P)) * P.n_pad);
     k.qw = cv.take<double>(P.n_pad);
     return k;
 }
@@ -1828,6 +2217,13 @@ static bool use_valu_kernel() {
 static bool use_tile_skip() {
     const char *v = std::getenv("KRR_NO_TILE_SKIP");
     return !(v && v[0] == '1');
+}
+// KRR_KMVP_SYM=0 keeps FP64 products one-sided (used to cross-check the
+// symmetric kernel); so do KRR_KMVP_VALU=1 and KRR_KMVP_SPLITS
+static bool use_sym_kernel(const Prepared &P, int prec) {
+    if (prec != KRR_FP64 || !sym_capable(P) || use_valu_kernel() || std::getenv("KRR_KMVP_SPLITS")) return false;
+    const char *v = std::getenv("KRR_KMVP_SYM");
+    return !(v && v[0] == '0');
 }
 static bool use_fp32_matrix_kernel() {
     const char *v = std::getenv("KRR_KMVP_MG32");
@@ -1908,6 +2304,29 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int D>
+static hipError_t launch_kmvp_sym(const KArgs &a, hipStream_t s) {
+    if constexpr (ms_supported<D>()) {
+        const int nb = a.ngroups * (a.ngroups + 1) / 2;
+        hipLaunchKernelGGL((k_kmvp_ms<D>), dim3(nb), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_kmvp_sym_d(int dpad, const KArgs &a, hipStream_t s) {
+    switch (dpad) {
+        case 1: return launch_kmvp_sym<1>(a, s);
+        case 2: return launch_kmvp_sym<2>(a, s);
+        case 3: return launch_kmvp_sym<3>(a, s);
+        case 4: return launch_kmvp_sym<4>(a, s);
+        case 6: return launch_kmvp_sym<6>(a, s);
+        case 8: return launch_kmvp_sym<8>(a, s);
+        case 12: return launch_kmvp_sym<12>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int PREC>
 static hipError_t launch_kmvp_d(int dpad, const KArgs &a, int kernel, hipStream_t s) {
     switch (dpad) {
@@ -1933,6 +2352,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
                            const void *q, void *y, const KmvpScratch &sc, const int *active, bool timed_slot,
                            hipStream_t s) {
     const bool square = (&R == &C);
+    // the symmetric FP64 kernel for square products (plan.sym_gs > 0)
+    const bool sym = square && pl.sym_gs > 0 && prec == KRR_FP64;
     KArgs a;
     a.n_rows = R.n;
     a.n_pad_rows = R.n_pad;
@@ -1942,8 +2363,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.ntiles = C.ntiles;
     a.splits = pl.splits;
     a.tps = pl.tiles_per_split;
-    a.gtiles = kmvp_group_tiles(C);
-    a.ngroups = kmvp_ngroups(C);
+    a.gtiles = sym ? pl.sym_gs : kmvp_group_tiles(C);
+    a.ngroups = sym ? (C.ntiles + pl.sym_gs - 1) / pl.sym_gs : kmvp_ngroups(C);
     a.anchor = C.anchor;
     a.tile_r2 = C.tile_r2;
     a.tile_nj = C.tile_nj;
@@ -1958,10 +2379,12 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.active = active;
     a.row_r2 = use_tile_skip() ? R.tile_r2 : nullptr;
     a.skip_count = nullptr;
-    a.out = a.ngroups > 1 ? sc.parts : y;
+    const bool use_parts = a.ngroups > 1 || sym;
+    a.out = use_parts ? sc.parts : y;
     const void *w = prec == KRR_FP64 ? static_cast<const void *>(C.w64)
                     : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
                                        : static_cast<const void *>(C.w16);
+    a.w = w;
     const dim3 gc((C.n_pad + BLOCK - 1) / BLOCK), gr((R.n_pad + BLOCK - 1) / BLOCK);
     if (C.kernel == KRR_KERNEL_GAUSS) {  // the Matern product reads q itself
         switch (prec) {
@@ -1982,7 +2405,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
             a.off = C.off64;
             a.pm = C.pm64;
             a.row_off = R.off64;
-            e = launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_d(C.dpad, a, s) : launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
             break;
         case KRR_FP32:
             a.off = C.off32;
@@ -2000,7 +2423,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     }
     KRR_HIP(e);
     if (timed) KRR_HIP(hipEventRecord(ev1, s));
-    if (a.ngroups > 1) {
+    if (use_parts) {
         const int sq = square ? 1 : 0;
         const int ng = a.ngroups;
         switch (prec) {
@@ -2024,7 +2447,12 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
 
 hipError_t kmvp_sorted(const Prepared &P, int prec, double shift, const void *q, void *y, const KmvpScratch &sc,
                        const int *active, hipStream_t s) {
-    return kmvp_run(P, P, prec, kmvp_plan(P, prec), shift, q, y, sc, active, true, s);
+    KmvpPlan pl;
+    if (use_sym_kernel(P, prec))
+        pl.sym_gs = kmvp_sym_group_tiles(P);
+    else
+        pl = kmvp_plan(P, prec);
+    return kmvp_run(P, P, prec, pl, shift, q, y, sc, active, true, s);
 }
 
 // Rectangular product y = K_hat(targets, sources) q on sorted vectors (targets
@@ -2056,6 +2484,7 @@ hipError_t kmvp_tune(const Prepared &P, int prec, const void *q, void *y, const 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
         return hipSuccess;
+    if (use_sym_kernel(P, prec)) return hipSuccess;  // its launch shape is fixed
     const TuneKey key{prec + 16 * P.kernel, P.dpad, P.ntiles};  // kernel type in the key
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

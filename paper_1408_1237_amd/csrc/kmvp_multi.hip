@@ -21,12 +21,6 @@ namespace krr {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int xcd_remap_m(int b, int nb) {
-    const int tall = nb / 8, extra = nb % 8;
-    const int xcd = b % 8, local = b / 8;
-    return xcd < extra ? xcd * (tall + 1) + local : extra * (tall + 1) + (xcd - extra) * tall + local;
-}
-
 template <int PREC>
 struct MP;
 template <>
@@ -539,7 +533,7 @@ static bool multi_use_h(int dpad, int prec) {
 
 template <int D, int PREC, bool H>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_multi(MArgs a) {
-    const int lb = xcd_remap_m(blockIdx.x, a.nrowblocks * a.splits * a.nrb);
+    const int lb = static_cast<int>(blockIdx.x);
     const int bx = lb % a.nrowblocks;
     const int rest = lb / a.nrowblocks;
     multi_select<D, PREC, H>(a, bx, rest % a.splits, rest / a.splits);

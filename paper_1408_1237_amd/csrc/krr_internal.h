@@ -182,15 +182,17 @@ hipError_t scatter_sorted(const Prepared &P, const Tin *src, Tout *dst, hipStrea
 struct KmvpPlan {
     int splits = 1;          // column splits
     int tiles_per_split = 0;
+    int sym_gs = 0;          // > 0: the symmetric FP64 kernel with groups of sym_gs tiles
 };
-// Scratch of one product: group partial sums (kmvp_max_splits = group count x
-// n_pad, 8 bytes each)
+// Scratch of one product: group partial sums (kmvp_parts_slots x n_pad, 8
+// bytes each)
 // and the prescaled sources q_j w_j (n_pad, 8 bytes each).
 struct KmvpScratch {
     void *parts = nullptr;
     void *qw = nullptr;
 };
 int kmvp_max_splits(const Prepared &P);
+int kmvp_parts_slots(const Prepared &P);
 KmvpPlan kmvp_plan(const Prepared &P, int prec);  // tuned, else a heuristic
 size_t kmvp_scratch_bytes(const Prepared &P);
 KmvpScratch carve_kmvp_scratch(Carver &cv, const Prepared &P);

@@ -12,7 +12,7 @@ int kmvp_gauss_on_scratch(const krr_points *pts, double sigma, double shift, int
 
 namespace {
 
-constexpr size_t kScratchBytes = static_cast<size_t>(64) << 20;  // 64 MiB
+constexpr size_t kScratchBytes = static_cast<size_t>(128) << 20;  // 128 MiB
 
 // Held by every device the library runs on until the process ends.  Host code
 // never uses this name as an address (it is a host-side stand-in): it takes the

@@ -217,10 +217,58 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
         monkeypatch.setenv("KRR_KMVP_SPLITS", k)
         outs.append(_gpu_mvp(x, sigma, q, 0.01, prec))
     monkeypatch.delenv("KRR_KMVP_SPLITS")
-    outs.append(_gpu_mvp(x, sigma, q, 0.01, prec))
+    default = _gpu_mvp(x, sigma, q, 0.01, prec)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    check(outs[0], oracle.mvp(x, sigma, call_vector(q, prec), shift=0.01), prec)
+    if prec == "fp64" and d <= 12:
+        # the default FP64 product is the symmetric kernel: its own fixed
+        # summation order and tile anchors (equal to the exponential's 2.5e-14
+        # per term, and the same on every call)
+        assert _relerr(default, outs[0]) <= 1e-13
+        assert np.array_equal(default, _gpu_mvp(x, sigma, q, 0.01, prec))
+    else:
+        assert np.array_equal(default, outs[0])
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.01)
+    check(outs[0], want, prec)
+    check(default, want, prec)
+
+
+# The symmetric FP64 product (one exponential per pair for both of its terms)
+# against the one-sided kernel (KRR_KMVP_SYM=0) and the oracle: single and
+# ragged tiles, one tile per group (up to 100 tiles) and several, every
+# compiled dimension up to 12.
+@pytest.mark.parametrize("n,d", [(1, 3), (2, 2), (255, 3), (256, 1), (257, 4), (2000, 2), (2000, 6),
+                                 (9000, 3), (26000, 3), (30000, 8), (12000, 12), (40000, 1)])
+def test_symmetric_fp64_product(monkeypatch, n, d):
+    x = workloads.random_points(500 + d, n, d, 2.0 * d ** 0.5, kind="normal")
+    q = workloads.random_vector(501 + d, n)
+    sigma = 0.7 * np.sqrt(d)
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    y = _gpu_mvp(x, sigma, q, 0.02, "fp64")
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    y1 = _gpu_mvp(x, sigma, q, 0.02, "fp64")
+    monkeypatch.delenv("KRR_KMVP_SYM")
+    # each pair's exponential is taken against another tile anchor (the table
+    # exponential's 2.5e-14 per term)
+    assert _relerr(y, y1) <= 1e-13
+    if n <= 12000:
+        check(y, oracle.mvp(x, sigma, q, shift=0.02), "fp64", what=(n, d))
+    else:
+        rows = np.random.default_rng(n).choice(n, 64, replace=False)
+        check(y[rows], oracle.mvp_rows(x, sigma, q, rows, shift=0.02), "fp64", what=(n, d))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_symmetric_fp64_product_wide_tiles(d):
+    # 700 points spread over a box hundreds of bandwidths wide: every tile is
+    # wider than the FP64 fold limit (direct form in both directions), most
+    # pairs underflow, a few neighbours remain
+    rng = np.random.default_rng(90 + d)
+    x = rng.uniform(0.0, 300.0, size=(700, d))
+    x[350:360] = x[349] + rng.normal(0.0, 0.5, size=(10, d))  # a small dense group inside a wide tile
+    q = workloads.random_vector(91 + d, 700)
+    y = _gpu_mvp(x, 1.0, q, 0.01, "fp64")
+    check(y, oracle.mvp(x, 1.0, q, shift=0.01), "fp64", what=d)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])

@@ -35,9 +35,9 @@ def test_noalloc_matches_workspace_entry_point(prec):
     lib = native.load()
     lib.kmvp_gauss_noalloc.restype = ctypes.c_int
     lib.krr_noalloc_scratch_bytes.restype = ctypes.c_size_t
-    assert lib.krr_noalloc_scratch_bytes() == 64 << 20
+    assert lib.krr_noalloc_scratch_bytes() == 128 << 20
     dt = torch.float64 if prec == "fp64" else torch.float32
-    for n, d, seed in ((60_000, 3, 1), (3_000, 2, 2)):  # the second call smaller
+    for n, d, seed in ((50_000, 3, 1), (3_000, 2, 2)):  # the second call smaller
         p = workloads.kriging(n=n) if d == 3 else workloads.plain_small(n=n)
         x = torch.from_numpy(p.x).cuda()
         q = torch.from_numpy(workloads.random_vector(40 + seed, n)).to(dt).cuda()
