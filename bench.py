@@ -55,6 +55,8 @@ def dpad(d: int) -> int:
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, index, shift, table product, ldexp
 C_EXP2_F64_TAB4096 = 9 * C_FMA              # the 4096-entry form (d <= 3): 2 FMAs
+C_SYM_STEP = 6 * C_FMA                      # symmetric FP64 product, per wave-step: the source terms
+                                            # summed over 4 lane rows (4 permlane swaps, 2 adds) and stored
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
@@ -89,6 +91,15 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
                 f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mgw<{D}, {tag}>"
+    if d <= 12 and prec == "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0":
+        # symmetric FP64 product: per wave-step 1024 evaluated pairs serve 2048
+        # terms (16 x (exp2 + 2 FMAs) per lane)
+        D = dpad(d)
+        dk = (D + 4) // 4
+        cyc = 4 * dk * C_MFMA64 + 16 * ((C_EXP2_F64_TAB4096 if D <= 3 else C_EXP2_F64_TAB) + 2 * C_FMA) + C_SYM_STEP
+        rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + "
+                f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_ms<{D}>"
     if d <= 16 and not valu:
         D = dpad(d)
         if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":
@@ -809,6 +820,8 @@ def main() -> int:
                                 "frac": round(achieved / peak, 4), "rule": peak_rule},
                 "fp64": {"kernel": kname64, "achieved": round(tflops64, 3), "peak": 78.6, "unit": "TFLOP/s",
                          "frac": round(tflops64 / 78.6, 4), "pair_rate_gpair_s": round(ach64, 1),
+                         "pairs_rule": "N^2 pair terms per product (the symmetric kernel evaluates each "
+                                       "unordered pair once for both of its terms)",
                          "issue_model_peak_gpair_s": round(peak64 / 1e9, 1),
                          "issue_model_frac": round(ach64 * 1e9 / peak64, 4),
                          "avg_launch_ms": round(f64["total_ms"] / max(f64["launches"], 1), 4)},

@@ -1066,16 +1066,18 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                         }
                     };
                     auto accumulate = [&](const V4 (&G)[RG], T qs, int cb) {
-                        T zl = T(0);
+                        T zl[RG];  // independent chains, one per target group
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg) zl[rg] = T(0);
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
 #pragma unroll
                             for (int rg = 0; rg < RG; ++rg) {
                                 const T e = exp2_tab<TN>(G[rg][v], s_exp2);
                                 acc[rg][v] = M::fma(e, qs, acc[rg][v]);
-                                if constexpr (SYM) zl = M::fma(e, qt[rg][v], zl);
+                                if constexpr (SYM) zl[rg] = M::fma(e, qt[rg][v], zl[rg]);
                             }
-                        if constexpr (SYM) emit_z(zl, cb);
+                        if constexpr (SYM) emit_z((zl[0] + zl[1]) + (zl[2] + zl[3]), cb);
                     };
                     // software pipeline over the 16 column steps (as k_kmvp_mg)
                     T av[2][DK], qs[2];
@@ -1495,6 +1497,319 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
     }
     if (a.skip_count != nullptr && tid == 0 && skipped > 0)
         atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * BLOCK);
+}
+
+// ---------------------------------------------------------------- symmetric split-f16 product
+//
+// The FP32 / BF16 Gaussian product of k_kmvp_mh with one exponential per
+// unordered pair, as k_kmvp_ms for FP64 (group pairs, tile pairs, partial-sum
+// slots and their owners are the same).  The targets form the A operand of
+// v_mfma_f32_32x32x16_f16 and the sources the B operand, so lane l holds source
+// l % 32 of the step against targets 8 (v / 4) + 4 (l / 32) + v % 4 (v < 16)
+// of the wave's 32 targets: the target terms accumulate per lane over the
+// column loop (summed over the 32 source lanes once per row unit), the source
+// terms are summed per step over the lane's 16 targets, over the two halves of
+// the wave (v_permlane32_swap) and over the waves in LDS once per tile pair.
+// A wave owns one group of 32 targets (two would keep twice the accumulators
+// and target weights live and cost a wave per SIMD), so a block takes a row
+// tile in two units of 128 rows, each against the same column tiles.
+template <int D, int PREC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_kmvp_mhs(KArgs a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    using P = Prec<PREC>;
+    using Off = typename P::Off;
+    using Q = typename P::Q;
+    constexpr int KC = split_chunks(D);
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int UNIT = NW * 32;  // rows per row unit
+    static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
+    __shared__ __align__(16) half8_t s_a[2][2 * KC][TILE];
+    __shared__ __align__(16) float s_q[2][TILE];
+    __shared__ float s_z[NW * TILE];
+    __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
+    const Off *__restrict__ off = static_cast<const Off *>(a.off);
+    const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
+    const Q *__restrict__ q = static_cast<const Q *>(a.q);
+    const float *__restrict__ qw = static_cast<const float *>(a.qw);
+    const float *__restrict__ wsrc = static_cast<const float *>(a.w);
+    float *__restrict__ out = static_cast<float *>(a.out);
+    const int64_t n_pad = a.n_pad;
+    const int ng = a.ngroups, gs = a.gtiles;
+
+    // block -> group pair (R, C), as k_kmvp_ms
+    const int nb_off = ng * (ng - 1) / 2;
+    const int b = blockIdx.x;
+    int R, C;
+    if (b < nb_off) {
+        const double m = 2.0 * ng - 1.0;
+        int r = static_cast<int>(0.5 * (m - sqrt(m * m - 8.0 * b)));
+        r = r < 0 ? 0 : (r > ng - 2 ? ng - 2 : r);
+        while (r > 0 && r * (2 * ng - r - 1) / 2 > b) --r;
+        while ((r + 1) * (2 * ng - r - 2) / 2 <= b) ++r;
+        R = r;
+        C = r + 1 + (b - r * (2 * ng - r - 1) / 2);
+    } else {
+        R = C = b - nb_off;
+    }
+    const bool diag = R == C;
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const int r32 = lane % 32, h = lane / 32;
+    const int I0 = R * gs, I1 = min(a.ntiles, I0 + gs);
+    const int C0 = C * gs, C1 = min(a.ntiles, C0 + gs);
+    float *__restrict__ zslot = out + static_cast<int64_t>(R) * n_pad;
+    float *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;
+    for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = 0.f;
+
+    // staging of a column tile's sources, as k_kmvp_mh
+    const half8_t *__restrict__ slots = static_cast<const half8_t *>(a.slots);
+    half8_t st_a[2 * KC];
+    float st_q;
+    auto stage_load = [&](int J) {
+        const int64_t j = static_cast<int64_t>(J) * TILE + tid;
+        if (a.tile_r2[J] > P::wide) {
+#pragma unroll
+            for (int c = 0; c < 2 * KC; ++c) {
+                uintx4_t u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float o = (4 * c + e < D) ? P::off(off[(4 * c + e) * n_pad + j]) : 0.f;
+                    u[e] = __builtin_bit_cast(unsigned, o);
+                }
+                st_a[c] = __builtin_bit_cast(half8_t, u);
+            }
+            st_q = P::q(q[j]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2 * KC; ++c) st_a[c] = slots[c * n_pad + j];
+            st_q = qw[j];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < 2 * KC; ++c) s_a[buf][c][tid] = st_a[c];
+        s_q[buf][tid] = st_q;
+    };
+    // the source terms of one step: the lane-local sum over its targets, summed
+    // over the two halves of the wave (the same sum in both) and stored
+    auto emit_z = [&](float zl, int cb) {
+        float z0, z1;
+        swap_halves(zl, z0, z1);
+        s_z[wv * TILE + cb + r32] = z0 + z1;
+    };
+    int skipped = 0;
+    for (int I = I0; I < I1; ++I) {
+        double aI[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(I) * D + k];
+        const double rI = a.row_r2 != nullptr ? sqrt(a.row_r2[I]) : INFINITY;  // null: no skipping
+        const int Js = diag ? I : C0;
+        for (int jj = tid; jj < C1 - Js; jj += BLOCK) {
+            const int Jt = Js + jj;
+            s_live[jj] = tiles_far<D>(aI, rI, a.anchor + static_cast<int64_t>(Jt) * D, a.tile_far[Jt]) ? 0 : 1;
+        }
+        __syncthreads();
+        auto next_live = [&](int J) {
+            while (J < C1 && s_live[J - Js] == 0) ++J;
+            return J;
+        };
+        const int Jfirst = next_live(Js);
+        skipped += Jfirst - Js;
+        if (Jfirst >= C1) {
+            const int64_t i = static_cast<int64_t>(I) * TILE + tid;
+            if (!diag) yslot[i] = 0.f;
+            __syncthreads();  // s_live is rewritten for the next row tile
+            continue;
+        }
+        for (int half = 0; half < TILE / UNIT; ++half) {
+            const int64_t row0 = static_cast<int64_t>(I) * TILE + half * UNIT + wv * 32;
+            // the lane's A-operand target row0 + r32 (octet h of its slots)
+            float oi[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) oi[k] = P::off(row_off[k * a.n_pad_rows + row0 + r32]);
+            // the lane's output targets 8 (v / 4) + 4 h + v % 4: their q (0 on the padding)
+            float qt[16], acc[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t i = row0 + 8 * (v / 4) + 4 * h + v % 4;
+                qt[v] = i < a.n_rows ? P::q(q[i]) : 0.f;
+                acc[v] = 0.f;
+            }
+            int J = Jfirst;
+            stage_load(J);
+            stage_store(0);
+            __syncthreads();
+            int buf = 0;
+            while (J < C1) {
+                const int Jn = next_live(J + 1);
+                if (half == 0) skipped += Jn - J - 1;
+                if (Jn < C1) stage_load(Jn);
+                const double r2 = a.tile_r2[J];
+                const float njf = static_cast<float>(a.tile_nj[J]);  // a small integer
+                const float far_t2 = a.tile_far[J];
+                const double *__restrict__ aJ = a.anchor + static_cast<int64_t>(J) * D;
+                const bool sym = J != I;
+                const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
+                const float zold = sym ? zslot[jz] : 0.f;
+                const float wj = (sym && r2 <= P::wide) ? wsrc[jz] : 1.f;
+                auto tile = [&](auto sym_c) {
+                    constexpr bool SYM = decltype(sym_c)::value;
+                    if (r2 <= P::wide) {
+                        // the target operand, as k_kmvp_mh's B operand
+                        float t[D];
+                        double tt = 0.0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const double td = (aI[k] - aJ[k]) + static_cast<double>(oi[k]);
+                            t[k] = static_cast<float>(td);
+                            tt = __builtin_fma(td, td, tt);
+                        }
+                        const bool far = static_cast<float>(tt) > far_t2;
+                        const _Float16 z16 = static_cast<_Float16>(0.f);
+                        HiLo v[D], c, c2;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                        c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
+                        c2 = HiLo{z16, z16};
+                        half8_t tval[KC];
+#pragma unroll
+                        for (int kc = 0; kc < KC; ++kc) {
+                            const half8_t o0 = slot_octet<D, false>(2 * kc, v, c, c2);
+                            const half8_t o1 = slot_octet<D, false>(2 * kc + 1, v, c, c2);
+                            tval[kc] = h ? o1 : o0;
+                        }
+                        auto load_a = [&](int cb, half8_t (&av)[KC]) {
+#pragma unroll
+                            for (int kc = 0; kc < KC; ++kc) av[kc] = s_a[buf][2 * kc + h][cb + r32];
+                        };
+                        auto exponents = [&](const half8_t (&av)[KC], floatx16_t &G) {
+#pragma unroll
+                            for (int v2 = 0; v2 < 16; ++v2) G[v2] = 0.f;
+#pragma unroll
+                            for (int kc = 0; kc < KC; ++kc)
+                                G = __builtin_amdgcn_mfma_f32_32x32x16_f16(tval[kc], av[kc], G, 0, 0, 0);
+                        };
+                        // the steps' source terms, stored to LDS after the last step (a
+                        // store per step would hold up the next step's operand reads)
+                        float zst[TILE / 32];
+                        auto accumulate = [&](const floatx16_t &G, float qs, int st) {
+                            float zl[4] = {0.f, 0.f, 0.f, 0.f};  // independent chains
+#pragma unroll
+                            for (int v2 = 0; v2 < 16; ++v2) {
+                                const float e = __builtin_amdgcn_exp2f(G[v2]);
+                                acc[v2] = __builtin_fmaf(e, qs, acc[v2]);
+                                if constexpr (SYM) zl[v2 % 4] = __builtin_fmaf(e, qt[v2], zl[v2 % 4]);
+                            }
+                            if constexpr (SYM) {
+                                float z0, z1;
+                                swap_halves((zl[0] + zl[1]) + (zl[2] + zl[3]), z0, z1);
+                                zst[st] = z0 + z1;
+                            }
+                        };
+                        // software pipeline over the 8 column steps of 32 sources (as k_kmvp_mh)
+                        half8_t av[2][KC];
+                        floatx16_t G[2];
+                        load_a(0, av[0]);
+                        exponents(av[0], G[0]);
+                        load_a(32, av[1]);
+#pragma unroll
+                        for (int st = 1; st < TILE / 32; ++st) {
+                            exponents(av[st & 1], G[st & 1]);
+                            if (st + 1 < TILE / 32) load_a((st + 1) * 32, av[(st + 1) & 1]);
+                            accumulate(G[(st - 1) & 1], s_q[buf][(st - 1) * 32 + r32], st - 1);
+                        }
+                        accumulate(G[(TILE / 32 - 1) & 1], s_q[buf][TILE - 32 + r32], TILE / 32 - 1);
+                        if constexpr (SYM) {
+#pragma unroll
+                            for (int st = 0; st < TILE / 32; ++st) s_z[wv * TILE + st * 32 + r32] = zst[st];
+                        }
+                    } else {
+                        // wide tile: the direct form on the staged FP32 offsets, one
+                        // output target at a time (few registers: wide tiles are rare)
+                        float zs[TILE / 32];
+#pragma unroll
+                        for (int st = 0; st < TILE / 32; ++st) zs[st] = 0.f;
+#pragma unroll 1
+                        for (int v2 = 0; v2 < 16; ++v2) {
+                            // keeps the staged offsets from being read once for all
+                            // targets (registers the rest of the kernel needs)
+                            __asm__ __volatile__("" ::: "memory");
+                            const int64_t i = row0 + 8 * (v2 / 4) + 4 * h + v2 % 4;
+                            float tg[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k)
+                                tg[k] = static_cast<float>((aI[k] - aJ[k]) +
+                                                           static_cast<double>(P::off(row_off[k * a.n_pad_rows + i])));
+                            const float qi = i < a.n_rows ? P::q(q[i]) : 0.f;
+                            float sacc = 0.f;
+#pragma unroll
+                            for (int st = 0; st < TILE / 32; ++st) {
+                                const int cj = st * 32 + r32;
+                                float ss = 0.f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    // the word goes through a scalar (see k_kmvp_mh)
+                                    const unsigned w = __builtin_bit_cast(uintx4_t, s_a[buf][k / 4][cj])[k % 4];
+                                    const float dd = tg[k] - __builtin_bit_cast(float, w);
+                                    ss = __builtin_fmaf(dd, dd, ss);
+                                }
+                                const float e = __builtin_amdgcn_exp2f(-ss);
+                                sacc = __builtin_fmaf(e, s_q[buf][cj], sacc);
+                                if constexpr (SYM) zs[st] = __builtin_fmaf(e, qi, zs[st]);
+                            }
+                            // into acc[v2] (v2 varies at run time here)
+#pragma unroll
+                            for (int va = 0; va < 16; ++va) acc[va] += (va == v2) ? sacc : 0.f;
+                        }
+                        if constexpr (SYM) {
+#pragma unroll
+                            for (int st = 0; st < TILE / 32; ++st) emit_z(zs[st], st * 32);
+                        }
+                    }
+                };
+                if (sym)
+                    tile(std::true_type{});
+                else
+                    tile(std::false_type{});
+                if (Jn < C1) stage_store(buf ^ 1);
+                __syncthreads();
+                if (sym) {
+                    const float z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
+                    zslot[jz] = __builtin_fmaf(z, wj, zold);
+                    __syncthreads();  // s_z is rewritten by the next tile pair
+                }
+                buf ^= 1;
+                J = Jn;
+            }
+            // the unit's target terms: summed over the 32 source lanes; lanes 0
+            // and 32 hold targets 8 (v / 4) + 4 h + v % 4 of the wave
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) {
+                float x = acc[v2];
+                x += __shfl_xor(x, 1, WAVE);
+                x += __shfl_xor(x, 2, WAVE);
+                x += __shfl_xor(x, 4, WAVE);
+                x += __shfl_xor(x, 8, WAVE);
+                x += __shfl_xor(x, 16, WAVE);
+                acc[v2] = x;
+            }
+            if (r32 == 0) {
+#pragma unroll
+                for (int v2 = 0; v2 < 16; ++v2) s_z[wv * 32 + 8 * (v2 / 4) + 4 * h + v2 % 4] = acc[v2];
+            }
+            __syncthreads();
+            if (tid < UNIT) {
+                const int64_t i = static_cast<int64_t>(I) * TILE + half * UNIT + tid;
+                if (diag)
+                    yslot[i] += s_z[tid];
+                else
+                    yslot[i] = s_z[tid];
+            }
+            __syncthreads();
+        }
+    }
+    if (a.skip_count != nullptr && tid == 0 && skipped > 0)
+        atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * 2 * TILE);
 }
 
 // qw_j = q_j * w_j (the per-source factor of the folded form), once per product.
@@ -2086,8 +2401,8 @@ int kmvp_ngroups(const Prepared &C) {
 // Column splits (blocks per row tile): from 1 to the group count.
 int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
-// The symmetric FP64 product (k_kmvp_ms): Gaussian point sets up to the
-// compiled dimension 12, groups of gs tiles with gs fixed by the tile count, so
+// The symmetric products (k_kmvp_ms FP64, compiled dimensions up to 12;
+// k_kmvp_mhs FP32 / BF16, up to 3): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
 // that the summation order does not depend on tuning: about 100 groups up to
 // 1000 tiles, groups of 10 tiles above (clustered sets skip most tile pairs, and
 // small groups leave enough blocks with work), and at most about 512 groups
@@ -2218,13 +2533,6 @@ static bool use_tile_skip() {
     const char *v = std::getenv("KRR_NO_TILE_SKIP");
     return !(v && v[0] == '1');
 }
-// KRR_KMVP_SYM=0 keeps FP64 products one-sided (used to cross-check the
-// symmetric kernel); so do KRR_KMVP_VALU=1 and KRR_KMVP_SPLITS
-static bool use_sym_kernel(const Prepared &P, int prec) {
-    if (prec != KRR_FP64 || !sym_capable(P) || use_valu_kernel() || std::getenv("KRR_KMVP_SPLITS")) return false;
-    const char *v = std::getenv("KRR_KMVP_SYM");
-    return !(v && v[0] == '0');
-}
 static bool use_fp32_matrix_kernel() {
     const char *v = std::getenv("KRR_KMVP_MG32");
     return v && v[0] == '1';
@@ -2304,6 +2612,19 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     return hipGetLastError();
 }
 
+// KRR_KMVP_SYM=0 keeps the square Gaussian products one-sided (used to
+// cross-check the symmetric kernels); so do KRR_KMVP_VALU=1, KRR_KMVP_MG32=1
+// (FP32 / BF16) and KRR_KMVP_SPLITS
+static bool use_sym_kernel(const Prepared &P, int prec) {
+    if (!sym_capable(P) || use_valu_kernel() || std::getenv("KRR_KMVP_SPLITS")) return false;
+    // FP32 / BF16: up to the compiled dimension 3, where it measured faster
+    // (2-5 % on the kriging shape, 20 % on the clustered one); above, its extra
+    // FMA per pair costs about what the shared exponential saves
+    if (prec == KRR_FP64 ? P.dpad > 12 : (P.dpad > 3 || use_fp32_matrix_kernel())) return false;
+    const char *v = std::getenv("KRR_KMVP_SYM");
+    return !(v && v[0] == '0');
+}
+
 template <int D>
 static hipError_t launch_kmvp_sym(const KArgs &a, hipStream_t s) {
     if constexpr (ms_supported<D>()) {
@@ -2312,6 +2633,23 @@ static hipError_t launch_kmvp_sym(const KArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
+}
+
+template <int D, int PREC>
+static hipError_t launch_kmvp_sym_h(const KArgs &a, hipStream_t s) {
+    const int nb = a.ngroups * (a.ngroups + 1) / 2;
+    hipLaunchKernelGGL((k_kmvp_mhs<D, PREC>), dim3(nb), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, hipStream_t s) {
+    switch (dpad) {
+        case 1: return launch_kmvp_sym_h<1, PREC>(a, s);
+        case 2: return launch_kmvp_sym_h<2, PREC>(a, s);
+        case 3: return launch_kmvp_sym_h<3, PREC>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 static hipError_t launch_kmvp_sym_d(int dpad, const KArgs &a, hipStream_t s) {
@@ -2352,8 +2690,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
                            const void *q, void *y, const KmvpScratch &sc, const int *active, bool timed_slot,
                            hipStream_t s) {
     const bool square = (&R == &C);
-    // the symmetric FP64 kernel for square products (plan.sym_gs > 0)
-    const bool sym = square && pl.sym_gs > 0 && prec == KRR_FP64;
+    // the symmetric kernels for square products (plan.sym_gs > 0)
+    const bool sym = square && pl.sym_gs > 0;
     KArgs a;
     a.n_rows = R.n;
     a.n_pad_rows = R.n_pad;
@@ -2411,13 +2749,13 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
             a.off = C.off32;
             a.pm = C.pm32;
             a.row_off = R.off32;
-            e = launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_hd<KRR_FP32>(C.dpad, a, s) : launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
             break;
         case KRR_BF16:
             a.off = C.offb;
             a.pm = C.pmb;
             a.row_off = R.offb;
-            e = launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_hd<KRR_BF16>(C.dpad, a, s) : launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -25,10 +25,17 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / 224)
     # FP32 d = 16: ceil(52 / 16) = 4 ops
     assert bench.product_peak(16)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
-    # FP64 d = 3: four 16x16x4 FP64 ops (64 each) + 16 x (9 x 4 + 4) (4096-entry table)
-    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 640))
+    # FP64 d = 3, symmetric kernel: per 1024 exponentials (2048 pair terms) four
+    # 16x16x4 FP64 ops (64 each) + 16 x (9 x 4 + 2 x 4) (4096-entry table) + 24
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 2048 / (256 + 704 + 24))
     # FP64 d = 8: the 256-entry table, 11 instructions
+    assert bench.product_peak(8, "fp64")[0] == pytest.approx(S * 2048 / (4 * 3 * 64 + 16 * 52 + 24))
+    # the one-sided FP64 kernel (KRR_KMVP_SYM=0): 1024 pairs per 256 + 16 x (36 + 4)
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 640))
     assert bench.product_peak(8, "fp64")[0] == pytest.approx(S * 1024 / (4 * 3 * 64 + 768))
+    monkeypatch.delenv("KRR_KMVP_SYM")
     # FP32 d = 20 runs at D = 24: ceil(74 / 16) = 5 ops; d = 41 at D = 48: 10 ops
     assert bench.product_peak(20)[0] == pytest.approx(S * 1024 / (5 * 32 + 192))
     assert bench.product_peak(41, "bf16")[0] == pytest.approx(S * 1024 / (10 * 32 + 192))

@@ -220,11 +220,11 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
     default = _gpu_mvp(x, sigma, q, 0.01, prec)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    if prec == "fp64" and d <= 12:
-        # the default FP64 product is the symmetric kernel: its own fixed
-        # summation order and tile anchors (equal to the exponential's 2.5e-14
-        # per term, and the same on every call)
-        assert _relerr(default, outs[0]) <= 1e-13
+    if (prec == "fp64" and d <= 12) or d <= 3:
+        # the default product is the symmetric kernel here: its own fixed
+        # summation order and tile anchors (FP64: equal to the exponential's
+        # 2.5e-14 per term; FP32 / BF16: to their rounding), the same on every call
+        assert _relerr(default, outs[0]) <= (1e-13 if prec == "fp64" else 1e-5)
         assert np.array_equal(default, _gpu_mvp(x, sigma, q, 0.01, prec))
     else:
         assert np.array_equal(default, outs[0])
@@ -256,6 +256,28 @@ def test_symmetric_fp64_product(monkeypatch, n, d):
     else:
         rows = np.random.default_rng(n).choice(n, 64, replace=False)
         check(y[rows], oracle.mvp_rows(x, sigma, q, rows, shift=0.02), "fp64", what=(n, d))
+
+
+# The symmetric FP32 / BF16 product (compiled dimensions up to 3) against the
+# one-sided split-f16 kernel and the oracle.
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d", [(1, 1), (200, 2), (257, 3), (3000, 3), (9000, 2), (30000, 1), (26000, 3)])
+def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
+    x = workloads.random_points(520 + d, n, d, 2.0 * d ** 0.5, kind="normal")
+    q = workloads.random_vector(521 + d, n)
+    sigma = 0.7 * np.sqrt(d)
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    y = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    y1 = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.delenv("KRR_KMVP_SYM")
+    assert _relerr(y, y1) <= 1e-5
+    qc = call_vector(q, prec)
+    if n <= 12000:
+        check(y, oracle.mvp(x, sigma, qc, shift=0.02), prec, what=(n, d))
+    else:
+        rows = np.random.default_rng(n).choice(n, 64, replace=False)
+        check(y[rows], oracle.mvp_rows(x, sigma, qc, rows, shift=0.02), prec, what=(n, d))
 
 
 @pytest.mark.parametrize("d", [1, 2, 3])
