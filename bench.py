@@ -55,8 +55,8 @@ def dpad(d: int) -> int:
 C_EXP2_F64 = 15 * C_FMA                     # clamp, rint, subtract, 10 FMAs, convert, ldexp
 C_EXP2_F64_TAB = 11 * C_FMA                 # rint, subtract, convert, 4 FMAs, index, shift, table product, ldexp
 C_EXP2_F64_TAB4096 = 9 * C_FMA              # the 4096-entry form (d <= 3): 2 FMAs
-C_SYM_STEP = 6 * C_FMA                      # symmetric FP64 product, per wave-step: the source terms
-                                            # summed over 4 lane rows (4 permlane swaps, 2 adds) and stored
+C_SYM_STEP = 6 * C_FMA                      # symmetric products, per wave-step: the source terms summed
+                                            # over the lane rows (permlane swaps, adds) and stored
 
 
 def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
@@ -100,6 +100,15 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + "
                 f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_ms<{D}>"
+    if (d <= 3 and prec != "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0"
+            and os.environ.get("KRR_KMVP_MG32", "0") != "1"):
+        # symmetric split-f16 product: per wave-step one 32x32x16 f16 op forms
+        # 1024 exponentials that serve 2048 terms (16 x (exp2 + 2 FMAs) per lane)
+        D = dpad(d)
+        cyc = C_MFMA_H32 + 16 * (C_EXP + 2 * C_FMA) + C_SYM_STEP
+        rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: one 32x32x16 f16 matrix-core op + "
+                f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_mhs<{D}, {tag}>"
     if d <= 16 and not valu:
         D = dpad(d)
         if prec != "fp64" and os.environ.get("KRR_KMVP_MG32", "0") != "1":

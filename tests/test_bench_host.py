@@ -21,8 +21,16 @@ def test_compiled_dimensions():
 def test_product_peaks_by_hand(monkeypatch):
     monkeypatch.delenv("KRR_KMVP_VALU", raising=False)
     monkeypatch.delenv("KRR_KMVP_MG32", raising=False)
-    # FP32 d = 3: one 32x32x16 f16 op (32) + 16 x (exp2 8 + FMA 4) per 1024 pairs
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    # FP32 d = 3, symmetric kernel: one 32x32x16 f16 op (32) + 16 x (exp2 8 + 2 FMAs 8) + 24 per
+    # 1024 exponentials (2048 pair terms)
+    assert bench.product_peak(3)[0] == pytest.approx(S * 2048 / (32 + 256 + 24))
+    assert bench.product_peak(3)[2] == "k_kmvp_mhs<3, FP32>"
+    # the one-sided split-f16 kernel (d = 4, or KRR_KMVP_SYM=0): 1024 pairs per 32 + 16 x 12
+    assert bench.product_peak(4)[0] == pytest.approx(S * 1024 / 224)
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / 224)
+    monkeypatch.delenv("KRR_KMVP_SYM")
     # FP32 d = 16: ceil(52 / 16) = 4 ops
     assert bench.product_peak(16)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
     # FP64 d = 3, symmetric kernel: per 1024 exponentials (2048 pair terms) four
