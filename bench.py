@@ -506,8 +506,8 @@ def workload_gp(args, api, native, workloads, torch) -> dict:
     log(f"gp fgmres (paper inner rule): {ip['outer_iters']} outer, {ip['inner_iters']} inner, "
         f"relres {ip['relres_true']:.3e}, {tp:.2f} s")
     t0 = time.perf_counter()
-    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=20000,
-                                 cg_check=32)
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol,
+                                 max_outer=args.max_outer or 20000, cg_check=32)
     torch.cuda.synchronize()
     tc = time.perf_counter() - t0
     log(f"gp cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
@@ -581,8 +581,8 @@ def workload_highd(args, api, native, workloads, torch) -> dict:
     log(f"high-d fgmres: {info['outer_iters']} outer, {info['inner_iters']} inner, relres {info['relres_true']:.3e}, "
         f"{tf:.2f} s")
     t0 = time.perf_counter()
-    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol, max_outer=20000,
-                                 cg_check=32)
+    (wc,), (ic,) = api.krr_solve([x], [p.sigma], [p.gamma], [y], mode="cg64", tol=p.tol,
+                                 max_outer=args.max_outer or 20000, cg_check=32)
     torch.cuda.synchronize()
     tc = time.perf_counter() - t0
     log(f"high-d cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
