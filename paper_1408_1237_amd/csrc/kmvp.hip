@@ -870,7 +870,7 @@ constexpr int MS_MAX_GROUP_TILES = 512;
 
 template <int D>
 constexpr bool ms_supported() {
-    return D <= 12;
+    return D <= 16;
 }
 
 template <int D>
@@ -880,14 +880,20 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     using T = double;
     using V4 = doublex4_t;
     constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
-    constexpr int RG = 4;            // groups of 16 targets per wave
+    // groups of 16 targets per wave: 4 (a block takes a row tile at once), or
+    // 2 at d = 16, where four groups' operands and accumulators do not fit (a
+    // block then takes a row tile in two units of 128 rows); there the source
+    // tile is also staged in one buffer (two would leave one block per CU)
+    constexpr int RG = D >= 16 ? 2 : 4;
+    constexpr int UNITS = 4 / RG;
+    constexpr int NBUF = D >= 16 ? 1 : 2;
     constexpr int NW = BLOCK / WAVE;
     constexpr int LDO = TILE + 16;
     constexpr int TN = D <= 3 ? 4096 : 256;  // exp2_tab table (as k_kmvp_mg)
     // target offsets kept in registers at small d, else re-read per tile pair
     constexpr bool KEEP = D <= 4;
-    __shared__ T s_off[2][D][LDO];
-    __shared__ __align__(16) T s_q[2][TILE];
+    __shared__ T s_off[NBUF][D][LDO];
+    __shared__ __align__(16) T s_q[NBUF][TILE];
     __shared__ double s_exp2[TN];
     // per wave: the source terms of the current tile pair (and, at the end of a
     // row tile, the block's target terms)
@@ -956,7 +962,6 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     };
     int skipped = 0;
     for (int I = I0; I < I1; ++I) {
-        const int64_t row0 = static_cast<int64_t>(I) * TILE + wv * (16 * RG);
         double aI[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) aI[k] = a.row_anchor[static_cast<int64_t>(I) * D + k];
@@ -972,15 +977,18 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
             while (J < C1 && s_live[J - Js] == 0) ++J;
             return J;
         };
-        int J = next_live(Js);
-        skipped += J - Js;
-        if (J >= C1) {
+        const int Jfirst = next_live(Js);
+        skipped += Jfirst - Js;
+        if (Jfirst >= C1) {
             // no live column tile: zero target terms (the source-side slots stay as they are)
             const int64_t i = static_cast<int64_t>(I) * TILE + tid;
             if (!diag) yslot[i] = T(0);
             __syncthreads();  // s_live is rewritten for the next row tile
             continue;
         }
+        for (int unit = 0; unit < UNITS; ++unit) {
+        const int64_t row0 = static_cast<int64_t>(I) * TILE + unit * (TILE / UNITS) + wv * (16 * RG);
+        int J = Jfirst;
         T oi[KEEP ? RG : 1][KEEP ? D : 1];
         if constexpr (KEEP) {
 #pragma unroll
@@ -1007,7 +1015,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
         int buf = 0;
         while (J < C1) {
             const int Jn = next_live(J + 1);
-            skipped += Jn - J - 1;
+            if (unit == 0) skipped += Jn - J - 1;
             if (Jn < C1) stage_load(Jn);
             const double r2 = a.tile_r2[J];
             const double nj = a.tile_nj[J];
@@ -1077,7 +1085,12 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                                 acc[rg][v] = M::fma(e, qs, acc[rg][v]);
                                 if constexpr (SYM) zl[rg] = M::fma(e, qt[rg][v], zl[rg]);
                             }
-                        if constexpr (SYM) emit_z((zl[0] + zl[1]) + (zl[2] + zl[3]), cb);
+                        if constexpr (SYM) {
+                            T zs = zl[0];
+#pragma unroll
+                            for (int rg = 1; rg < RG; ++rg) zs += zl[rg];
+                            emit_z(zs, cb);
+                        }
                     };
                     // software pipeline over the 16 column steps (as k_kmvp_mg)
                     T av[2][DK], qs[2];
@@ -1099,6 +1112,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                         T zs[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll 1
                         for (int rv = 0; rv < 4 * RG; ++rv) {
+                            // at d = 16: keeps the staged offsets from being read once for
+                            // all targets (registers the rest of the kernel needs; below,
+                            // measured no better)
+                            if constexpr (D >= 16) __asm__ __volatile__("" ::: "memory");
                             const int rg = rv / 4, v = rv % 4;
                             const int64_t i = row0 + rg * 16 + 4 * g + v;
                             T t[D];
@@ -1142,15 +1159,21 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                 tile(std::true_type{});
             else
                 tile(std::false_type{});
-            if (Jn < C1) stage_store(buf ^ 1);
-            __syncthreads();
+            if constexpr (NBUF == 2) {
+                if (Jn < C1) stage_store(buf ^ 1);
+                __syncthreads();
+            } else {
+                __syncthreads();  // every wave is done with the staged tile
+                if (Jn < C1) stage_store(0);
+                if (!sym) __syncthreads();
+            }
             if (sym) {
                 // the tile pair's source terms: summed over the waves, times w_j on a folded tile
                 const T z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
                 zslot[jz] = zold + z * wj;
-                __syncthreads();  // s_z is rewritten by the next tile pair
+                __syncthreads();  // s_z is rewritten by the next tile pair (one buffer: the staging is visible)
             }
-            buf ^= 1;
+            if constexpr (NBUF == 2) buf ^= 1;
             J = Jn;
         }
         // the row tile's target terms: summed over the 16 source lanes; lane
@@ -1173,12 +1196,15 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                 for (int v = 0; v < 4; ++v) s_z[wv * (16 * RG) + rg * 16 + 4 * g + v] = acc[rg][v];
         }
         __syncthreads();
-        const int64_t i = static_cast<int64_t>(I) * TILE + tid;
-        if (diag)
-            yslot[i] += s_z[tid];
-        else
-            yslot[i] = s_z[tid];
+        if (tid < TILE / UNITS) {
+            const int64_t i = static_cast<int64_t>(I) * TILE + unit * (TILE / UNITS) + tid;
+            if (diag)
+                yslot[i] += s_z[tid];
+            else
+                yslot[i] = s_z[tid];
+        }
         __syncthreads();
+        }  // unit
     }
     // both directions of every skipped tile pair (rows x column tiles)
     if (a.skip_count != nullptr && tid == 0 && skipped > 0)
@@ -2401,14 +2427,14 @@ int kmvp_ngroups(const Prepared &C) {
 // Column splits (blocks per row tile): from 1 to the group count.
 int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
-// The symmetric products (k_kmvp_ms FP64, compiled dimensions up to 12;
+// The symmetric products (k_kmvp_ms FP64, compiled dimensions up to 16;
 // k_kmvp_mhs FP32 / BF16, up to 3): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
 // that the summation order does not depend on tuning: about 100 groups up to
 // 1000 tiles, groups of 10 tiles above (clustered sets skip most tile pairs, and
 // small groups leave enough blocks with work), and at most about 512 groups
 // (the partial sums hold one slot per group and point).
 static bool sym_capable(const Prepared &P) {
-    return P.kernel == KRR_KERNEL_GAUSS && P.dpad <= 12 && P.ntiles <= 512 * MS_MAX_GROUP_TILES;
+    return P.kernel == KRR_KERNEL_GAUSS && P.dpad <= 16 && P.ntiles <= 512 * MS_MAX_GROUP_TILES;
 }
 int kmvp_sym_group_tiles(const Prepared &P) {
     const int a = (P.ntiles + 99) / 100, b = (P.ntiles + 511) / 512;
@@ -2620,7 +2646,7 @@ static bool use_sym_kernel(const Prepared &P, int prec) {
     // FP32 / BF16: up to the compiled dimension 3, where it measured faster
     // (2-5 % on the kriging shape, 20 % on the clustered one); above, its extra
     // FMA per pair costs about what the shared exponential saves
-    if (prec == KRR_FP64 ? P.dpad > 12 : (P.dpad > 3 || use_fp32_matrix_kernel())) return false;
+    if (prec == KRR_FP64 ? P.dpad > 16 : (P.dpad > 3 || use_fp32_matrix_kernel())) return false;
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
@@ -2661,6 +2687,7 @@ static hipError_t launch_kmvp_sym_d(int dpad, const KArgs &a, hipStream_t s) {
         case 6: return launch_kmvp_sym<6>(a, s);
         case 8: return launch_kmvp_sym<8>(a, s);
         case 12: return launch_kmvp_sym<12>(a, s);
+        case 16: return launch_kmvp_sym<16>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
