@@ -91,7 +91,7 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"1024 pairs per {cyc} SIMD cycles: {4 * dk} 16x16x4 matrix-core ops + 16 x (exp2 + FMA) per "
                 f"lane, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 1024 / cyc, rule, f"k_kmvp_mgw<{D}, {tag}>"
-    if d <= 12 and prec == "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0":
+    if d <= 16 and prec == "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0":
         # symmetric FP64 product: per wave-step 1024 evaluated pairs serve 2048
         # terms (16 x (exp2 + 2 FMAs) per lane)
         D = dpad(d)

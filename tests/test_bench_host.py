@@ -39,6 +39,8 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 2048 / (256 + 704 + 24))
     # FP64 d = 8: the 256-entry table, 11 instructions
     assert bench.product_peak(8, "fp64")[0] == pytest.approx(S * 2048 / (4 * 3 * 64 + 16 * 52 + 24))
+    # FP64 d = 16 (symmetric): five chunks of 4 over d + 1 = 17 coordinates
+    assert bench.product_peak(16, "fp64")[0] == pytest.approx(S * 2048 / (4 * 5 * 64 + 16 * 52 + 24))
     # the one-sided FP64 kernel (KRR_KMVP_SYM=0): 1024 pairs per 256 + 16 x (36 + 4)
     monkeypatch.setenv("KRR_KMVP_SYM", "0")
     assert bench.product_peak(3, "fp64")[0] == pytest.approx(S * 1024 / (256 + 640))
