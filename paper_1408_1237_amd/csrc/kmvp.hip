@@ -873,6 +873,16 @@ constexpr bool ms_supported() {
     return D <= 16;
 }
 
+// Tiles of a column group whose source terms k_kmvp_ms keeps in LDS: what fits
+// beside its other LDS arrays within 76 KiB (two blocks per CU), at most 16.
+template <int D>
+constexpr int ms_zacc_tiles() {
+    const int nbuf = D >= 16 ? 1 : 2, tn = D <= 3 ? 4096 : 256;
+    const int other = nbuf * D * (TILE + 16) * 8 + nbuf * TILE * 8 + tn * 8 + (BLOCK / WAVE) * TILE * 8 + 512;
+    const int t = (76 * 1024 - other) / (TILE * 8);
+    return t > 16 ? 16 : (t < 1 ? 1 : t);
+}
+
 template <int D>
 __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -900,6 +910,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     __shared__ T s_z[NW * TILE];
     // the column tiles of group C not far from the current row tile
     __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
+    // the source terms of group C, when it fits (entry [jl][j] owned by thread j)
+    constexpr int ZMAX = ms_zacc_tiles<D>();
+    __shared__ T s_zacc[ZMAX][TILE];
     for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE4096[k];
     const T *__restrict__ off = static_cast<const T *>(a.off);
     const T *__restrict__ row_off = static_cast<const T *>(a.row_off);
@@ -939,7 +952,15 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     const int C0 = C * gs, C1 = min(a.ntiles, C0 + gs);
     T *__restrict__ zslot = out + static_cast<int64_t>(R) * n_pad;  // source terms of the tiles of group C
     T *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;  // target terms of the tiles of group R
-    for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = T(0);
+    // the source terms accumulate in LDS and are stored once (a group that
+    // does not fit adds them into its cleared slots in memory instead)
+    const bool zlds = C1 - C0 <= ZMAX;
+    for (int J = C0; J < C1; ++J) {
+        if (zlds)
+            s_zacc[J - C0][tid] = T(0);
+        else
+            zslot[static_cast<int64_t>(J) * TILE + tid] = T(0);
+    }
 
     T st_o[D], st_q;
     auto stage_load = [&](int J) {
@@ -1153,7 +1174,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
             // the slot entry this thread adds the tile pair's source terms to (its
             // own earlier store; read before the compute to hide the latency)
             const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
-            const T zold = sym ? zslot[jz] : T(0);
+            const T zold = (sym && !zlds) ? zslot[jz] : T(0);
             const T wj = (sym && r2 <= WIDE_R2_FP64) ? wsrc[jz] : T(1);
             if (sym)
                 tile(std::true_type{});
@@ -1170,7 +1191,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
             if (sym) {
                 // the tile pair's source terms: summed over the waves, times w_j on a folded tile
                 const T z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
-                zslot[jz] = zold + z * wj;
+                if (zlds)
+                    s_zacc[J - C0][tid] += z * wj;
+                else
+                    zslot[jz] = zold + z * wj;
                 __syncthreads();  // s_z is rewritten by the next tile pair (one buffer: the staging is visible)
             }
             if constexpr (NBUF == 2) buf ^= 1;
@@ -1197,14 +1221,20 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
         }
         __syncthreads();
         if (tid < TILE / UNITS) {
-            const int64_t i = static_cast<int64_t>(I) * TILE + unit * (TILE / UNITS) + tid;
-            if (diag)
-                yslot[i] += s_z[tid];
-            else
+            const int il = unit * (TILE / UNITS) + tid;
+            const int64_t i = static_cast<int64_t>(I) * TILE + il;
+            if (!diag)
                 yslot[i] = s_z[tid];
+            else if (zlds)
+                yslot[i] = s_z[tid] + s_zacc[I - C0][il];  // the source terms of tile I are complete
+            else
+                yslot[i] += s_z[tid];
         }
         __syncthreads();
         }  // unit
+    }
+    if (zlds && !diag) {
+        for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = s_zacc[J - C0][tid];
     }
     // both directions of every skipped tile pair (rows x column tiles)
     if (a.skip_count != nullptr && tid == 0 && skipped > 0)
@@ -1553,6 +1583,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     __shared__ __align__(16) float s_q[2][TILE];
     __shared__ float s_z[NW * TILE];
     __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
+    // the source terms of group C, when it fits (entry [jl][j] owned by thread j;
+    // 16 tiles keep the block within a third of the LDS)
+    constexpr int ZMAX = 16;
+    __shared__ float s_zacc[ZMAX][TILE];
     const Off *__restrict__ off = static_cast<const Off *>(a.off);
     const Off *__restrict__ row_off = static_cast<const Off *>(a.row_off);
     const Q *__restrict__ q = static_cast<const Q *>(a.q);
@@ -1585,7 +1619,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const int C0 = C * gs, C1 = min(a.ntiles, C0 + gs);
     float *__restrict__ zslot = out + static_cast<int64_t>(R) * n_pad;
     float *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;
-    for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = 0.f;
+    const bool zlds = C1 - C0 <= ZMAX;
+    for (int J = C0; J < C1; ++J) {
+        if (zlds)
+            s_zacc[J - C0][tid] = 0.f;
+        else
+            zslot[static_cast<int64_t>(J) * TILE + tid] = 0.f;
+    }
 
     // staging of a column tile's sources, as k_kmvp_mh
     const half8_t *__restrict__ slots = static_cast<const half8_t *>(a.slots);
@@ -1676,7 +1716,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 const double *__restrict__ aJ = a.anchor + static_cast<int64_t>(J) * D;
                 const bool sym = J != I;
                 const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
-                const float zold = sym ? zslot[jz] : 0.f;
+                const float zold = (sym && !zlds) ? zslot[jz] : 0.f;
                 const float wj = (sym && r2 <= P::wide) ? wsrc[jz] : 1.f;
                 auto tile = [&](auto sym_c) {
                     constexpr bool SYM = decltype(sym_c)::value;
@@ -1801,7 +1841,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 __syncthreads();
                 if (sym) {
                     const float z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
-                    zslot[jz] = __builtin_fmaf(z, wj, zold);
+                    if (zlds)
+                        s_zacc[J - C0][tid] = __builtin_fmaf(z, wj, s_zacc[J - C0][tid]);
+                    else
+                        zslot[jz] = __builtin_fmaf(z, wj, zold);
                     __syncthreads();  // s_z is rewritten by the next tile pair
                 }
                 buf ^= 1;
@@ -1825,14 +1868,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             }
             __syncthreads();
             if (tid < UNIT) {
-                const int64_t i = static_cast<int64_t>(I) * TILE + half * UNIT + tid;
-                if (diag)
-                    yslot[i] += s_z[tid];
-                else
+                const int il = half * UNIT + tid;
+                const int64_t i = static_cast<int64_t>(I) * TILE + il;
+                if (!diag)
                     yslot[i] = s_z[tid];
+                else if (zlds)
+                    yslot[i] = s_z[tid] + s_zacc[I - C0][il];  // the source terms of tile I are complete
+                else
+                    yslot[i] += s_z[tid];
             }
             __syncthreads();
         }
+    }
+    if (zlds && !diag) {
+        for (int J = C0; J < C1; ++J) zslot[static_cast<int64_t>(J) * TILE + tid] = s_zacc[J - C0][tid];
     }
     if (a.skip_count != nullptr && tid == 0 && skipped > 0)
         atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * 2 * TILE);
