@@ -105,6 +105,8 @@ struct KArgs {
     const void *q;
     const void *qw;  // q_j * w_j in the arithmetic type (folded tiles)
     const void *w;   // w_j in the arithmetic type (symmetric product: the source terms)
+    int zmem;        // symmetric product: 1 adds the source terms into the slots in memory even
+                     // where the column group fits in LDS (the two paths are bitwise equal)
     void *out;
     double shift;    // square products only
     int square;
@@ -954,7 +956,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     T *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;  // target terms of the tiles of group R
     // the source terms accumulate in LDS and are stored once (a group that
     // does not fit adds them into its cleared slots in memory instead)
-    const bool zlds = C1 - C0 <= ZMAX;
+    const bool zlds = a.zmem == 0 && C1 - C0 <= ZMAX;
     for (int J = C0; J < C1; ++J) {
         if (zlds)
             s_zacc[J - C0][tid] = T(0);
@@ -1619,7 +1621,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const int C0 = C * gs, C1 = min(a.ntiles, C0 + gs);
     float *__restrict__ zslot = out + static_cast<int64_t>(R) * n_pad;
     float *__restrict__ yslot = out + static_cast<int64_t>(C) * n_pad;
-    const bool zlds = C1 - C0 <= ZMAX;
+    const bool zlds = a.zmem == 0 && C1 - C0 <= ZMAX;
     for (int J = C0; J < C1; ++J) {
         if (zlds)
             s_zacc[J - C0][tid] = 0.f;
@@ -2608,6 +2610,12 @@ static bool use_tile_skip() {
     const char *v = std::getenv("KRR_NO_TILE_SKIP");
     return !(v && v[0] == '1');
 }
+// KRR_KMVP_SYM_SLOTS=1: the symmetric products add their source terms into the
+// slots in memory even where a column group fits in LDS (tests compare the two)
+static bool sym_slots_in_memory() {
+    const char *v = std::getenv("KRR_KMVP_SYM_SLOTS");
+    return v && v[0] == '1';
+}
 static bool use_fp32_matrix_kernel() {
     const char *v = std::getenv("KRR_KMVP_MG32");
     return v && v[0] == '1';
@@ -2792,6 +2800,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     a.square = square ? 1 : 0;
     a.active = active;
     a.row_r2 = use_tile_skip() ? R.tile_r2 : nullptr;
+    a.zmem = sym_slots_in_memory() ? 1 : 0;
     a.skip_count = nullptr;
     const bool use_parts = a.ngroups > 1 || sym;
     a.out = use_parts ? sc.parts : y;

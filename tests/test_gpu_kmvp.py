@@ -282,6 +282,28 @@ def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
         check(y[rows], oracle.mvp_rows(x, sigma, qc, rows, shift=0.02), prec, what=(n, d))
 
 
+# The symmetric products keep a column group's source terms in LDS where it fits
+# and otherwise add them into the slots in memory; both paths add the same terms
+# in the same order (KRR_KMVP_SYM_SLOTS=1 forces the memory path).  At N = 140,000,
+# d = 12 (FP64) the groups of 6 tiles exceed the LDS room, so the memory path
+# runs either way and is checked against the oracle.
+@pytest.mark.parametrize("prec,n,d", [("fp64", 9000, 3), ("fp64", 30000, 12), ("fp64", 27000, 16),
+                                      ("fp32", 26000, 3), ("bf16", 9000, 2), ("fp64", 140000, 12)])
+def test_symmetric_slot_paths_agree(monkeypatch, prec, n, d):
+    x = workloads.random_points(540 + d, n, d, 2.0 * d ** 0.5, kind="normal")
+    q = workloads.random_vector(541 + d, n)
+    sigma = 0.7 * np.sqrt(d)
+    monkeypatch.delenv("KRR_KMVP_SYM_SLOTS", raising=False)
+    y = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.setenv("KRR_KMVP_SYM_SLOTS", "1")
+    y1 = _gpu_mvp(x, sigma, q, 0.02, prec)
+    monkeypatch.delenv("KRR_KMVP_SYM_SLOTS")
+    assert np.array_equal(y, y1)
+    rows = np.random.default_rng(n + d).choice(n, 48, replace=False)
+    qc = call_vector(q, prec)
+    check(y[rows], oracle.mvp_rows(x, sigma, qc, rows, shift=0.02), prec, what=(prec, n, d))
+
+
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_symmetric_fp64_product_wide_tiles(d):
     # 700 points spread over a box hundreds of bandwidths wide: every tile is
