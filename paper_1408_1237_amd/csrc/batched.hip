@@ -921,13 +921,12 @@ int batch_setup(BatchRun &R, const krr_points *probs, int nprob, const double *s
         int end = pos;
         int class_tiles = 0;
         double pairs = 0.0;
-        int64_t me = 0, mr = 0;
+        int64_t me = 0;
         while (end < nprob && L.sys[order[end]].P.dpad == dp) {
             const Prepared &P = L.sys[order[end]].P;
             class_tiles += P.ntiles;
             pairs += static_cast<double>(P.n) * static_cast<double>(P.n);
             me = std::max<int64_t>(me, P.n_pad * 16 * nrb);
-            mr = std::max<int64_t>(mr, P.n_pad * Rp);
             ++end;
         }
         BatchedProduct bi, bo;
@@ -940,7 +939,6 @@ int batch_setup(BatchRun &R, const krr_points *probs, int nprob, const double *s
         bi.d_items = bo.d_items = L.d_items + items.size();
         bi.nsys = bo.nsys = end - pos;
         bi.max_elems = bo.max_elems = me;
-        bi.max_rows = bo.max_rows = mr;
         bi.pairs = bo.pairs = pairs;
         // the tile: forced, cached, or timed now on this class (inner precision,
         // every column live) and cached for the process and KRR_TUNE_CACHE

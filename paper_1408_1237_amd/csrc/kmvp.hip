@@ -1904,6 +1904,13 @@ __global__ __launch_bounds__(BLOCK) void k_prescale(int64_t n_pad, const void *q
 }
 
 // y_i = sum_s parts[s][i] (+ shift q_i when square) for i < n, 0 on the padding.
+// A block takes FINISH_ROWS<PREC> consecutive rows, 16 bytes of each slot per
+// lane; wave w adds the slots w, w + 4, w + 8, ... in increasing order and the
+// four wave sums are added in wave order, so the order is the same on every
+// launch.  (One row per thread walking all slots left too few waves in flight
+// to cover the latency of its dependent loads.)
+template <int PREC>
+constexpr int finish_rows() { return WAVE * static_cast<int>(16 / sizeof(typename Prec<PREC>::T)); }
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad, int ngroups, const void *parts_,
                                                        const void *q_, double shift, int square, void *y_,
@@ -1911,18 +1918,33 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_finish(int64_t n, int64_t n_pad,
     if (active != nullptr && *active == 0) return;
     using P = Prec<PREC>;
     using T = typename P::T;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int NW = BLOCK / WAVE;
+    typedef T VT __attribute__((ext_vector_type(V)));
+    __shared__ VT s_part[NW - 1][WAVE];
     const T *parts = static_cast<const T *>(parts_);
     const typename P::Q *q = static_cast<const typename P::Q *>(q_);
     T *y = static_cast<T *>(y_);
-    const int64_t i = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
-    if (i >= n_pad) return;
-    if (i >= n) {
-        y[i] = T(0);
-        return;
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int64_t i0 = blockIdx.x * static_cast<int64_t>(finish_rows<PREC>()) + lane * V;
+    VT acc = {};
+    if (i0 < n_pad) {  // n_pad is a multiple of V: the whole vector is inside
+        const VT *p = reinterpret_cast<const VT *>(parts + i0);
+        const int64_t stride = n_pad / V;
+#pragma unroll 8
+        for (int k = wv; k < ngroups; k += NW) acc += p[static_cast<int64_t>(k) * stride];
     }
-    T s = parts[i];
-    for (int k = 1; k < ngroups; ++k) s += parts[static_cast<int64_t>(k) * n_pad + i];
-    y[i] = square ? s + static_cast<T>(shift) * P::q(q[i]) : s;
+    if (wv > 0) s_part[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && i0 < n_pad) {
+#pragma unroll
+        for (int w = 0; w < NW - 1; ++w) acc += s_part[w][lane];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int64_t i = i0 + v;
+            y[i] = i >= n ? T(0) : square ? acc[v] + static_cast<T>(shift) * P::q(q[i]) : acc[v];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- split-f16, d = 24 .. 48
@@ -2808,7 +2830,7 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
                     : prec == KRR_FP32 ? static_cast<const void *>(C.w32)
                                        : static_cast<const void *>(C.w16);
     a.w = w;
-    const dim3 gc((C.n_pad + BLOCK - 1) / BLOCK), gr((R.n_pad + BLOCK - 1) / BLOCK);
+    const dim3 gc((C.n_pad + BLOCK - 1) / BLOCK);
     if (C.kernel == KRR_KERNEL_GAUSS) {  // the Matern product reads q itself
         switch (prec) {
             case KRR_FP64: hipLaunchKernelGGL(k_prescale<KRR_FP64>, gc, dim3(BLOCK), 0, s, C.n_pad, q, w, sc.qw, active); break;
@@ -2849,18 +2871,19 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
     if (use_parts) {
         const int sq = square ? 1 : 0;
         const int ng = a.ngroups;
+        auto fgrid = [&](int rows) { return dim3(static_cast<unsigned>((R.n_pad + rows - 1) / rows)); };
         switch (prec) {
             case KRR_FP64:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
-                                   q, shift, sq, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP64>, fgrid(finish_rows<KRR_FP64>()), dim3(BLOCK), 0, s, R.n,
+                                   R.n_pad, ng, sc.parts, q, shift, sq, y, active);
                 break;
             case KRR_FP32:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
-                                   q, shift, sq, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_FP32>, fgrid(finish_rows<KRR_FP32>()), dim3(BLOCK), 0, s, R.n,
+                                   R.n_pad, ng, sc.parts, q, shift, sq, y, active);
                 break;
             default:
-                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, gr, dim3(BLOCK), 0, s, R.n, R.n_pad, ng, sc.parts,
-                                   q, shift, sq, y, active);
+                hipLaunchKernelGGL(k_kmvp_finish<KRR_BF16>, fgrid(finish_rows<KRR_BF16>()), dim3(BLOCK), 0, s, R.n,
+                                   R.n_pad, ng, sc.parts, q, shift, sq, y, active);
                 break;
         }
         KRR_HIP(hipGetLastError());

@@ -51,7 +51,6 @@ struct BatchedProduct {
     MSysB *d_sys = nullptr;
     MItem *d_items = nullptr;
     int64_t max_elems = 0;  // max over systems of n_pad * 16 * nrb
-    int64_t max_rows = 0;   // max over systems of n_pad * nrhs
     double pairs = 0.0;     // sum over systems of n^2
 };
 

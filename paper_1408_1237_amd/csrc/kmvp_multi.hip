@@ -588,29 +588,47 @@ __global__ __launch_bounds__(BLOCK) void k_multi_prescale(int64_t n_pad, int nrh
 }
 
 // Y[p_i + r ldy] = sum_s parts[s][r / 16][i][r % 16] + shift Q[p_i + r ldq], i < n.
+// A block takes 64 sorted rows x the 16 right-hand sides of block blockIdx.y, as
+// k_multi_finish_b: reads along the [row][16] layout (splits added from the
+// first, in order), an LDS turn-over, one wave per column on the way out.
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_multi_finish(int64_t n, int64_t n_pad, int nrhs, int nrb, int splits,
                                                         const int32_t *perm, const void *parts_, const void *Q_,
                                                         int64_t ldq, double shift, void *Y_, int64_t ldy) {
     using T = typename MP<PREC>::T;
+    constexpr int ROWS = 64;
+    constexpr int PER = ROWS * 16 / BLOCK;
+    __shared__ T s_y[16][ROWS + 1];
     const T *parts = static_cast<const T *>(parts_);
     const T *Q = static_cast<const T *>(Q_);
     T *Y = static_cast<T *>(Y_);
-    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
-    if (idx >= n_pad * nrhs) return;
-    const int64_t i = idx % n_pad;
-    const int r = static_cast<int>(idx / n_pad);
-    const int64_t p = perm ? static_cast<int64_t>(perm[i]) : (i < n ? i : -1);
-    if (p < 0) {
-        if (!perm) Y[i + static_cast<int64_t>(r) * ldy] = T(0);  // keep sorted vectors zero-padded
-        return;
+    const int rbk = blockIdx.y;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * ROWS;
+    if (row0 >= n_pad) return;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int l = threadIdx.x + e * BLOCK;  // row l / 16, right-hand side l % 16
+        T acc = T(0);
+        for (int k = 0; k < splits; ++k) acc += parts[((static_cast<int64_t>(k) * nrb + rbk) * n_pad + row0) * 16 + l];
+        s_y[l % 16][l / 16] = acc;
     }
-    const int rbk = r / 16, r16 = r % 16;
-    T s = T(0);
-    for (int k = 0; k < splits; ++k) s += parts[((static_cast<int64_t>(k) * nrb + rbk) * n_pad + i) * 16 + r16];
-    T qv = Q[p + static_cast<int64_t>(r) * ldq];
-    if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
-    Y[p + static_cast<int64_t>(r) * ldy] = s + static_cast<T>(shift) * qv;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int l = threadIdx.x + e * BLOCK;
+        const int c = l / ROWS, il = l % ROWS;
+        const int r = rbk * 16 + c;
+        if (r >= nrhs) continue;
+        const int64_t i = row0 + il;
+        const int64_t p = perm ? static_cast<int64_t>(perm[i]) : (i < n ? i : -1);
+        if (p < 0) {
+            if (!perm) Y[i + static_cast<int64_t>(r) * ldy] = T(0);  // keep sorted vectors zero-padded
+            continue;
+        }
+        T qv = Q[p + static_cast<int64_t>(r) * ldq];
+        if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
+        Y[p + static_cast<int64_t>(r) * ldy] = s_y[c][il] + static_cast<T>(shift) * qv;
+    }
 }
 
 // ---------------------------------------------------------------- batched over systems
@@ -644,31 +662,59 @@ __global__ __launch_bounds__(BLOCK) void k_multi_prescale_b(const MSysB *__restr
     qwt[idx] = v;
 }
 
+// Y = sum over the column chunks of the partial sums + shift Q, per system and
+// live column.  A block takes 64 rows x the 16 right-hand sides of one block:
+// it reads the [row][16] partial sums along memory (the chunks added from the
+// first, in order), turns the 64 x 16 sums over in LDS and writes each column's
+// 64 rows with one wave.
 template <int PREC>
 __global__ __launch_bounds__(BLOCK) void k_multi_finish_b(const MSysB *__restrict__ S, const void *Qall_, void *Yall_,
                                                           int nrhs, int inner, ColGate gate) {
     using T = typename MP<PREC>::T;
+    constexpr int ROWS = 64;
+    constexpr int PER = ROWS * 16 / BLOCK;
+    __shared__ T s_y[16][ROWS + 1];
     const MSysB &m = S[blockIdx.y];
     const int64_t n_pad = m.a.n_pad;
-    const int64_t idx = blockIdx.x * static_cast<int64_t>(BLOCK) + threadIdx.x;
-    if (idx >= n_pad * nrhs) return;
-    const int64_t i = idx % n_pad;
-    const int r = static_cast<int>(idx / n_pad);
-    if (!gate_live(gate, m.col0 + r)) return;
-    T *Y = static_cast<T *>(Yall_) + m.base;
-    if (i >= m.a.n) {
-        Y[idx] = T(0);
-        return;
+    const int nchunk = static_cast<int>(n_pad / ROWS);
+    const int nrb = m.a.nrb;
+    if (static_cast<int>(blockIdx.x) >= nchunk * nrb) return;
+    const int rbk = blockIdx.x / nchunk;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x % nchunk) * ROWS;
+    bool any = false;
+    for (int c = 0; c < 16; ++c) {
+        const int r = rbk * 16 + c;
+        any = any || (r < nrhs && gate_live(gate, m.col0 + r));
     }
-    const T *Q = static_cast<const T *>(Qall_) + m.base;
+    if (!any) return;
     const T *parts = static_cast<const T *>(m.a.parts);
-    const int rbk = r / 16, r16 = r % 16;
-    T s = T(0);
-    for (int k = 0; k < m.a.splits; ++k)
-        s += parts[((static_cast<int64_t>(k) * m.a.nrb + rbk) * n_pad + i) * 16 + r16];
-    T qv = Q[idx];
-    if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
-    Y[idx] = s + static_cast<T>(inner ? m.shift_in : m.shift_out) * qv;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int l = threadIdx.x + e * BLOCK;  // row l / 16, right-hand side l % 16
+        T acc = T(0);
+        for (int k = 0; k < m.a.splits; ++k)
+            acc += parts[((static_cast<int64_t>(k) * nrb + rbk) * n_pad + row0) * 16 + l];
+        s_y[l % 16][l / 16] = acc;
+    }
+    __syncthreads();
+    T *Y = static_cast<T *>(Yall_) + m.base;
+    const T *Q = static_cast<const T *>(Qall_) + m.base;
+    const T shift = static_cast<T>(inner ? m.shift_in : m.shift_out);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int l = threadIdx.x + e * BLOCK;
+        const int c = l / ROWS, il = l % ROWS;
+        const int r = rbk * 16 + c;
+        if (r >= nrhs || !gate_live(gate, m.col0 + r)) continue;
+        const int64_t i = row0 + il, idx = static_cast<int64_t>(r) * n_pad + i;
+        if (i >= m.a.n) {
+            Y[idx] = T(0);
+            continue;
+        }
+        T qv = Q[idx];
+        if (PREC == KRR_BF16) qv = bf16_to_f32(f32_to_bf16_rne(static_cast<float>(qv)));
+        Y[idx] = s_y[c][il] + shift * qv;
+    }
 }
 
 size_t batched_product_scratch_bytes(const Prepared &P, int nrhs, int min_tps) {
@@ -749,7 +795,7 @@ static hipError_t batched_run(const BatchedProduct &bp, const void *Qall, void *
     if (timed) KRR_HIP(hipEventRecord(ev0, s));
     KRR_HIP(launch_multi_b_d<PREC>(bp.dpad, bp.d_sys, bp.d_items, bp.nitems, gate, s));
     if (timed) KRR_HIP(hipEventRecord(ev1, s));
-    const dim3 gf((bp.max_rows + BLOCK - 1) / BLOCK, bp.nsys);
+    const dim3 gf((bp.max_elems + 64 * 16 - 1) / (64 * 16), bp.nsys);
     hipLaunchKernelGGL(k_multi_finish_b<PREC>, gf, dim3(BLOCK), 0, s, bp.d_sys, Qall, Yall, bp.nrhs, inner, gate);
     return hipGetLastError();
 }
@@ -850,9 +896,8 @@ static hipError_t multi_run(const Prepared &P, int nrhs, double shift, const int
     if (timed) KRR_HIP(hipEventRecord(ev0, s));
     KRR_HIP(launch_multi_d<PREC>(P.dpad, a, s));
     if (timed) KRR_HIP(hipEventRecord(ev1, s));
-    const int64_t tot = P.n_pad * nrhs;
-    hipLaunchKernelGGL(k_multi_finish<PREC>, dim3((tot + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P.n, P.n_pad, nrhs,
-                       nrb, a.splits, perm, a.parts, Q, ldq, shift, Y, ldy);
+    hipLaunchKernelGGL(k_multi_finish<PREC>, dim3(static_cast<unsigned>((P.n_pad + 63) / 64), nrb), dim3(BLOCK), 0, s,
+                       P.n, P.n_pad, nrhs, nrb, a.splits, perm, a.parts, Q, ldq, shift, Y, ldy);
     return hipGetLastError();
 }
 
