@@ -1557,6 +1557,13 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
         atomicAdd(a.skip_count, static_cast<unsigned long long>(skipped) * BLOCK);
 }
 
+// v of the lane that DPP control C selects within its row of 16 (every row and
+// bank written; each control used here has a source lane for every lane)
+template <int C>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), C, 0xF, 0xF, true));
+}
+
 // ---------------------------------------------------------------- symmetric split-f16 product
 //
 // The FP32 / BF16 Gaussian product of k_kmvp_mh with one exponential per
@@ -1852,21 +1859,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 buf ^= 1;
                 J = Jn;
             }
-            // the unit's target terms: summed over the 32 source lanes; lanes 0
-            // and 32 hold targets 8 (v / 4) + 4 h + v % 4 of the wave
+            // the unit's target terms, summed over the 32 source lanes of each
+            // half: v_permlane16_swap pairs value v of the even row of 16 lanes
+            // with value v + 8 of the odd row, so that after one add row parity
+            // b holds value v + 8 b summed over both rows; four DPP adds then
+            // sum each row (48 VALU operations against 80 lane permutes and 80
+            // adds of a shuffle per value and stage)
+            float red[8];
 #pragma unroll
-            for (int v2 = 0; v2 < 16; ++v2) {
-                float x = acc[v2];
-                x += __shfl_xor(x, 1, WAVE);
-                x += __shfl_xor(x, 2, WAVE);
-                x += __shfl_xor(x, 4, WAVE);
-                x += __shfl_xor(x, 8, WAVE);
-                x += __shfl_xor(x, 16, WAVE);
-                acc[v2] = x;
+            for (int v2 = 0; v2 < 8; ++v2) {
+                const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, acc[v2]),
+                                                                __builtin_bit_cast(unsigned, acc[v2 + 8]), false, false);
+                float x = __builtin_bit_cast(float, static_cast<unsigned>(r[0])) +
+                          __builtin_bit_cast(float, static_cast<unsigned>(r[1]));
+                x += dpp_f32<0x128>(x);  // row_ror:8, lane ^ 8
+                x += dpp_f32<0x124>(x);  // row_ror:4: with the above, the lanes of one residue mod 4
+                x += dpp_f32<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+                x += dpp_f32<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+                red[v2] = x;
             }
-            if (r32 == 0) {
+            if ((lane & 15) == 0) {
+                const int b4 = (lane >> 4) & 1;
 #pragma unroll
-                for (int v2 = 0; v2 < 16; ++v2) s_z[wv * 32 + 8 * (v2 / 4) + 4 * h + v2 % 4] = acc[v2];
+                for (int v2 = 0; v2 < 8; ++v2) {
+                    const int v = v2 + 8 * b4;
+                    s_z[wv * 32 + 8 * (v / 4) + 4 * h + v % 4] = red[v2];
+                }
             }
             __syncthreads();
             if (tid < UNIT) {
