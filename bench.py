@@ -100,13 +100,15 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + "
                 f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_ms<{D}>"
-    if (d <= 3 and prec != "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0"
+    if (d <= 12 and prec != "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0"
             and os.environ.get("KRR_KMVP_MG32", "0") != "1"):
-        # symmetric split-f16 product: per wave-step one 32x32x16 f16 op forms
-        # 1024 exponentials that serve 2048 terms (16 x (exp2 + 2 FMAs) per lane)
+        # symmetric split-f16 product: per wave-step ceil((3D + 2) / 16) 32x32x16
+        # f16 ops form 1024 exponentials that serve 2048 terms (16 x (exp2 +
+        # 2 FMAs) per lane)
         D = dpad(d)
-        cyc = C_MFMA_H32 + 16 * (C_EXP + 2 * C_FMA) + C_SYM_STEP
-        rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: one 32x32x16 f16 matrix-core op + "
+        kc = (3 * D + 2 + 15) // 16
+        cyc = kc * C_MFMA_H32 + 16 * (C_EXP + 2 * C_FMA) + C_SYM_STEP
+        rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core op(s) + "
                 f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_mhs<{D}, {tag}>"
     if d <= 16 and not valu:

@@ -1579,7 +1579,7 @@ __device__ __forceinline__ float dpp_f32(float v) {
 // and target weights live and cost a wave per SIMD), so a block takes a row
 // tile in two units of 128 rows, each against the same column tiles.
 template <int D, int PREC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_kmvp_mhs(KArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 3 : 2))) void k_kmvp_mhs(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
     using Off = typename P::Off;
@@ -1702,12 +1702,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             float oi[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) oi[k] = P::off(row_off[k * a.n_pad_rows + row0 + r32]);
-            // the lane's output targets 8 (v / 4) + 4 h + v % 4: their q (0 on the padding)
+            // the lane's output targets 8 (v / 4) + 4 h + v % 4: their q (0 on the
+            // padding).  The product is square, so q is the sorted vector of n_pad
+            // entries (as k_prescale reads it): the loads need no guard (a guard
+            // made a branch per load), a select zeroes the padding
             float qt[16], acc[16];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int64_t i = row0 + 8 * (v / 4) + 4 * h + v % 4;
-                qt[v] = i < a.n_rows ? P::q(q[i]) : 0.f;
+                const float qi = P::q(q[i]);
+                qt[v] = i < a.n_rows ? qi : 0.f;
                 acc[v] = 0.f;
             }
             int J = Jfirst;
@@ -2519,7 +2523,7 @@ int kmvp_ngroups(const Prepared &C) {
 int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
 // The symmetric products (k_kmvp_ms FP64, compiled dimensions up to 16;
-// k_kmvp_mhs FP32 / BF16, up to 3): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
+// k_kmvp_mhs FP32 / BF16, up to 12): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
 // that the summation order does not depend on tuning: about 100 groups up to
 // 1000 tiles, groups of 10 tiles above (clustered sets skip most tile pairs, and
 // small groups leave enough blocks with work), and at most about 512 groups
@@ -2740,10 +2744,10 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
 // (FP32 / BF16) and KRR_KMVP_SPLITS
 static bool use_sym_kernel(const Prepared &P, int prec) {
     if (!sym_capable(P) || use_valu_kernel() || std::getenv("KRR_KMVP_SPLITS")) return false;
-    // FP32 / BF16: up to the compiled dimension 3, where it measured faster
-    // (2-5 % on the kriging shape, 20 % on the clustered one); above, its extra
-    // FMA per pair costs about what the shared exponential saves
-    if (prec == KRR_FP64 ? P.dpad > 16 : (P.dpad > 3 || use_fp32_matrix_kernel())) return false;
+    // FP32 / BF16: up to the compiled dimension 12, where it measured faster
+    // (N = 1e5: 5-13 % at d = 4-12, 15 % on the kriging shape, 20 % on the
+    // clustered one); at 16 its operands and staging leave one wave per SIMD
+    if (prec == KRR_FP64 ? P.dpad > 16 : (P.dpad > 12 || use_fp32_matrix_kernel())) return false;
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
@@ -2771,6 +2775,10 @@ static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, hipStream_t s) {
         case 1: return launch_kmvp_sym_h<1, PREC>(a, s);
         case 2: return launch_kmvp_sym_h<2, PREC>(a, s);
         case 3: return launch_kmvp_sym_h<3, PREC>(a, s);
+        case 4: return launch_kmvp_sym_h<4, PREC>(a, s);
+        case 6: return launch_kmvp_sym_h<6, PREC>(a, s);
+        case 8: return launch_kmvp_sym_h<8, PREC>(a, s);
+        case 12: return launch_kmvp_sym_h<12, PREC>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -26,9 +26,14 @@ def test_product_peaks_by_hand(monkeypatch):
     # 1024 exponentials (2048 pair terms)
     assert bench.product_peak(3)[0] == pytest.approx(S * 2048 / (32 + 256 + 24))
     assert bench.product_peak(3)[2] == "k_kmvp_mhs<3, FP32>"
-    # the one-sided split-f16 kernel (d = 4, or KRR_KMVP_SYM=0): 1024 pairs per 32 + 16 x 12
-    assert bench.product_peak(4)[0] == pytest.approx(S * 1024 / 224)
+    # d = 8 (symmetric): ceil(26 / 16) = 2 f16 ops per 1024 exponentials
+    assert bench.product_peak(8)[0] == pytest.approx(S * 2048 / (2 * 32 + 256 + 24))
+    assert bench.product_peak(8)[2] == "k_kmvp_mhs<8, FP32>"
+    # d = 12 (symmetric): ceil(38 / 16) = 3 ops
+    assert bench.product_peak(12)[0] == pytest.approx(S * 2048 / (3 * 32 + 256 + 24))
+    # the one-sided split-f16 kernel (d = 16, or KRR_KMVP_SYM=0): 1024 pairs per kc x 32 + 16 x 12
     monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    assert bench.product_peak(4)[0] == pytest.approx(S * 1024 / 224)
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / 224)
     monkeypatch.delenv("KRR_KMVP_SYM")
     # FP32 d = 16: ceil(52 / 16) = 4 ops

@@ -220,7 +220,7 @@ def test_result_independent_of_column_splits(monkeypatch, prec, n, d):
     default = _gpu_mvp(x, sigma, q, 0.01, prec)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
-    if (prec == "fp64" and d <= 16) or d <= 3:
+    if d <= (16 if prec == "fp64" else 12):
         # the default product is the symmetric kernel here: its own fixed
         # summation order and tile anchors (FP64: equal to the exponential's
         # 2.5e-14 per term; FP32 / BF16: to their rounding), the same on every call
@@ -260,10 +260,12 @@ def test_symmetric_fp64_product(monkeypatch, n, d):
         check(y[rows], oracle.mvp_rows(x, sigma, q, rows, shift=0.02), "fp64", what=(n, d))
 
 
-# The symmetric FP32 / BF16 product (compiled dimensions up to 3) against the
+# The symmetric FP32 / BF16 product (compiled dimensions up to 12) against the
 # one-sided split-f16 kernel and the oracle.
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("n,d", [(1, 1), (200, 2), (257, 3), (3000, 3), (9000, 2), (30000, 1), (26000, 3)])
+@pytest.mark.parametrize("n,d", [(1, 1), (200, 2), (257, 3), (3000, 3), (9000, 2), (30000, 1), (26000, 3),
+                                 (257, 4), (3000, 5), (9000, 6), (2000, 8), (26000, 8), (12000, 10),
+                                 (5000, 12), (30000, 12)])
 def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
     x = workloads.random_points(520 + d, n, d, 2.0 * d ** 0.5, kind="normal")
     q = workloads.random_vector(521 + d, n)
@@ -288,7 +290,8 @@ def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
 # d = 12 (FP64) the groups of 6 tiles exceed the LDS room, so the memory path
 # runs either way and is checked against the oracle.
 @pytest.mark.parametrize("prec,n,d", [("fp64", 9000, 3), ("fp64", 30000, 12), ("fp64", 27000, 16),
-                                      ("fp32", 26000, 3), ("bf16", 9000, 2), ("fp64", 140000, 12)])
+                                      ("fp32", 26000, 3), ("bf16", 9000, 2), ("fp32", 30000, 8),
+                                      ("bf16", 12000, 12), ("fp64", 140000, 12)])
 def test_symmetric_slot_paths_agree(monkeypatch, prec, n, d):
     x = workloads.random_points(540 + d, n, d, 2.0 * d ** 0.5, kind="normal")
     q = workloads.random_vector(541 + d, n)
@@ -365,6 +368,36 @@ def test_split_f16_kernel_far_and_wide_tiles(monkeypatch, prec):
         check(got, want, prec)
         check(got[rows], want[rows], prec)
     assert _relerr(y, y_mg) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [6, 12])
+def test_symmetric_split_f16_far_and_wide_tiles(monkeypatch, prec, d):
+    # the three-cluster set above in d dimensions (clusters 6 and 40 bandwidths
+    # apart, a sparse cluster of wide tiles): the symmetric kernel (default for
+    # square products up to d = 12) against the one-sided one and the oracle,
+    # on all rows and on the sparse rows alone
+    rng = np.random.default_rng(19 + d)
+    shift_b, shift_c, shift_s = np.zeros(d), np.zeros(d), np.zeros(d)
+    shift_b[0], shift_c[1], shift_s[2] = 6.0, 40.0, 400.0
+    a = rng.normal(0.0, 1.0, size=(1200, d))
+    b = rng.normal(0.0, 1.0, size=(1100, d)) + shift_b
+    c = rng.normal(0.0, 1.0, size=(900, d)) + shift_c
+    sp = rng.uniform(-300.0, 300.0, size=(700, d)) + shift_s
+    x = np.ascontiguousarray(np.concatenate([a, b, c, sp]))
+    q = workloads.random_vector(20 + d, x.shape[0])
+    sigma = 0.5 * np.sqrt(d)
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    y = _gpu_mvp(x, sigma, q, 0.01, prec)
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    y1 = _gpu_mvp(x, sigma, q, 0.01, prec)
+    monkeypatch.delenv("KRR_KMVP_SYM")
+    want = oracle.mvp(x, sigma, call_vector(q, prec), shift=0.01)
+    rows = np.arange(3200, 3900)
+    for got in (y, y1):
+        check(got, want, prec, what=d)
+        check(got[rows], want[rows], prec, what=d)
+    assert _relerr(y, y1) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
