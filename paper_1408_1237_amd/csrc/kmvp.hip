@@ -1483,18 +1483,35 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mh(KArgs a) {
             };
             auto accumulate = [&](const floatx16_t (&G)[RG], const floatx4_t (&qv)[4],
                                   const floatx4_t (&qv2)[MAT ? 4 : 1]) {
+                if constexpr (MAT || D < 16) {
 #pragma unroll
-                for (int v = 0; v < 16; ++v)
+                    for (int v = 0; v < 16; ++v)
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg) {
-                        if constexpr (MAT) {
-                            const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[rg][v]));
-                            const float w = __builtin_fmaf(u, qv2[v / 4][v % 4], qv[v / 4][v % 4]);
-                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-u), w, acc[rg]);
-                        } else {
-                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                        for (int rg = 0; rg < RG; ++rg) {
+                            if constexpr (MAT) {
+                                const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[rg][v]));
+                                const float w = __builtin_fmaf(u, qv2[v / 4][v % 4], qv[v / 4][v % 4]);
+                                acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-u), w, acc[rg]);
+                            } else {
+                                acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
+                            }
                         }
-                    }
+                } else {
+                    // D = 16: all exponentials of the step first, then the FMAs
+                    // in the same order.  Written next to its FMA, each
+                    // exponential was scheduled (at this kernel's register use)
+                    // right before the FMA that reads it, with a wait state
+                    // between them: 3 % of the kernel
+                    floatx16_t E[RG];
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) E[rg][v] = __builtin_amdgcn_exp2f(G[rg][v]);
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg) acc[rg] = __builtin_fmaf(E[rg][v], qv[v / 4][v % 4], acc[rg]);
+                }
             };
             half8_t av[2][KC];
             floatx4_t qv[4], qv2[MAT ? 4 : 1];
@@ -2149,19 +2166,29 @@ __global__ __launch_bounds__(BLOCK) void k_kmvp_mhw(KArgs a) {
                     qv[m] = *reinterpret_cast<const floatx4_t *>(&s_q[buf][st * 32 + 8 * m + 4 * h]);
                     if constexpr (MAT) qv2[m] = *reinterpret_cast<const floatx4_t *>(&s_q2[buf][st * 32 + 8 * m + 4 * h]);
                 }
+                if constexpr (MAT) {
 #pragma unroll
-                for (int v = 0; v < 16; ++v)
+                    for (int v = 0; v < 16; ++v)
 #pragma unroll
-                    for (int rg = 0; rg < RG; ++rg) {
-                        if constexpr (MAT) {
+                        for (int rg = 0; rg < RG; ++rg) {
                             // G = (log2(e) s)^2: (1 + s) e^(-s) q = 2^(-u) (q + u ln2 q), u = sqrt(G)
                             const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[rg][v]));
                             const float w = __builtin_fmaf(u, qv2[v / 4][v % 4], qv[v / 4][v % 4]);
                             acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(-u), w, acc[rg]);
-                        } else {
-                            acc[rg] = __builtin_fmaf(__builtin_amdgcn_exp2f(G[rg][v]), qv[v / 4][v % 4], acc[rg]);
                         }
-                    }
+                } else {
+                    // exponentials first, then the FMAs in the same order (as
+                    // k_kmvp_mh at D = 16: no wait state between each pair)
+                    floatx16_t E[RG];
+#pragma unroll
+                    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) E[rg][v] = __builtin_amdgcn_exp2f(G[rg][v]);
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+#pragma unroll
+                        for (int rg = 0; rg < RG; ++rg) acc[rg] = __builtin_fmaf(E[rg][v], qv[v / 4][v % 4], acc[rg]);
+                }
             }
         } else {
             // wide tile: the direct form on the staged FP32 offsets, the two halves

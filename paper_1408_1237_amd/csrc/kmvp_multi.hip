@@ -60,10 +60,13 @@ struct MP<KRR_BF16> : MP<KRR_FP32> {
 namespace krr {
 
 // 16-row blocks processed together by one wave (register budget); a wave
-// covers its 64 rows in 4 / RB passes over the columns.
+// covers its 64 rows in 4 / RB passes over the columns.  FP64 keeps 2 RB D
+// doubles of target offsets live (oi and t): from D = 6 it takes two row
+// blocks, and its column steps are not unrolled, for two waves per SIMD
+// instead of one (FP64 16-RHS products 5-7 % faster at d = 6, 8).
 template <int D, int PREC>
 constexpr int multi_rb() {
-    return (PREC == KRR_FP64 ? 2 : 1) * D <= 16 ? 4 : (PREC == KRR_FP64 ? 2 : 1) * D <= 32 ? 2 : 1;
+    return (PREC == KRR_FP64 ? 4 : 1) * D <= 16 ? 4 : (PREC == KRR_FP64 ? 2 : 1) * D <= 32 ? 2 : 1;
 }
 
 // Global-address-space view of a pointer (the batched kernel reads its
@@ -92,7 +95,7 @@ __device__ __forceinline__ void multi_body(const MArgs &a, int bx, int by, int r
     constexpr int SC = multi_chunk<D, PREC>();
     constexpr int CPT = TILE / SC;  // chunks per column tile
     constexpr int LDO = SC + 16;
-    constexpr int UN = D > 16 ? 1 : 4;  // unroll of the column steps (register budget)
+    constexpr int UN = D > 16 ? 1 : (PREC == KRR_FP64 && D >= 6) ? 1 : 4;  // unroll of the column steps (registers)
     // The sources of the current column chunk (offsets and the 16 prescaled
     // right-hand sides) are staged in LDS, double-buffered: the block loads
     // chunk c + 1 from memory while it computes chunk c.
