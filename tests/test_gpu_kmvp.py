@@ -264,8 +264,8 @@ def test_symmetric_fp64_product(monkeypatch, n, d):
 # one-sided split-f16 kernel and the oracle.
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n,d", [(1, 1), (200, 2), (257, 3), (3000, 3), (9000, 2), (30000, 1), (26000, 3),
-                                 (257, 4), (3000, 5), (9000, 6), (2000, 8), (26000, 8), (12000, 10),
-                                 (5000, 12), (30000, 12)])
+                                 (1, 8), (2, 12), (257, 4), (3000, 5), (9000, 6), (2000, 8), (26000, 8),
+                                 (12000, 10), (5000, 12), (30000, 12)])
 def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
     x = workloads.random_points(520 + d, n, d, 2.0 * d ** 0.5, kind="normal")
     q = workloads.random_vector(521 + d, n)

@@ -37,18 +37,27 @@ def test_noalloc_matches_workspace_entry_point(prec):
     lib.krr_noalloc_scratch_bytes.restype = ctypes.c_size_t
     assert lib.krr_noalloc_scratch_bytes() == 128 << 20
     dt = torch.float64 if prec == "fp64" else torch.float32
-    for n, d, seed in ((50_000, 3, 1), (3_000, 2, 2)):  # the second call smaller
-        p = workloads.kriging(n=n) if d == 3 else workloads.plain_small(n=n)
-        x = torch.from_numpy(p.x).cuda()
+    # each call smaller than the one before; d = 8 takes the symmetric kernels'
+    # d > 3 forms
+    for n, d, seed in ((50_000, 3, 1), (8_000, 8, 3), (3_000, 2, 2)):
+        if d == 3:
+            p = workloads.kriging(n=n)
+            xn, sigma, shift = p.x, p.sigma, p.gamma
+        elif d == 2:
+            p = workloads.plain_small(n=n)
+            xn, sigma, shift = p.x, p.sigma, p.gamma
+        else:
+            xn, sigma, shift = workloads.random_points(40 + seed, n, d, 1.0, kind="normal"), 0.6 * np.sqrt(d), 1e-2
+        x = torch.from_numpy(xn).cuda()
         q = torch.from_numpy(workloads.random_vector(40 + seed, n)).to(dt).cuda()
-        y_ws = api.kmvp_gauss(x, p.sigma, q, shift=p.gamma, prec=prec)
-        rc, y = _noalloc(x, p.sigma, q, p.gamma, prec)
+        y_ws = api.kmvp_gauss(x, sigma, q, shift=shift, prec=prec)
+        rc, y = _noalloc(x, sigma, q, shift, prec)
         torch.cuda.synchronize()
         assert rc == 0
         assert torch.equal(y, y_ws)
         rows = np.random.default_rng(seed).choice(n, 32, replace=False)
-        want = oracle.mvp_rows(p.x, p.sigma, call_vector(q.double().cpu().numpy(), prec), rows, shift=p.gamma)
-        check(y.double().cpu().numpy()[rows], want, prec)
+        want = oracle.mvp_rows(xn, sigma, call_vector(q.double().cpu().numpy(), prec), rows, shift=shift)
+        check(y.double().cpu().numpy()[rows], want, prec, what=(n, d))
 
 
 def test_noalloc_refuses_sizes_beyond_its_array():
