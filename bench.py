@@ -59,7 +59,13 @@ C_SYM_STEP = 6 * C_FMA                      # symmetric products, per wave-step:
                                             # over the lane rows (permlane swaps, adds) and stored
 
 
-def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
+def sym_group_tiles(n: int) -> int:
+    """Tiles per group of the symmetric products for n points (the library's rule)."""
+    nt = (n + 255) // 256
+    return max(min((nt + 99) // 100, 10), (nt + 511) // 512)
+
+
+def product_peak(d: int, prec: str = "fp32", n: int | None = None) -> tuple[float, str, str]:
     """Peak pairs/s of the product kernel that runs for dimension d and precision.
 
     Matrix-core kernels, per 1024 pairs (one wave-step) plus, per lane, 16
@@ -100,7 +106,8 @@ def product_peak(d: int, prec: str = "fp32") -> tuple[float, str, str]:
         rule = (f"2048 pair terms (1024 exponentials) per {cyc} SIMD cycles: {4 * dk} 16x16x4 FP64 matrix-core ops + "
                 f"16 x (exp2 + 2 FMAs) per lane + the source-term reduction, serial issue; 1024 SIMDs x 2.4 GHz")
         return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_ms<{D}>"
-    if (d <= 12 and prec != "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0"
+    sym32 = d <= 12 or (d <= 16 and n is not None and sym_group_tiles(n) >= 8)  # square products of n points
+    if (sym32 and prec != "fp64" and not valu and os.environ.get("KRR_KMVP_SYM", "1") != "0"
             and os.environ.get("KRR_KMVP_MG32", "0") != "1"):
         # symmetric split-f16 product: per wave-step ceil((3D + 2) / 16) 32x32x16
         # f16 ops form 1024 exponentials that serve 2048 terms (16 x (exp2 +

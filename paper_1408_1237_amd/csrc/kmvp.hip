@@ -1594,7 +1594,9 @@ __device__ __forceinline__ float dpp_f32(float v) {
 // the wave (v_permlane32_swap) and over the waves in LDS once per tile pair.
 // A wave owns one group of 32 targets (two would keep twice the accumulators
 // and target weights live and cost a wave per SIMD), so a block takes a row
-// tile in two units of 128 rows, each against the same column tiles.
+// tile in two units of 128 rows, each against the same column tiles.  At
+// d = 16 the source tiles are staged in one buffer (after a barrier that ends
+// every wave's reads), which keeps two blocks per CU.
 template <int D, int PREC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 3 : 2))) void k_kmvp_mhs(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -1605,8 +1607,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
     constexpr int NW = BLOCK / WAVE;
     constexpr int UNIT = NW * 32;  // rows per row unit
     static_assert(P::wide <= 64.0, "the f16 range bound assumes R^2 <= 64 on folded tiles");
-    __shared__ __align__(16) half8_t s_a[2][2 * KC][TILE];
-    __shared__ __align__(16) float s_q[2][TILE];
+    // one staging buffer at d = 16 (two would leave one block per CU)
+    constexpr int NBUF = D >= 16 ? 1 : 2;
+    __shared__ __align__(16) half8_t s_a[NBUF][2 * KC][TILE];
+    __shared__ __align__(16) float s_q[NBUF][TILE];
     __shared__ float s_z[NW * TILE];
     __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
     // the source terms of group C, when it fits (entry [jl][j] owned by thread j;
@@ -1867,17 +1871,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
                     tile(std::true_type{});
                 else
                     tile(std::false_type{});
-                if (Jn < C1) stage_store(buf ^ 1);
-                __syncthreads();
+                if constexpr (NBUF == 2) {
+                    if (Jn < C1) stage_store(buf ^ 1);
+                    __syncthreads();
+                } else {
+                    __syncthreads();  // every wave is done with the one staging buffer
+                    if (Jn < C1) stage_store(0);
+                }
                 if (sym) {
                     const float z = (s_z[tid] + s_z[TILE + tid]) + (s_z[2 * TILE + tid] + s_z[3 * TILE + tid]);
                     if (zlds)
                         s_zacc[J - C0][tid] = __builtin_fmaf(z, wj, s_zacc[J - C0][tid]);
                     else
                         zslot[jz] = __builtin_fmaf(z, wj, zold);
-                    __syncthreads();  // s_z is rewritten by the next tile pair
                 }
-                buf ^= 1;
+                if (sym || NBUF == 1) __syncthreads();  // s_z rewritten next; the staging visible
+                if constexpr (NBUF == 2) buf ^= 1;
                 J = Jn;
             }
             // the unit's target terms, summed over the 32 source lanes of each
@@ -2550,7 +2559,7 @@ int kmvp_ngroups(const Prepared &C) {
 int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 
 // The symmetric products (k_kmvp_ms FP64, compiled dimensions up to 16;
-// k_kmvp_mhs FP32 / BF16, up to 12): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
+// k_kmvp_mhs FP32 / BF16, up to 12, and 16 with groups of 8 tiles or more): Gaussian point sets, groups of gs tiles with gs fixed by the tile count, so
 // that the summation order does not depend on tuning: about 100 groups up to
 // 1000 tiles, groups of 10 tiles above (clustered sets skip most tile pairs, and
 // small groups leave enough blocks with work), and at most about 512 groups
@@ -2772,9 +2781,13 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
 static bool use_sym_kernel(const Prepared &P, int prec) {
     if (!sym_capable(P) || use_valu_kernel() || std::getenv("KRR_KMVP_SPLITS")) return false;
     // FP32 / BF16: up to the compiled dimension 12, where it measured faster
-    // (N = 1e5: 5-13 % at d = 4-12, 15 % on the kriging shape, 20 % on the
-    // clustered one); at 16 its operands and staging leave one wave per SIMD
-    if (prec == KRR_FP64 ? P.dpad > 16 : (P.dpad > 12 || use_fp32_matrix_kernel())) return false;
+    // (N = 1e5: 4-10 % at d = 4-12, 15 % on the kriging shape, 20 % on the
+    // clustered one); at 16 only with groups of at least 8 tiles (N above
+    // about 180,000: 8 % at N = 2e5), where a row unit meets enough column
+    // tiles to repay its set-up (N = 1e5, groups of 4: 11 % slower)
+    if (prec == KRR_FP64 ? P.dpad > 16
+                         : (P.dpad > 16 || (P.dpad == 16 && kmvp_sym_group_tiles(P) < 8) || use_fp32_matrix_kernel()))
+        return false;
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
@@ -2806,6 +2819,7 @@ static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, hipStream_t s) {
         case 6: return launch_kmvp_sym_h<6, PREC>(a, s);
         case 8: return launch_kmvp_sym_h<8, PREC>(a, s);
         case 12: return launch_kmvp_sym_h<12, PREC>(a, s);
+        case 16: return launch_kmvp_sym_h<16, PREC>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -31,6 +31,11 @@ def test_product_peaks_by_hand(monkeypatch):
     assert bench.product_peak(8)[2] == "k_kmvp_mhs<8, FP32>"
     # d = 12 (symmetric): ceil(38 / 16) = 3 ops
     assert bench.product_peak(12)[0] == pytest.approx(S * 2048 / (3 * 32 + 256 + 24))
+    # d = 16: symmetric only with groups of 8 tiles or more (N = 2e5: 782 tiles, groups of 8)
+    assert bench.sym_group_tiles(200_000) == 8 and bench.sym_group_tiles(100_000) == 4
+    assert bench.product_peak(16, n=200_000)[2] == "k_kmvp_mhs<16, FP32>"
+    assert bench.product_peak(16, n=200_000)[0] == pytest.approx(S * 2048 / (4 * 32 + 256 + 24))
+    assert bench.product_peak(16, n=100_000)[2] == "k_kmvp_mh<16, FP32>"
     # the one-sided split-f16 kernel (d = 16, or KRR_KMVP_SYM=0): 1024 pairs per kc x 32 + 16 x 12
     monkeypatch.setenv("KRR_KMVP_SYM", "0")
     assert bench.product_peak(4)[0] == pytest.approx(S * 1024 / 224)

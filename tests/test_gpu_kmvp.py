@@ -260,12 +260,13 @@ def test_symmetric_fp64_product(monkeypatch, n, d):
         check(y[rows], oracle.mvp_rows(x, sigma, q, rows, shift=0.02), "fp64", what=(n, d))
 
 
-# The symmetric FP32 / BF16 product (compiled dimensions up to 12) against the
-# one-sided split-f16 kernel and the oracle.
+# The symmetric FP32 / BF16 product (compiled dimensions up to 12, and 16 from
+# groups of 8 tiles: N = 200,000) against the one-sided split-f16 kernel and the
+# oracle.
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n,d", [(1, 1), (200, 2), (257, 3), (3000, 3), (9000, 2), (30000, 1), (26000, 3),
                                  (1, 8), (2, 12), (257, 4), (3000, 5), (9000, 6), (2000, 8), (26000, 8),
-                                 (12000, 10), (5000, 12), (30000, 12)])
+                                 (12000, 10), (5000, 12), (30000, 12), (200000, 16)])
 def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
     x = workloads.random_points(520 + d, n, d, 2.0 * d ** 0.5, kind="normal")
     q = workloads.random_vector(521 + d, n)
@@ -291,7 +292,7 @@ def test_symmetric_split_f16_product(monkeypatch, prec, n, d):
 # runs either way and is checked against the oracle.
 @pytest.mark.parametrize("prec,n,d", [("fp64", 9000, 3), ("fp64", 30000, 12), ("fp64", 27000, 16),
                                       ("fp32", 26000, 3), ("bf16", 9000, 2), ("fp32", 30000, 8),
-                                      ("bf16", 12000, 12), ("fp64", 140000, 12)])
+                                      ("bf16", 12000, 12), ("fp32", 200000, 16), ("fp64", 140000, 12)])
 def test_symmetric_slot_paths_agree(monkeypatch, prec, n, d):
     x = workloads.random_points(540 + d, n, d, 2.0 * d ** 0.5, kind="normal")
     q = workloads.random_vector(541 + d, n)
