@@ -1597,7 +1597,7 @@ __device__ __forceinline__ float dpp_f32(float v) {
 // tile in two units of 128 rows, each against the same column tiles.  At
 // d = 16 the source tiles are staged in one buffer (after a barrier that ends
 // every wave's reads), which keeps two blocks per CU.
-template <int D, int PREC>
+template <int D, int PREC, bool MAT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 3 : 2))) void k_kmvp_mhs(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using P = Prec<PREC>;
@@ -1678,7 +1678,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
         } else {
 #pragma unroll
             for (int c = 0; c < 2 * KC; ++c) st_a[c] = slots[c * n_pad + j];
-            st_q = qw[j];
+            st_q = MAT ? P::q(q[j]) : qw[j];
         }
     };
     auto stage_store = [&](int buf) {
@@ -1751,7 +1751,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
                 const bool sym = J != I;
                 const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
                 const float zold = (sym && !zlds) ? zslot[jz] : 0.f;
-                const float wj = (sym && r2 <= P::wide) ? wsrc[jz] : 1.f;
+                const float wj = (sym && r2 <= P::wide && !MAT) ? wsrc[jz] : 1.f;  // Matern: no folding
                 auto tile = [&](auto sym_c) {
                     constexpr bool SYM = decltype(sym_c)::value;
                     if (r2 <= P::wide) {
@@ -1765,12 +1765,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
                             tt = __builtin_fma(td, td, tt);
                         }
                         const bool far = static_cast<float>(tt) > far_t2;
-                        const _Float16 z16 = static_cast<_Float16>(0.f);
+                        const _Float16 z16 = static_cast<_Float16>(0.f), one16 = static_cast<_Float16>(1.f);
                         HiLo v[D], c, c2;
+                        if constexpr (MAT) {
+                            // -2 t', |t'|^2 and (1, 1) for the source constant, as k_kmvp_mh
 #pragma unroll
-                        for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
-                        c = far ? HiLo{static_cast<_Float16>(-2000.f), z16} : split_f16(-static_cast<float>(tt) - njf);
-                        c2 = HiLo{z16, z16};
+                            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : -2.f * LOG2E_F * t[k]);
+                            c = far ? HiLo{static_cast<_Float16>(60000.f), z16}
+                                    : split_f16(LOG2E_F * LOG2E_F * static_cast<float>(tt));
+                            c2 = HiLo{one16, one16};
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < D; ++k) v[k] = split_f16(far ? 0.f : 2.f * t[k]);
+                            c = far ? HiLo{static_cast<_Float16>(-2000.f), z16}
+                                    : split_f16(-static_cast<float>(tt) - njf);
+                            c2 = HiLo{z16, z16};
+                        }
                         half8_t tval[KC];
 #pragma unroll
                         for (int kc = 0; kc < KC; ++kc) {
@@ -1796,7 +1806,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
                             float zl[4] = {0.f, 0.f, 0.f, 0.f};  // independent chains
 #pragma unroll
                             for (int v2 = 0; v2 < 16; ++v2) {
-                                const float e = __builtin_amdgcn_exp2f(G[v2]);
+                                // the pair's kernel value: 2^G (folded Gaussian), or the
+                                // Matern (1 + s) e^-s = 2^-u (1 + u ln2), u = sqrt(G)
+                                float e;
+                                if constexpr (MAT) {
+                                    const float u = __builtin_amdgcn_sqrtf(__builtin_fabsf(G[v2]));
+                                    e = __builtin_amdgcn_exp2f(-u) * __builtin_fmaf(u, LN2_F, 1.f);
+                                } else {
+                                    e = __builtin_amdgcn_exp2f(G[v2]);
+                                }
                                 acc[v2] = __builtin_fmaf(e, qs, acc[v2]);
                                 if constexpr (SYM) zl[v2 % 4] = __builtin_fmaf(e, qt[v2], zl[v2 % 4]);
                             }
@@ -1853,7 +1871,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 
                                     const float dd = tg[k] - __builtin_bit_cast(float, w);
                                     ss = __builtin_fmaf(dd, dd, ss);
                                 }
-                                const float e = __builtin_amdgcn_exp2f(-ss);
+                                float e;
+                                if constexpr (MAT) {
+                                    const float sd = __builtin_sqrtf(ss);
+                                    const float e0 = __builtin_amdgcn_exp2f(-LOG2E_F * sd);
+                                    e = __builtin_fmaf(sd, e0, e0);
+                                } else {
+                                    e = __builtin_amdgcn_exp2f(-ss);
+                                }
                                 sacc = __builtin_fmaf(e, s_q[buf][cj], sacc);
                                 if constexpr (SYM) zs[st] = __builtin_fmaf(e, qi, zs[st]);
                             }
@@ -2565,7 +2590,8 @@ int kmvp_max_splits(const Prepared &P) { return kmvp_ngroups(P); }
 // small groups leave enough blocks with work), and at most about 512 groups
 // (the partial sums hold one slot per group and point).
 static bool sym_capable(const Prepared &P) {
-    return P.kernel == KRR_KERNEL_GAUSS && P.dpad <= 16 && P.ntiles <= 512 * MS_MAX_GROUP_TILES;
+    return (P.kernel == KRR_KERNEL_GAUSS || P.kernel == KRR_KERNEL_MATERN32) && P.dpad <= 16 &&
+           P.ntiles <= 512 * MS_MAX_GROUP_TILES;
 }
 int kmvp_sym_group_tiles(const Prepared &P) {
     const int a = (P.ntiles + 99) / 100, b = (P.ntiles + 511) / 512;
@@ -2775,7 +2801,7 @@ static hipError_t launch_kmvp(const KArgs &a, int kernel, hipStream_t s) {
     return hipGetLastError();
 }
 
-// KRR_KMVP_SYM=0 keeps the square Gaussian products one-sided (used to
+// KRR_KMVP_SYM=0 keeps the square products one-sided (used to
 // cross-check the symmetric kernels); so do KRR_KMVP_VALU=1, KRR_KMVP_MG32=1
 // (FP32 / BF16) and KRR_KMVP_SPLITS
 static bool use_sym_kernel(const Prepared &P, int prec) {
@@ -2788,6 +2814,9 @@ static bool use_sym_kernel(const Prepared &P, int prec) {
     if (prec == KRR_FP64 ? P.dpad > 16
                          : (P.dpad > 16 || (P.dpad == 16 && kmvp_sym_group_tiles(P) < 8) || use_fp32_matrix_kernel()))
         return false;
+    // Matern-3/2: the split-f16 form only (FP32 / BF16), up to the compiled
+    // dimension 12
+    if (P.kernel == KRR_KERNEL_MATERN32 && (prec == KRR_FP64 || P.dpad > 12)) return false;
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
@@ -2803,23 +2832,26 @@ static hipError_t launch_kmvp_sym(const KArgs &a, hipStream_t s) {
 }
 
 template <int D, int PREC>
-static hipError_t launch_kmvp_sym_h(const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp_sym_h(const KArgs &a, bool mat, hipStream_t s) {
     const int nb = a.ngroups * (a.ngroups + 1) / 2;
-    hipLaunchKernelGGL((k_kmvp_mhs<D, PREC>), dim3(nb), dim3(BLOCK), 0, s, a);
+    if (mat)
+        hipLaunchKernelGGL((k_kmvp_mhs<D, PREC, true>), dim3(nb), dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_kmvp_mhs<D, PREC, false>), dim3(nb), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, bool mat, hipStream_t s) {
     switch (dpad) {
-        case 1: return launch_kmvp_sym_h<1, PREC>(a, s);
-        case 2: return launch_kmvp_sym_h<2, PREC>(a, s);
-        case 3: return launch_kmvp_sym_h<3, PREC>(a, s);
-        case 4: return launch_kmvp_sym_h<4, PREC>(a, s);
-        case 6: return launch_kmvp_sym_h<6, PREC>(a, s);
-        case 8: return launch_kmvp_sym_h<8, PREC>(a, s);
-        case 12: return launch_kmvp_sym_h<12, PREC>(a, s);
-        case 16: return launch_kmvp_sym_h<16, PREC>(a, s);
+        case 1: return launch_kmvp_sym_h<1, PREC>(a, mat, s);
+        case 2: return launch_kmvp_sym_h<2, PREC>(a, mat, s);
+        case 3: return launch_kmvp_sym_h<3, PREC>(a, mat, s);
+        case 4: return launch_kmvp_sym_h<4, PREC>(a, mat, s);
+        case 6: return launch_kmvp_sym_h<6, PREC>(a, mat, s);
+        case 8: return launch_kmvp_sym_h<8, PREC>(a, mat, s);
+        case 12: return launch_kmvp_sym_h<12, PREC>(a, mat, s);
+        case 16: return launch_kmvp_sym_h<16, PREC>(a, mat, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2923,13 +2955,15 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
             a.off = C.off32;
             a.pm = C.pm32;
             a.row_off = R.off32;
-            e = sym ? launch_kmvp_sym_hd<KRR_FP32>(C.dpad, a, s) : launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_hd<KRR_FP32>(C.dpad, a, C.kernel == KRR_KERNEL_MATERN32, s)
+                    : launch_kmvp_d<KRR_FP32>(C.dpad, a, C.kernel, s);
             break;
         case KRR_BF16:
             a.off = C.offb;
             a.pm = C.pmb;
             a.row_off = R.offb;
-            e = sym ? launch_kmvp_sym_hd<KRR_BF16>(C.dpad, a, s) : launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_hd<KRR_BF16>(C.dpad, a, C.kernel == KRR_KERNEL_MATERN32, s)
+                    : launch_kmvp_d<KRR_BF16>(C.dpad, a, C.kernel, s);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -139,6 +139,29 @@ def test_matern_matrix_core_kernel_matches_valu_kernel(monkeypatch, prec, d):
     check(b, want, prec, floor=floor)
 
 
+# The symmetric Matern product (square FP32 / BF16 products up to d = 12: one
+# kernel value per unordered pair for both of its terms) against the one-sided
+# kernel (KRR_KMVP_SYM=0) and the oracle: a single point, ragged tiles, one and
+# several tiles per group.
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d", [(1, 3), (300, 1), (2500, 3), (9000, 8), (4000, 12), (30000, 2)])
+def test_matern_symmetric_product(monkeypatch, prec, n, d):
+    x = workloads.random_points(140 + d, n, d, 1.0, kind="normal")
+    q = workloads.random_vector(141 + d, n)
+    h = 0.8 * np.sqrt(d)
+    monkeypatch.delenv("KRR_KMVP_SYM", raising=False)
+    y = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
+    y1 = _mvp(x, h, q, 0.03, prec)
+    monkeypatch.delenv("KRR_KMVP_SYM")
+    assert _rel(y, y1) <= 1e-5
+    q32 = call_vector(q, prec)
+    rows = np.arange(n) if n <= 9000 else np.random.default_rng(n).choice(n, 64, replace=False)
+    ref = lambda v: oracle.matern_mvp_rows(x, h, v, rows, shift=0.03)  # noqa: E731
+    floor = format_floor(ref, q32) if prec == "bf16" else (0.0, 0.0)
+    check(y[rows], ref(q32), prec, floor=floor, what=(n, d))
+
+
 def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch):
     # two tight clusters 150 length scales apart (targets of one are beyond the
     # clamp distance from every tile of the other) and a sparse cluster with wide
