@@ -144,11 +144,25 @@ def product_peak(d: int, prec: str = "fp32", n: int | None = None) -> tuple[floa
 
 
 def matern_peak(d: int) -> tuple[float, str, str]:
-    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 48 (split-f16 kernels),
+    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 12 (square products):
+    the symmetric split-f16 kernel, per 2048 pair terms the one-sided step's
+    operations with 4 FMA-class ops per pair plus the source-term reduction.
+    d <= 48 (one-sided split-f16 kernels),
     per 1024 pairs: ceil((3D + 4) / 16) 32x32x16 f16 matrix-core operations and,
     per lane, 16 x (sqrt + exp2 + 2 FMAs), serial issue (v_sqrt_f32 costs 8
     cycles, as v_exp_f32).  Otherwise (VALU kernel) per 64 pairs: 2d + 3
     FMA-class operations, sqrt and exp2 per lane."""
+    if (d <= 12 and os.environ.get("KRR_KMVP_VALU", "0") != "1" and os.environ.get("KRR_KMVP_SYM", "1") != "0"
+            and os.environ.get("KRR_KMVP_MG32", "0") != "1"):
+        # symmetric split-f16 form (square products): per wave-step 1024 kernel
+        # values serve 2048 terms, 16 x (sqrt + exp2 + 4 FMA-class ops) per lane
+        D = dpad(d)
+        kc = (3 * D + 4 + 15) // 16
+        cyc = kc * C_MFMA_H32 + 16 * (C_SQRT + C_EXP + 4 * C_FMA) + C_SYM_STEP
+        rule = (f"2048 pair terms (1024 kernel values) per {cyc} SIMD cycles: {kc} 32x32x16 f16 matrix-core op(s) + "
+                f"16 x (sqrt + exp2 + 4 FMA-class ops) per lane + the source-term reduction, serial issue; "
+                f"1024 SIMDs x 2.4 GHz")
+        return SIMD_CYCLES_S * 2048 / cyc, rule, f"k_kmvp_mhs<{D}, FP32, matern>"
     if d <= 48 and os.environ.get("KRR_KMVP_VALU", "0") != "1":
         D = dpad(d)
         kc = (3 * D + 4 + 15) // 16

@@ -69,9 +69,14 @@ def test_product_peaks_by_hand(monkeypatch):
     monkeypatch.delenv("KRR_KMVP_VALU")
     monkeypatch.setenv("KRR_KMVP_MG32", "1")
     assert bench.product_peak(3)[0] == pytest.approx(S * 1024 / (4 * 32 + 192))
-    # Matern d = 8: two f16 ops + 16 x (sqrt 8 + exp2 8 + 2 FMAs)
+    # Matern d = 8, symmetric: two f16 ops + 16 x (sqrt 8 + exp2 8 + 4 FMA-class ops) + 24 per
+    # 2048 terms; one-sided (KRR_KMVP_SYM=0): two f16 ops + 16 x (sqrt 8 + exp2 8 + 2 FMAs) per 1024
     monkeypatch.delenv("KRR_KMVP_MG32")
+    assert bench.matern_peak(8)[0] == pytest.approx(S * 2048 / (64 + 512 + 24))
+    assert bench.matern_peak(8)[2] == "k_kmvp_mhs<8, FP32, matern>"
+    monkeypatch.setenv("KRR_KMVP_SYM", "0")
     assert bench.matern_peak(8)[0] == pytest.approx(S * 1024 / (64 + 384))
+    monkeypatch.delenv("KRR_KMVP_SYM")
     # 16-RHS product d = 4: one 16x16x32 f16 op + 4 exp2 + four 16x16x4 FP32 ops per 4096 pair-RHS
     assert bench.multi_peak(4)[0] == pytest.approx(S * 4096 / (16 + 32 + 128))
 
