@@ -162,11 +162,12 @@ def test_matern_symmetric_product(monkeypatch, prec, n, d):
     check(y[rows], ref(q32), prec, floor=floor, what=(n, d))
 
 
-def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch, prec):
     # two tight clusters 150 length scales apart (targets of one are beyond the
     # clamp distance from every tile of the other) and a sparse cluster with wide
-    # tiles; the matrix-core kernel is held to the oracle (all rows and the
-    # sparse rows) and to the VALU kernel
+    # tiles; the default (symmetric) product is held to the oracle (all rows and
+    # the sparse rows; BF16: or its format floor) and to the VALU kernel
     rng = np.random.default_rng(23)
     a = rng.normal(0.0, 1.0, size=(1000, 2))
     b = rng.normal(0.0, 1.0, size=(900, 2)) + np.array([150.0, 0.0])
@@ -174,15 +175,22 @@ def test_matern_matrix_core_kernel_far_and_wide_tiles(monkeypatch):
     x = np.ascontiguousarray(np.concatenate([a, b, s]))
     q = workloads.random_vector(24, x.shape[0])
     monkeypatch.setenv("KRR_KMVP_VALU", "0")
-    y = _mvp(x, 1.0, q, 0.01, "fp32")
+    y = _mvp(x, 1.0, q, 0.01, prec)
     monkeypatch.setenv("KRR_KMVP_VALU", "1")
-    yv = _mvp(x, 1.0, q, 0.01, "fp32")
+    yv = _mvp(x, 1.0, q, 0.01, prec)
     monkeypatch.delenv("KRR_KMVP_VALU")
-    want = oracle.matern_mvp(x, 1.0, call_vector(q, "fp32"), shift=0.01)
+    q32 = call_vector(q, prec)
+    ref = lambda v: oracle.matern_mvp(x, 1.0, v, shift=0.01)  # noqa: E731
+    want = ref(q32)
     assert _rel(y, yv) <= 1e-5
-    check(y, want, "fp32")
     rows = np.arange(1900, 2400)
-    check(y[rows], want[rows], "fp32")
+    if prec == "bf16":
+        check(y, want, prec, floor=format_floor(ref, q32))
+        rref = lambda v: ref(v)[rows]  # noqa: E731
+        check(y[rows], want[rows], prec, floor=format_floor(rref, q32))
+    else:
+        check(y, want, prec)
+        check(y[rows], want[rows], prec)
 
 
 @pytest.mark.parametrize("d", [24, 48])
