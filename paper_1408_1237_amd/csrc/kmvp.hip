@@ -877,21 +877,24 @@ constexpr bool ms_supported() {
 
 // Tiles of a column group whose source terms k_kmvp_ms keeps in LDS: what fits
 // beside its other LDS arrays within 76 KiB (two blocks per CU), at most 16.
-template <int D>
+template <int D, bool MAT>
 constexpr int ms_zacc_tiles() {
-    const int nbuf = D >= 16 ? 1 : 2, tn = D <= 3 ? 4096 : 256;
-    const int other = nbuf * D * (TILE + 16) * 8 + nbuf * TILE * 8 + tn * 8 + (BLOCK / WAVE) * TILE * 8 + 512;
+    const int nbuf = D >= 16 ? 1 : 2, tn = (D <= 3 && !MAT) ? 4096 : 256;
+    const int other = nbuf * D * (TILE + 16) * 8 + nbuf * TILE * 8 * (MAT ? 2 : 1) + tn * 8 +
+                      (BLOCK / WAVE) * TILE * 8 + 512;
     const int t = (76 * 1024 - other) / (TILE * 8);
     return t > 16 ? 16 : (t < 1 ? 1 : t);
 }
 
-template <int D>
+template <int D, bool MAT>
 __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     if (a.active != nullptr && *a.active == 0) return;
     using M = MG<KRR_FP64>;
     using T = double;
     using V4 = doublex4_t;
-    constexpr int DK = (D + 4) / 4;  // chunks of 4 over the d + 1 coordinates
+    // chunks of 4 over the d + 1 coordinates [o, 1] (Matern: d + 2, [o, 1, |o'|^2])
+    constexpr int DK = (D + (MAT ? 5 : 4)) / 4;
+    constexpr double L2E = 1.4426950408889634074, LN2 = 0.69314718055994530942;
     // groups of 16 targets per wave: 4 (a block takes a row tile at once), or
     // 2 at d = 16, where four groups' operands and accumulators do not fit (a
     // block then takes a row tile in two units of 128 rows); there the source
@@ -901,7 +904,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     constexpr int NBUF = D >= 16 ? 1 : 2;
     constexpr int NW = BLOCK / WAVE;
     constexpr int LDO = TILE + 16;
-    constexpr int TN = D <= 3 ? 4096 : 256;  // exp2_tab table (as k_kmvp_mg)
+    // exp2_tab table (as k_kmvp_mg; Matern: the 256-entry one, which leaves room
+    // for its staged source constants within two blocks per CU)
+    constexpr int TN = (D <= 3 && !MAT) ? 4096 : 256;
     // target offsets kept in registers at small d, else re-read per tile pair
     constexpr bool KEEP = D <= 4;
     __shared__ T s_off[NBUF][D][LDO];
@@ -913,8 +918,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
     // the column tiles of group C not far from the current row tile
     __shared__ unsigned char s_live[MS_MAX_GROUP_TILES];
     // the source terms of group C, when it fits (entry [jl][j] owned by thread j)
-    constexpr int ZMAX = ms_zacc_tiles<D>();
+    constexpr int ZMAX = ms_zacc_tiles<D, MAT>();
     __shared__ T s_zacc[ZMAX][TILE];
+    // Matern: the sources' log2(e)^2 |o|^2 (the prepared FP64 squares)
+    __shared__ T s_e[MAT ? NBUF : 1][MAT ? TILE : 1];
     for (int k = threadIdx.x; k < TN; k += BLOCK) s_exp2[k] = TN == 256 ? EXP2_TABLE256[k] : EXP2_TABLE4096[k];
     const T *__restrict__ off = static_cast<const T *>(a.off);
     const T *__restrict__ row_off = static_cast<const T *>(a.row_off);
@@ -964,17 +971,23 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
             zslot[static_cast<int64_t>(J) * TILE + tid] = T(0);
     }
 
-    T st_o[D], st_q;
+    T st_o[D], st_q, st_e = T(0);
     auto stage_load = [&](int J) {
         const int64_t j = static_cast<int64_t>(J) * TILE + tid;
 #pragma unroll
         for (int k = 0; k < D; ++k) st_o[k] = off[k * n_pad + j];
-        st_q = a.tile_r2[J] > WIDE_R2_FP64 ? q[j] : qw[j];
+        if constexpr (MAT) {
+            st_q = q[j];  // no folded weights
+            st_e = static_cast<T>(L2E * L2E) * a.sq[j];
+        } else {
+            st_q = a.tile_r2[J] > WIDE_R2_FP64 ? q[j] : qw[j];
+        }
     };
     auto stage_store = [&](int buf) {
 #pragma unroll
         for (int k = 0; k < D; ++k) s_off[buf][k][tid] = st_o[k];
         s_q[buf][tid] = st_q;
+        if constexpr (MAT) s_e[buf][tid] = st_e;
     };
     // the source terms of one step (lane-local sum zl over the lane's targets):
     // summed over the 4 lane rows (the same sum, in the same order, in each;
@@ -1062,17 +1075,31 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                             t[k] = (aI[k] - aJ[k]) + o;
                             tt = __builtin_fma(t[k], t[k], tt);
                         }
-                        // a target whose every exponent against the tile is <= -1100
-                        // gets -2000 for the whole tile (exp2 is 0 either way)
-                        const bool far = tt > static_cast<double>(a.tile_far64[J]);
-                        const T c = far ? T(-2000.0 * TN) : (-tt - nj) * T(TN);
+                        if constexpr (MAT) {
+                            // [-2 log2(e)^2 t, log2(e)^2 |t|^2, 1]: the product forms
+                            // (log2(e) s)^2 (as k_kmvp_mgw; far pairs reach the exponential's
+                            // clamp)
 #pragma unroll
-                        for (int kc = 0; kc < DK; ++kc) {
-                            const int dim = 4 * kc + g;
-                            T v = (dim == D) ? c : T(0);
+                            for (int kc = 0; kc < DK; ++kc) {
+                                const int dim = 4 * kc + g;
+                                T v = (dim == D) ? static_cast<T>(L2E * L2E) * tt : (dim == D + 1 ? T(1) : T(0));
 #pragma unroll
-                            for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2 * TN) * t[k]) : v;
-                            bval[rg][kc] = v;
+                                for (int k = 0; k < D; ++k) v = (dim == k) ? static_cast<T>(-2.0 * L2E * L2E) * t[k] : v;
+                                bval[rg][kc] = v;
+                            }
+                        } else {
+                            // a target whose every exponent against the tile is <= -1100
+                            // gets -2000 for the whole tile (exp2 is 0 either way)
+                            const bool far = tt > static_cast<double>(a.tile_far64[J]);
+                            const T c = far ? T(-2000.0 * TN) : (-tt - nj) * T(TN);
+#pragma unroll
+                            for (int kc = 0; kc < DK; ++kc) {
+                                const int dim = 4 * kc + g;
+                                T v = (dim == D) ? c : T(0);
+#pragma unroll
+                                for (int k = 0; k < D; ++k) v = (dim == k) ? (far ? T(0) : T(2 * TN) * t[k]) : v;
+                                bval[rg][kc] = v;
+                            }
                         }
                     }
                     auto load_step = [&](int cb, T (&av)[DK], T &qs) {
@@ -1084,6 +1111,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                             } else {
                                 const T o = s_off[buf][min(dim, D - 1)][cb + r16];
                                 av[kc] = M::fma(o, static_cast<T>(dim < D), static_cast<T>(dim == D));
+                                if constexpr (MAT) av[kc] = M::fma(s_e[buf][cb + r16], static_cast<T>(dim == D + 1), av[kc]);
                             }
                         }
                         qs = s_q[buf][cb + r16];
@@ -1104,7 +1132,16 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                         for (int v = 0; v < 4; ++v)
 #pragma unroll
                             for (int rg = 0; rg < RG; ++rg) {
-                                const T e = exp2_tab<TN>(G[rg][v], s_exp2);
+                                // the pair's kernel value: 2^G (folded Gaussian, G scaled by
+                                // TN), or the Matern 2^-u (1 + u ln2), u = sqrt(G)
+                                T e;
+                                if constexpr (MAT) {
+                                    const T u = __builtin_sqrt(__builtin_fabs(G[rg][v]));
+                                    e = exp2_tab<TN>(__builtin_fmax(-u * TN, -2000.0 * TN), s_exp2) *
+                                        M::fma(u, static_cast<T>(LN2), T(1));
+                                } else {
+                                    e = exp2_tab<TN>(G[rg][v], s_exp2);
+                                }
                                 acc[rg][v] = M::fma(e, qs, acc[rg][v]);
                                 if constexpr (SYM) zl[rg] = M::fma(e, qt[rg][v], zl[rg]);
                             }
@@ -1155,7 +1192,14 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
                                     const T dd = t[k] - s_off[buf][k][cj];
                                     ss = M::fma(dd, dd, ss);
                                 }
-                                const T e = exp2_tab<TN>(__builtin_fmax(-ss * TN, -2000.0 * TN), s_exp2);
+                                T e;
+                                if constexpr (MAT) {
+                                    const T sd = __builtin_sqrt(ss);
+                                    const T e0 = exp2_tab<TN>(__builtin_fmax(-L2E * sd * TN, -2000.0 * TN), s_exp2);
+                                    e = M::fma(sd, e0, e0);
+                                } else {
+                                    e = exp2_tab<TN>(__builtin_fmax(-ss * TN, -2000.0 * TN), s_exp2);
+                                }
                                 sacc = M::fma(e, s_q[buf][cj], sacc);
                                 if constexpr (SYM) zs[s4] = M::fma(e, qi, zs[s4]);
                             }
@@ -1177,7 +1221,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_kmvp_ms(KArgs a) {
             // own earlier store; read before the compute to hide the latency)
             const int64_t jz = static_cast<int64_t>(J) * TILE + tid;
             const T zold = (sym && !zlds) ? zslot[jz] : T(0);
-            const T wj = (sym && r2 <= WIDE_R2_FP64) ? wsrc[jz] : T(1);
+            const T wj = (sym && r2 <= WIDE_R2_FP64 && !MAT) ? wsrc[jz] : T(1);  // Matern: no folding
             if (sym)
                 tile(std::true_type{});
             else
@@ -2814,18 +2858,20 @@ static bool use_sym_kernel(const Prepared &P, int prec) {
     if (prec == KRR_FP64 ? P.dpad > 16
                          : (P.dpad > 16 || (P.dpad == 16 && kmvp_sym_group_tiles(P) < 8) || use_fp32_matrix_kernel()))
         return false;
-    // Matern-3/2: the split-f16 form only (FP32 / BF16), under the same rule
-    // (N = 1e5: 1.26-1.41x at d = 3-12; d = 16, N = 2e5: 1.24x)
-    if (P.kernel == KRR_KERNEL_MATERN32 && prec == KRR_FP64) return false;
+    // Matern-3/2 under the same rules (FP32 / BF16, N = 1e5: 1.26-1.41x at
+    // d = 3-12; d = 16, N = 2e5: 1.24x; FP64: see k_kmvp_ms)
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
 
 template <int D>
-static hipError_t launch_kmvp_sym(const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp_sym(const KArgs &a, bool mat, hipStream_t s) {
     if constexpr (ms_supported<D>()) {
         const int nb = a.ngroups * (a.ngroups + 1) / 2;
-        hipLaunchKernelGGL((k_kmvp_ms<D>), dim3(nb), dim3(BLOCK), 0, s, a);
+        if (mat)
+            hipLaunchKernelGGL((k_kmvp_ms<D, true>), dim3(nb), dim3(BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_kmvp_ms<D, false>), dim3(nb), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -2856,16 +2902,16 @@ static hipError_t launch_kmvp_sym_hd(int dpad, const KArgs &a, bool mat, hipStre
     }
 }
 
-static hipError_t launch_kmvp_sym_d(int dpad, const KArgs &a, hipStream_t s) {
+static hipError_t launch_kmvp_sym_d(int dpad, const KArgs &a, bool mat, hipStream_t s) {
     switch (dpad) {
-        case 1: return launch_kmvp_sym<1>(a, s);
-        case 2: return launch_kmvp_sym<2>(a, s);
-        case 3: return launch_kmvp_sym<3>(a, s);
-        case 4: return launch_kmvp_sym<4>(a, s);
-        case 6: return launch_kmvp_sym<6>(a, s);
-        case 8: return launch_kmvp_sym<8>(a, s);
-        case 12: return launch_kmvp_sym<12>(a, s);
-        case 16: return launch_kmvp_sym<16>(a, s);
+        case 1: return launch_kmvp_sym<1>(a, mat, s);
+        case 2: return launch_kmvp_sym<2>(a, mat, s);
+        case 3: return launch_kmvp_sym<3>(a, mat, s);
+        case 4: return launch_kmvp_sym<4>(a, mat, s);
+        case 6: return launch_kmvp_sym<6>(a, mat, s);
+        case 8: return launch_kmvp_sym<8>(a, mat, s);
+        case 12: return launch_kmvp_sym<12>(a, mat, s);
+        case 16: return launch_kmvp_sym<16>(a, mat, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2949,7 +2995,8 @@ static hipError_t kmvp_run(const Prepared &R, const Prepared &C, int prec, const
             a.off = C.off64;
             a.pm = C.pm64;
             a.row_off = R.off64;
-            e = sym ? launch_kmvp_sym_d(C.dpad, a, s) : launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
+            e = sym ? launch_kmvp_sym_d(C.dpad, a, C.kernel == KRR_KERNEL_MATERN32, s)
+                    : launch_kmvp_d<KRR_FP64>(C.dpad, a, C.kernel, s);
             break;
         case KRR_FP32:
             a.off = C.off32;

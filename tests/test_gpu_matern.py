@@ -139,11 +139,12 @@ def test_matern_matrix_core_kernel_matches_valu_kernel(monkeypatch, prec, d):
     check(b, want, prec, floor=floor)
 
 
-# The symmetric Matern product (square FP32 / BF16 products up to d = 12, and 16
-# from groups of 8 tiles: N = 200,000; one kernel value per unordered pair for
-# both of its terms) against the one-sided kernel (KRR_KMVP_SYM=0) and the
-# oracle: a single point, ragged tiles, one and several tiles per group.
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+# The symmetric Matern product (square FP64 products up to d = 16; FP32 / BF16
+# ones up to d = 12, and 16 from groups of 8 tiles: N = 200,000; one kernel
+# value per unordered pair for both of its terms) against the one-sided kernel
+# (KRR_KMVP_SYM=0) and the oracle: a single point, ragged tiles, one and several
+# tiles per group.
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("n,d", [(1, 3), (300, 1), (2500, 3), (9000, 8), (4000, 12), (30000, 2), (200000, 16)])
 def test_matern_symmetric_product(monkeypatch, prec, n, d):
     x = workloads.random_points(140 + d, n, d, 1.0, kind="normal")
@@ -154,7 +155,7 @@ def test_matern_symmetric_product(monkeypatch, prec, n, d):
     monkeypatch.setenv("KRR_KMVP_SYM", "0")
     y1 = _mvp(x, h, q, 0.03, prec)
     monkeypatch.delenv("KRR_KMVP_SYM")
-    assert _rel(y, y1) <= 1e-5
+    assert _rel(y, y1) <= (1e-12 if prec == "fp64" else 1e-5)
     q32 = call_vector(q, prec)
     rows = np.arange(n) if n <= 9000 else np.random.default_rng(n).choice(n, 64, replace=False)
     ref = lambda v: oracle.matern_mvp_rows(x, h, v, rows, shift=0.03)  # noqa: E731
