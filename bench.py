@@ -143,9 +143,8 @@ def product_peak(d: int, prec: str = "fp32", n: int | None = None) -> tuple[floa
     return SIMD_CYCLES_S * 64 / cyc, rule, kname
 
 
-def matern_peak(d: int, n: int | None = None) -> tuple[float, str, str]:
-    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 12, or 16 for n with
-    groups of 8 tiles (square products):
+def matern_peak(d: int) -> tuple[float, str, str]:
+    """Peak pairs/s of the FP32 Matern-3/2 product.  d <= 16 (square products):
     the symmetric split-f16 kernel, per 2048 pair terms the one-sided step's
     operations with 4 FMA-class ops per pair plus the source-term reduction.
     d <= 48 (one-sided split-f16 kernels),
@@ -153,7 +152,7 @@ def matern_peak(d: int, n: int | None = None) -> tuple[float, str, str]:
     per lane, 16 x (sqrt + exp2 + 2 FMAs), serial issue (v_sqrt_f32 costs 8
     cycles, as v_exp_f32).  Otherwise (VALU kernel) per 64 pairs: 2d + 3
     FMA-class operations, sqrt and exp2 per lane."""
-    sym = d <= 12 or (d <= 16 and n is not None and sym_group_tiles(n) >= 8)  # square products of n points
+    sym = d <= 16  # square products (the Matern form at every group size)
     if (sym and os.environ.get("KRR_KMVP_VALU", "0") != "1" and os.environ.get("KRR_KMVP_SYM", "1") != "0"
             and os.environ.get("KRR_KMVP_MG32", "0") != "1"):
         # symmetric split-f16 form (square products): per wave-step 1024 kernel
@@ -666,7 +665,7 @@ def workload_matern(args, api, native, workloads, torch) -> dict:
     tc = time.perf_counter() - t0
     log(f"matern cg64: {ic['outer_iters']} iterations, relres {ic['relres_true']:.3e}, {tc:.2f} s")
     d = p.d
-    peak, rule, kname = matern_peak(d, p.n)
+    peak, rule, kname = matern_peak(d)
     ach = rates["fp32"]["gpair_s"]
     return {"metric": METRIC, "value": ach * 1e9, "unit": "pairs/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
             "higher_is_better": True, "vs_baseline": None,

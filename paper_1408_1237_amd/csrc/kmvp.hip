@@ -2855,11 +2855,14 @@ static bool use_sym_kernel(const Prepared &P, int prec) {
     // clustered one); at 16 only with groups of at least 8 tiles (N above
     // about 180,000: 8 % at N = 2e5), where a row unit meets enough column
     // tiles to repay its set-up (N = 1e5, groups of 4: 11 % slower)
+    // Matern-3/2 (FP32 / BF16): at every compiled dimension up to 16, groups of
+    // 4 tiles included (its pair costs more: N = 1e5, 1.26-1.41x at d = 3-12,
+    // 1.14x at d = 16; N = 2e5, d = 16: 1.24x); FP64: see k_kmvp_ms
+    const bool mat = P.kernel == KRR_KERNEL_MATERN32;
     if (prec == KRR_FP64 ? P.dpad > 16
-                         : (P.dpad > 16 || (P.dpad == 16 && kmvp_sym_group_tiles(P) < 8) || use_fp32_matrix_kernel()))
+                         : (P.dpad > 16 || (P.dpad == 16 && kmvp_sym_group_tiles(P) < 8 && !mat) ||
+                            use_fp32_matrix_kernel()))
         return false;
-    // Matern-3/2 under the same rules (FP32 / BF16, N = 1e5: 1.26-1.41x at
-    // d = 3-12; d = 16, N = 2e5: 1.24x; FP64: see k_kmvp_ms)
     const char *v = std::getenv("KRR_KMVP_SYM");
     return !(v && v[0] == '0');
 }
