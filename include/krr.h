@@ -204,9 +204,9 @@ int kmvp_gauss(const krr_points *pts /* host */, double sigma, double shift, int
  * shares that device's array, which keeps the last call's contents: calls that
  * overlap on one device (other streams, other threads) race and must be
  * serialised by the caller.  Errors as kmvp_gauss, and KRR_EUNSUPPORTED when the
- * product's scratch (krr_workspace_size(KRR_WS_KMVP, ...): about 460 bytes per
- * point plus 17 MiB at d = 3, so up to about 100,000 points there) exceeds the
- * array. */
+ * product's scratch (krr_workspace_size(KRR_WS_KMVP, ...): about 1 KB per point,
+ * mostly partial-sum slots, plus 17 MiB at d = 3, so up to about 120,000 points
+ * there) exceeds the array. */
 size_t krr_noalloc_scratch_bytes(void);
 int kmvp_gauss_noalloc(const krr_points *pts /* host */, double sigma, double shift, int32_t prec,
                        const void *q, void *y, krr_stream_t stream);
